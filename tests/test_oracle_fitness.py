@@ -1,0 +1,196 @@
+"""Pins of the oracle's fitness (uplink sum SE, Eq. 5-7) on the CPU.
+
+Each check is fixed by something other than the oracle's own formula:
+hand-worked instances (tests/golden/fitness_hand.json), invariances of
+Eq. 7 under relabelling, the closed form of a single uncontaminated cell, the
+M -> infinity limit stated in Sec. 3.2, a Monte-Carlo simulation of the
+channel model of Eq. 1 for the finite-M bound, and the K!^(L-1) count of
+Sec. 3.3 for exhaustive search."""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from conftest import GOLDEN
+from paper_2511_20511_amd import scenario
+
+
+def _hand():
+    with open(os.path.join(GOLDEN, "fitness_hand.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["L2_K1", "L2_K3_three_cycle", "L2_K3_identity"])
+def test_hand_worked(oracle_mod, name):
+    case = {c["name"]: c for c in _hand()["cases"]}[name]
+    beta = np.array(case["beta"], dtype=np.float64)
+    chrom = np.array(case["chrom"], dtype=np.uint8)
+    want_terms = [math.log2(1.0 + s) for s in case["sir"]]
+    se = oracle_mod.se_terms(beta, chrom).reshape(-1)
+    np.testing.assert_allclose(se, want_terms, rtol=1e-12, atol=1e-12)
+    fit = oracle_mod.fitness(beta, chrom[None])[0]
+    assert fit == pytest.approx(sum(want_terms), rel=1e-12)
+    if "sum_se_bits" in case:
+        assert fit == pytest.approx(case["sum_se_bits"], rel=1e-12)
+
+
+def test_prelog(oracle_mod):
+    case = {c["name"]: c for c in _hand()["cases"]}["L2_K3_three_cycle"]
+    beta = np.array(case["beta"])
+    chrom = np.array(case["chrom"], dtype=np.uint8)[None]
+    # training takes tau = K = 3 of T = 196 symbols (Sec. 3)
+    assert oracle_mod.fitness(beta, chrom, T=196)[0] == pytest.approx(21.0 * (1 - 3 / 196), rel=1e-12)
+
+
+def _rand_pop(rng, n, L, K):
+    return np.stack([np.stack([rng.permutation(K) for _ in range(L)]) for _ in range(n)]).astype(np.uint8)
+
+
+@pytest.mark.parametrize("L,K", [(3, 3), (7, 4), (5, 6)])
+def test_invariances(oracle_mod, L, K):
+    rng = np.random.default_rng(L * 100 + K)
+    drop = scenario.make_drop(L, K, seed=7, instance_id=L)
+    beta = drop.beta
+    pop = _rand_pop(rng, 6, L, K)
+    f0 = oracle_mod.fitness(beta, pop)
+    # same pilot relabelling in every cell
+    sigma = rng.permutation(K).astype(np.uint8)
+    np.testing.assert_allclose(oracle_mod.fitness(beta, sigma[pop]), f0, rtol=1e-12)
+    # cell relabelling: permute BS and cell axes of beta together with the rows
+    pi = rng.permutation(L)
+    beta_c = beta[np.ix_(pi, pi, np.arange(K))]
+    np.testing.assert_allclose(oracle_mod.fitness(beta_c, pop[:, pi, :]), f0, rtol=1e-12)
+    # user relabelling inside each cell
+    sig = [rng.permutation(K) for _ in range(L)]
+    beta_u = np.stack([np.stack([beta[l, j, sig[j]] for j in range(L)]) for l in range(L)])
+    pop_u = np.stack([np.stack([pop[n, j, sig[j]] for j in range(L)]) for n in range(pop.shape[0])])
+    np.testing.assert_allclose(oracle_mod.fitness(beta_u, pop_u), f0, rtol=1e-12)
+    # scaling what one BS hears scales signal and interference alike
+    scale = np.exp(rng.normal(0, 5, L))
+    np.testing.assert_allclose(oracle_mod.fitness(beta * scale[:, None, None], pop), f0, rtol=1e-11)
+
+
+def test_interference_is_what_changes(oracle_mod):
+    """Moving a strong interferer onto another pilot raises the victim's SE."""
+    L, K = 2, 2
+    beta = np.ones((L, L, K))
+    beta[0, 1, 0] = 10.0  # user 0 of cell 1 is loud at BS 0
+    same = np.array([[[0, 1], [0, 1]]], dtype=np.uint8)
+    se_same = oracle_mod.se_terms(beta, same[0])
+    # with identical pilots user (0,0) is hit by the loud user: SIR 1/100
+    assert se_same[0, 0] == pytest.approx(math.log2(1 + 1 / 100), rel=1e-12)
+    swapped = np.array([[[0, 1], [1, 0]]], dtype=np.uint8)
+    se_sw = oracle_mod.se_terms(beta, swapped[0])
+    assert se_sw[0, 0] == pytest.approx(1.0, rel=1e-12)      # now SIR 1
+    assert se_sw[0, 1] == pytest.approx(math.log2(1 + 1 / 100), rel=1e-12)
+
+
+def test_finite_m_single_cell_closed_form(oracle_mod):
+    h = _hand()["finite_m_single_cell"]
+    beta = np.array(h["beta"])
+    chrom = np.array(h["chrom"], dtype=np.uint8)
+    se = oracle_mod.se_terms(beta, chrom, se_mode=oracle_mod.SE_FINITE_M, M=h["M"], rho=h["rho"])
+    np.testing.assert_allclose(se.reshape(-1), [math.log2(1 + s) for s in h["sinr"]], rtol=1e-12)
+
+
+def test_finite_m_isolated_cells(oracle_mod):
+    """Cells that do not hear each other: sum of single-cell values, whatever the pilots."""
+    L, K = 3, 3
+    rng = np.random.default_rng(3)
+    beta = np.zeros((L, L, K))
+    for l in range(L):
+        beta[l, l] = rng.uniform(0.1, 1.0, K)
+    M, rho = 16, 2.0
+    single = 0.0
+    for l in range(L):
+        b = beta[l:l + 1, l:l + 1, :]
+        single += oracle_mod.fitness(b, np.arange(K, dtype=np.uint8)[None, None, :],
+                                     se_mode=oracle_mod.SE_FINITE_M, M=M, rho=rho)[0]
+    pop = _rand_pop(rng, 5, L, K)
+    f = oracle_mod.fitness(beta, pop, se_mode=oracle_mod.SE_FINITE_M, M=M, rho=rho)
+    np.testing.assert_allclose(f, single, rtol=1e-12)
+
+
+def test_finite_m_tends_to_eq5(oracle_mod):
+    """As M grows the finite-M SINR tends to Eq. 5 (Sec. 3.2, Eq. 4)."""
+    L, K = 7, 4
+    drop = scenario.make_drop(L, K, seed=3, instance_id=1)
+    pop = _rand_pop(np.random.default_rng(1), 4, L, K)
+    rho = scenario.snr_to_rho(10.0)
+    fa = oracle_mod.fitness(drop.beta, pop)
+    fm = oracle_mod.fitness(drop.beta, pop, se_mode=oracle_mod.SE_FINITE_M, M=1e15, rho=rho)
+    np.testing.assert_allclose(fm, fa, rtol=1e-6)
+    f_small = oracle_mod.fitness(drop.beta, pop, se_mode=oracle_mod.SE_FINITE_M, M=64, rho=rho)
+    assert np.all(f_small < fa)
+
+
+def test_finite_m_matches_channel_simulation(oracle_mod):
+    """Monte-Carlo of Eq. 1 (h = g sqrt(beta), g ~ CN(0, I_M)) with MMSE estimates from
+    orthogonal pilots and maximum-ratio combining; the use-and-then-forget SINR
+    estimated from samples agrees with the closed form the oracle uses."""
+    rng = np.random.default_rng(12345)
+    L, K, M, rho = 2, 2, 4, 3.0
+    tau = K
+    beta = rng.uniform(0.2, 1.0, (L, L, K))
+    chrom = np.array([[0, 1], [1, 0]], dtype=np.uint8)
+    inv = np.argsort(chrom, axis=1)      # inv[j][s] = user of cell j on pilot s
+    S = 200_000
+    l, k = 0, 0                          # the victim: user 0 of cell 0 at BS 0
+    s = chrom[l, k]
+    # channels at BS l of every user, [S][L][K][M]
+    g = (rng.standard_normal((S, L, K, M)) + 1j * rng.standard_normal((S, L, K, M))) / np.sqrt(2)
+    h = g * np.sqrt(beta[l])[None, :, :, None]
+    noise = (rng.standard_normal((S, M)) + 1j * rng.standard_normal((S, M))) / np.sqrt(2)
+    yp = np.sqrt(tau * rho) * sum(h[:, j, inv[j, s]] for j in range(L)) + noise
+    Ssum = sum(beta[l, j, inv[j, s]] for j in range(L))
+    v = (np.sqrt(tau * rho) * beta[l, l, k] / (1 + tau * rho * Ssum)) * yp
+    hk = h[:, l, k]
+    sig = np.mean(np.sum(np.conj(v) * hk, axis=1))
+    interf = 0.0
+    for j in range(L):
+        for kk in range(K):
+            interf += np.mean(np.abs(np.sum(np.conj(v) * h[:, j, kk], axis=1)) ** 2)
+    vnorm = np.mean(np.sum(np.abs(v) ** 2, axis=1))
+    sinr_mc = rho * abs(sig) ** 2 / (rho * interf - rho * abs(sig) ** 2 + vnorm)
+    se = oracle_mod.se_terms(beta, chrom, se_mode=oracle_mod.SE_FINITE_M, M=M, rho=rho)
+    sinr_cf = 2.0 ** se[l, k] - 1.0
+    assert sinr_mc == pytest.approx(sinr_cf, rel=0.03)
+
+
+@pytest.mark.parametrize("L,K,classes", [(3, 3, 36), (4, 4, 13824), (2, 5, 120)])
+def test_bruteforce_count_and_optimum(oracle_mod, L, K, classes):
+    """Exhaustive search visits K!^(L-1) classes (Sec. 3.3); its optimum equals the
+    best over every full assignment, which differ only by a global pilot relabelling."""
+    assert classes == math.factorial(K) ** (L - 1)
+    drop = scenario.make_drop(L, K, seed=11, instance_id=K)
+    best, bf, cnt = oracle_mod.bruteforce(drop.beta)
+    assert cnt == classes
+    assert oracle_mod.fitness(drop.beta, best[None])[0] == bf
+    if L * K <= 9:
+        perms = list(itertools.permutations(range(K)))
+        allpop = np.array([list(rows) for rows in itertools.product(perms, repeat=L)], dtype=np.uint8)
+        f = oracle_mod.fitness(drop.beta, allpop)
+        assert f.max() == pytest.approx(bf, rel=1e-12)
+        # each class value appears K! times (up to rounding order)
+        vals = np.sort(np.round(f, 9))
+        _, counts = np.unique(vals, return_counts=True)
+        assert np.all(counts % math.factorial(K) == 0)
+
+
+def test_se_terms_sum_to_fitness(oracle_mod):
+    L, K = 7, 4
+    drop = scenario.make_drop(L, K, seed=2, instance_id=0)
+    chrom = _rand_pop(np.random.default_rng(0), 1, L, K)
+    se = oracle_mod.se_terms(drop.beta, chrom[0])
+    f = oracle_mod.fitness(drop.beta, chrom, T=196)[0]
+    assert f == pytest.approx(se.sum() * (1 - K / 196), rel=1e-13)
+
+
+def test_rejects_non_permutation(oracle_mod):
+    beta = np.ones((2, 2, 3))
+    bad = np.array([[[0, 0, 1], [0, 1, 2]]], dtype=np.uint8)
+    with pytest.raises(ValueError):
+        oracle_mod.fitness(beta, bad)
