@@ -1,0 +1,230 @@
+/*
+ * pa.h -- C ABI of the MI355X (gfx950) pilot-assignment library.
+ *
+ * The library runs the K-means-seeded elitist two-dimensional genetic
+ * algorithm of Alqudah & Khokhar, "Efficient Parallel Implementation of the
+ * Pilot Assignment Problem in Massive MIMO Systems":
+ *   - a chromosome is an L x K matrix of pilot indices, row j being the
+ *     pilots of the K users of cell j, a permutation of the tau = K pilots
+ *     (Sec. 4.1, chromosome encoding; Sec. 3.3, pilots unique inside a cell
+ *     and reused across cells);
+ *   - its fitness is the uplink sum spectral efficiency (Sec. 3.2, Eq. 5-6),
+ *     the objective of Eq. 7, optionally scaled by the share 1 - tau/T of the
+ *     coherence interval left after uplink training (Sec. 3);
+ *   - the population is seeded by K-means clustering of the users
+ *     (Sec. 1 contribution 2, Sec. 4.1, Alg. 1) and evolved with elitism
+ *     (Sec. 1 contribution 1), selection, crossover and mutation (Alg. 1).
+ *
+ * Conventions
+ *   - Status: every call returns pa_status; 0 is success, negative is an
+ *     error.  pa_last_error() returns a thread-local message for the last
+ *     error raised on the calling thread.  No C++ exception crosses the ABI.
+ *   - Memory: "HOST" pointers are ordinary host memory, "DEVICE" pointers are
+ *     device memory of the context's GPU (e.g. a torch tensor's data_ptr()).
+ *     The caller owns every buffer it passes; objects created by the library
+ *     own only their internal copies and are released by their destroy call.
+ *   - Streams: `stream` is a hipStream_t of the context's device (NULL = the
+ *     null stream).  Calls marked "async" only enqueue work; their outputs are
+ *     valid once the stream has been synchronised.  Calls marked "blocking"
+ *     return after their host outputs are written.
+ *   - Layouts are dense, row-major, with the index names of the paper:
+ *       beta[(l*L + j)*K + k]  large-scale fading of user k of cell j at the
+ *                              BS of cell l (Sec. 3.1, Eq. 1-2), FP64;
+ *       pop[(n*L + j)*K + k]   pilot (0..K-1) of user k of cell j in
+ *                              chromosome n, uint8;
+ *       fit[n]                 FP32 sum SE of chromosome n (pre-log applied).
+ *   - Random numbers: every random decision is a pure function of
+ *     (seed, instance_id, generation, slot), drawn from Philox4x32-10, so
+ *     results do not depend on launch shapes, batching or timing.
+ *   - Thread safety: a context and its instances must not be used from two
+ *     threads at once.  The server's submit and poll calls are thread-safe.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pa_status;
+enum {
+  PA_OK = 0,
+  PA_EINVAL = -1,      /* an argument is out of its documented range */
+  PA_ENOMEM = -2,      /* device or host allocation failed */
+  PA_EDEVICE = -3,     /* a HIP runtime call or kernel launch failed */
+  PA_EAGAIN = -4,      /* not finished yet (server poll) or queue full */
+  PA_ECANCELED = -5,   /* request cancelled */
+  PA_EINTERNAL = -6,   /* library bug: please report */
+  PA_EUNSUPPORTED = -7 /* valid request this build cannot serve */
+};
+
+/* Fitness modes.
+ * PA_SE_ASYMPTOTIC: Eq. 5, the M -> infinity uplink SE
+ *   SE_ik = log2(1 + beta_iik^2 / sum_{j != i} beta_ijk'^2), where k' is the
+ *   user of cell j that reuses user (i,k)'s pilot.  M and rho are ignored.
+ * PA_SE_FINITE_M: the finite-antenna uplink bound whose limit is Eq. 5 (the
+ *   paper's Eq. 3 is garbled): maximum-ratio combining, MMSE estimates from
+ *   tau-symbol orthogonal pilots, pilot and data SNR rho:
+ *   SINR = M tau rho^2 b^2 / ((1 + rho B_i)(1 + tau rho S) + M tau rho^2 I),
+ *   b = beta_iik, S = sum_j beta_ijk' (own user included),
+ *   I = sum_{j != i} beta_ijk'^2, B_i = sum over all users of beta_i..   */
+enum { PA_SE_ASYMPTOTIC = 0, PA_SE_FINITE_M = 1 };
+
+typedef struct pa_context pa_context;
+typedef struct pa_instance pa_instance;
+typedef struct pa_server pa_server;
+
+/* One pilot-assignment problem (the inputs of Alg. 1/Alg. 2: cells L,
+ * pilots K, the fading table beta; plus the coherence length T).
+ *   L        cells, 1..64 (2..64 in asymptotic mode: one cell has no
+ *            interference and an unbounded SINR)
+ *   K        users per cell, 1..64
+ *   tau      pilots; must equal K (pilots are a permutation inside a cell)
+ *   T        coherence length in symbols; 0 = no pre-log, else T > tau
+ *   M        BS antennas (finite-M mode), >= 1
+ *   rho      transmit SNR (finite-M mode), > 0
+ *   se_mode  PA_SE_ASYMPTOTIC or PA_SE_FINITE_M
+ *   beta     HOST [L][L][K] FP64, finite; > 0 in asymptotic mode, >= 0 in
+ *            finite-M mode; per BS l the ratio max/min over the nonzero
+ *            entries must not exceed 2^60 (FP32 range after normalisation)
+ *   user_xy  HOST [L][K][2] metres, or NULL (then only kmeans_frac == 0)
+ *   bs_xy    HOST [L][2] metres, or NULL (same)
+ *            user offsets from their own BS must be below 8388 m.        */
+typedef struct pa_problem {
+  int32_t L, K, tau, T, M;
+  double rho;
+  int32_t se_mode;
+  const double *beta;
+  const double *user_xy;
+  const double *bs_xy;
+} pa_problem;
+
+/* GA parameters.
+ *   pop          population size N, 2..65536
+ *   gens         generations G >= 0 (a fixed number reads "termination")
+ *   elite        E in [0, N]: slots 0..E-1 receive the E best, in order
+ *   p_cross      probability of single-point crossover on the cell axis
+ *   p_mut        per-gene probability of a swap mutation
+ *   kmeans_frac  share of the initial population derived from the K-means
+ *                seed (0 = random initialisation, the conventional GA)
+ *   p_init       per-gene swap probability used to perturb the seed
+ *   seed         64-bit Philox key
+ *   instance_id  distinguishes instances sharing a seed (Philox counter)   */
+typedef struct pa_ga_params {
+  int32_t pop, gens, elite;
+  double p_cross, p_mut, kmeans_frac, p_init;
+  uint64_t seed;
+  uint32_t instance_id;
+} pa_ga_params;
+
+/* Result of a solve.
+ *   best        HOST, caller-allocated, L*K bytes: best chromosome of the
+ *               last population
+ *   best_fit    its FP32 fitness
+ *   best_index  its slot in the last population
+ *   trace       HOST [gens+1] or NULL: best fitness of each generation
+ *   device_ms   device time of the solve (events on the solve's stream)  */
+typedef struct pa_result {
+  uint8_t *best;
+  float best_fit;
+  int32_t best_index;
+  float *trace;
+  double device_ms;
+} pa_result;
+
+/* ---- validation (host only, no device needed) ------------------------ */
+
+/* Checks a problem against the ranges documented at pa_problem.  Returns
+ * PA_OK or PA_EINVAL (message in pa_last_error()). */
+pa_status pa_problem_check(const pa_problem *prob);
+/* Checks GA parameters against the ranges documented at pa_ga_params, for
+ * the given (valid) problem (kmeans_frac > 0 needs positions). */
+pa_status pa_params_check(const pa_problem *prob, const pa_ga_params *params);
+
+/* ---- context and instances ------------------------------------------- */
+
+/* Creates a context on HIP device `device`.  Blocking. */
+pa_status pa_context_create(int32_t device, pa_context **out);
+void pa_context_destroy(pa_context *ctx);
+
+/* Validates a problem (see pa_problem), copies beta and the positions to the
+ * device and builds the device-side tables: per BS l, beta is scaled by a
+ * power of two 2^-e_l so its largest entry lies in [0.5, 1) (this leaves
+ * Eq. 5 unchanged and keeps squares inside FP32 range) and the squares are
+ * rounded to FP32.  Blocking.  PA_EINVAL on invalid input. */
+pa_status pa_instance_create(pa_context *ctx, const pa_problem *prob, pa_instance **out);
+void pa_instance_destroy(pa_instance *inst);
+
+/* ---- the per-generation hot path ------------------------------------- */
+
+/* K-means seeding and the initial population (Sec. 4.1; the population
+ * initialisation of Alg. 1): clusters the users' offsets from their own BS
+ * (integer millimetres) into K groups (farthest-point start, integer Lloyd
+ * iterations, at most 100), matches each cell's users to the clusters
+ * greedily (cluster index = pilot) to form the seed chromosome, then fills
+ * d_pop [N][L][K] (DEVICE): slot 0 the seed, slots 1..n_km-1 the seed
+ * swap-mutated at rate p_init, the rest uniformly random permutations, with
+ * n_km = max(1, floor(kmeans_frac*N + 1/2)) (0 when kmeans_frac == 0).
+ * Async. */
+pa_status pa_kmeans_init(pa_instance *inst, const pa_ga_params *params, uint8_t *d_pop,
+                         void *stream);
+
+/* Fitness (Eq. 5-7) of n chromosomes: d_pop [n][L][K] (DEVICE) ->
+ * d_fit [n] (DEVICE, FP32).  Rows must be permutations (not checked).
+ * The FP32 result is within 1e-5 relative of the FP64 definition and is
+ * bit-identical for a chromosome whatever n, the batch or the launch shape.
+ * Async.  n == 0 is a no-op. */
+pa_status pa_fitness(pa_instance *inst, const uint8_t *d_pop, int32_t n, float *d_fit,
+                     void *stream);
+
+/* One generation (Alg. 1 loop body): from d_pop_in [N][L][K] and its
+ * fitness d_fit_in [N] (both DEVICE) writes d_pop_out [N][L][K] (DEVICE):
+ * slots 0..E-1 = the E best (fitness descending, lower slot first on ties,
+ * NaN last), then children in pairs (a, a+1): two binary tournaments choose
+ * the parents, single-point crossover on the cell axis with p_cross, swap
+ * mutation per gene with p_mut.  d_pop_in and d_pop_out must not overlap.
+ * Async. */
+pa_status pa_ga_step(pa_instance *inst, const pa_ga_params *params, int32_t gen,
+                     const uint8_t *d_pop_in, const float *d_fit_in, uint8_t *d_pop_out,
+                     void *stream);
+
+/* A whole solve: seeding, then `gens` generations of select / evolve /
+ * evaluate with the population resident on the device, then the best
+ * chromosome of the last population (Alg. 1 "return best assignment").
+ * Blocking. */
+pa_status pa_solve(pa_instance *inst, const pa_ga_params *params, pa_result *out, void *stream);
+
+/* The same solve as one launch per step (seeding, fitness, then per
+ * generation a pa_ga_step launch and a pa_fitness launch), no fusion and no
+ * graph: the plain comparator.  Bit-identical results to pa_solve. */
+pa_status pa_solve_plain(pa_instance *inst, const pa_ga_params *params, pa_result *out,
+                         void *stream);
+
+/* pa_fitness with an explicit launch shape, for tuning and tests:
+ *   block     threads per workgroup (64..1024, multiple of 64, >= K; 0 = default)
+ *   grid_cap  maximum workgroups (0 = enough to fill the GPU)
+ *   generic   1 forces the runtime-L kernel instead of the unrolled one
+ * Results are bit-identical to pa_fitness for every shape.  Async. */
+pa_status pa_fitness_shaped(pa_instance *inst, const uint8_t *d_pop, int32_t n, float *d_fit,
+                            int32_t block, int32_t grid_cap, int32_t generic, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------ */
+
+/* After pa_kmeans_init with kmeans_frac > 0: copies the K-means state to
+ * HOST buffers (any may be NULL): seed [L][K], centroids [K][2] (int32 mm),
+ * labels [L*K], iterations.  Blocking. */
+pa_status pa_instance_kmeans_state(pa_instance *inst, uint8_t *seed, int32_t *centroids,
+                                   int32_t *labels, int32_t *iters);
+
+const char *pa_status_string(pa_status s);
+const char *pa_last_error(void);
+/* Library version string. */
+const char *pa_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PA_H */

@@ -197,7 +197,7 @@ int pao_rank(const double *fit, int32_t n, int32_t *order) {
 /* cluster indices (= pilots) greedily by increasing distance.               */
 /* ------------------------------------------------------------------------ */
 #define KM_MAX_ITERS 100
-#define KM_COORD_LIMIT (1ll << 24)
+#define KM_COORD_LIMIT (1ll << 23)
 
 /* floor((2s + n) / (2n)): the mean s/n rounded half up, with floor division */
 static int64_t rdiv(int64_t s, int64_t n) {

@@ -1,0 +1,302 @@
+"""MI355X (gfx950) pilot assignment: K-means-seeded elitist 2D genetic algorithm.
+
+Thin ctypes binding over ``libpa_amd.so`` (C ABI declared in ``include/pa.h``).
+The functions keep the C names; they only marshal arguments (torch tensors
+for device buffers, numpy arrays for host buffers) and raise ``PaError`` on a
+nonzero status.  Every step of the method runs in the library's HIP kernels;
+there is no CPU fallback: without the built library every call raises.
+
+torch is imported before the library is loaded so both use the same HIP
+runtime (``libamdhip64.so.7``) and torch's device pointers and streams are
+valid inside the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "PaError", "GaParams", "Result", "lib", "library_path",
+    "pa_context_create", "pa_context_destroy", "pa_instance_create", "pa_instance_destroy",
+    "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
+    "pa_solve_plain", "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
+    "pa_status_string", "pa_last_error", "pa_version",
+    "SE_ASYMPTOTIC", "SE_FINITE_M",
+]
+
+SE_ASYMPTOTIC = 0
+SE_FINITE_M = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libpa_amd.so")
+
+
+class PaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("K", ctypes.c_int32), ("tau", ctypes.c_int32),
+                ("T", ctypes.c_int32), ("M", ctypes.c_int32), ("rho", ctypes.c_double),
+                ("se_mode", ctypes.c_int32), ("beta", ctypes.c_void_p),
+                ("user_xy", ctypes.c_void_p), ("bs_xy", ctypes.c_void_p)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("pop", ctypes.c_int32), ("gens", ctypes.c_int32), ("elite", ctypes.c_int32),
+                ("p_cross", ctypes.c_double), ("p_mut", ctypes.c_double),
+                ("kmeans_frac", ctypes.c_double), ("p_init", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("instance_id", ctypes.c_uint32)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("best", ctypes.c_void_p), ("best_fit", ctypes.c_float),
+                ("best_index", ctypes.c_int32), ("trace", ctypes.c_void_p),
+                ("device_ms", ctypes.c_double)]
+
+
+@dataclass
+class GaParams:
+    pop: int = 50
+    gens: int = 100
+    elite: int = 2
+    p_cross: float = 0.8
+    p_mut: float = 0.05
+    kmeans_frac: float = 0.5
+    p_init: float = 0.1
+    seed: int = 1
+    instance_id: int = 0
+
+    def to_c(self) -> _Params:
+        return _Params(self.pop, self.gens, self.elite, self.p_cross, self.p_mut,
+                       self.kmeans_frac, self.p_init, self.seed & ((1 << 64) - 1),
+                       self.instance_id & 0xFFFFFFFF)
+
+
+@dataclass
+class Result:
+    best: np.ndarray
+    best_fit: float
+    best_index: int
+    trace: np.ndarray
+    device_ms: float
+
+
+_lib = None
+
+
+def lib():
+    """Loads libpa_amd.so (after torch, so the HIP runtime is shared)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads torch's libamdhip64 first)
+    if not os.path.exists(library_path):
+        raise RuntimeError(f"{library_path} is not built: run `python -m paper_2511_20511_amd.build`")
+    L = ctypes.CDLL(library_path)
+    vp, i32, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32
+    sig = {
+        "pa_context_create": (st, [i32, ctypes.POINTER(vp)]),
+        "pa_context_destroy": (None, [vp]),
+        "pa_instance_create": (st, [vp, ctypes.POINTER(_Problem), ctypes.POINTER(vp)]),
+        "pa_instance_destroy": (None, [vp]),
+        "pa_kmeans_init": (st, [vp, ctypes.POINTER(_Params), vp, vp]),
+        "pa_fitness": (st, [vp, vp, i32, vp, vp]),
+        "pa_fitness_shaped": (st, [vp, vp, i32, vp, i32, i32, i32, vp]),
+        "pa_ga_step": (st, [vp, ctypes.POINTER(_Params), i32, vp, vp, vp, vp]),
+        "pa_solve": (st, [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Result), vp]),
+        "pa_solve_plain": (st, [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Result), vp]),
+        "pa_instance_kmeans_state": (st, [vp, vp, vp, vp, vp]),
+        "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
+        "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
+        "pa_status_string": (ctypes.c_char_p, [st]),
+        "pa_last_error": (ctypes.c_char_p, []),
+        "pa_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise PaError(status, lib().pa_last_error().decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda) torch tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _Host:
+    """Keeps the host arrays of a pa_problem alive while the C struct points at them."""
+
+    def __init__(self, beta, user_xy, bs_xy, T, M, rho, se_mode):
+        self.beta = np.ascontiguousarray(beta, dtype=np.float64)
+        L, L2, K = self.beta.shape
+        if L != L2:
+            raise ValueError("beta must be [L][L][K]")
+        self.user_xy = None if user_xy is None else np.ascontiguousarray(user_xy, dtype=np.float64)
+        self.bs_xy = None if bs_xy is None else np.ascontiguousarray(bs_xy, dtype=np.float64)
+        self.c = _Problem(L, K, K, int(T), int(M), float(rho), int(se_mode),
+                          self.beta.ctypes.data,
+                          None if self.user_xy is None else self.user_xy.ctypes.data,
+                          None if self.bs_xy is None else self.bs_xy.ctypes.data)
+        self.L, self.K = L, K
+
+
+def pa_version() -> str:
+    return lib().pa_version().decode()
+
+
+def pa_status_string(status: int) -> str:
+    return lib().pa_status_string(status).decode()
+
+
+def pa_last_error() -> str:
+    return lib().pa_last_error().decode()
+
+
+def pa_problem_check(beta, user_xy=None, bs_xy=None, T=0, M=1, rho=1.0, se_mode=SE_ASYMPTOTIC):
+    """Host-only validation of a problem; returns the status (0 = valid)."""
+    h = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode)
+    return int(lib().pa_problem_check(ctypes.byref(h.c)))
+
+
+def pa_params_check(beta, params: GaParams, user_xy=None, bs_xy=None, T=0, M=1, rho=1.0,
+                    se_mode=SE_ASYMPTOTIC):
+    h = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode)
+    p = params.to_c()
+    return int(lib().pa_params_check(ctypes.byref(h.c), ctypes.byref(p)))
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.h = ctypes.c_void_p()
+        _check(lib().pa_context_create(device, ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().pa_context_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Instance:
+    def __init__(self, ctx: Context, beta, user_xy=None, bs_xy=None, T=0, M=1, rho=1.0,
+                 se_mode=SE_ASYMPTOTIC):
+        self.ctx = ctx
+        host = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode)
+        self.L, self.K = host.L, host.K
+        self.h = ctypes.c_void_p()
+        _check(lib().pa_instance_create(ctx.h, ctypes.byref(host.c), ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().pa_instance_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pa_context_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def pa_context_destroy(ctx: Context):
+    ctx.close()
+
+
+def pa_instance_create(ctx: Context, beta, user_xy=None, bs_xy=None, T=0, M=1, rho=1.0,
+                       se_mode=SE_ASYMPTOTIC) -> Instance:
+    return Instance(ctx, beta, user_xy, bs_xy, T, M, rho, se_mode)
+
+
+def pa_instance_destroy(inst: Instance):
+    inst.close()
+
+
+def pa_kmeans_init(inst: Instance, params: GaParams, d_pop, stream=None):
+    import torch
+    p = params.to_c()
+    _check(lib().pa_kmeans_init(inst.h, ctypes.byref(p), _dev(d_pop, torch.uint8), _stream(stream)))
+
+
+def pa_fitness(inst: Instance, d_pop, n: int, d_fit, stream=None):
+    import torch
+    _check(lib().pa_fitness(inst.h, _dev(d_pop, torch.uint8), int(n), _dev(d_fit, torch.float32),
+                            _stream(stream)))
+
+
+def pa_fitness_shaped(inst: Instance, d_pop, n: int, d_fit, block=0, grid_cap=0, generic=0,
+                      stream=None):
+    import torch
+    _check(lib().pa_fitness_shaped(inst.h, _dev(d_pop, torch.uint8), int(n),
+                                   _dev(d_fit, torch.float32), int(block), int(grid_cap),
+                                   int(generic), _stream(stream)))
+
+
+def pa_ga_step(inst: Instance, params: GaParams, gen: int, d_pop_in, d_fit_in, d_pop_out,
+               stream=None):
+    import torch
+    p = params.to_c()
+    _check(lib().pa_ga_step(inst.h, ctypes.byref(p), int(gen), _dev(d_pop_in, torch.uint8),
+                            _dev(d_fit_in, torch.float32), _dev(d_pop_out, torch.uint8),
+                            _stream(stream)))
+
+
+def _solve(fn, inst: Instance, params: GaParams, stream) -> Result:
+    best = np.zeros((inst.L, inst.K), dtype=np.uint8)
+    trace = np.zeros(params.gens + 1, dtype=np.float32)
+    r = _Result(best.ctypes.data, 0.0, 0, trace.ctypes.data, 0.0)
+    p = params.to_c()
+    _check(fn(inst.h, ctypes.byref(p), ctypes.byref(r), _stream(stream)))
+    return Result(best, float(r.best_fit), int(r.best_index), trace, float(r.device_ms))
+
+
+def pa_solve(inst: Instance, params: GaParams, stream=None) -> Result:
+    return _solve(lib().pa_solve, inst, params, stream)
+
+
+def pa_solve_plain(inst: Instance, params: GaParams, stream=None) -> Result:
+    return _solve(lib().pa_solve_plain, inst, params, stream)
+
+
+def pa_instance_kmeans_state(inst: Instance):
+    seed = np.zeros((inst.L, inst.K), dtype=np.uint8)
+    cent = np.zeros((inst.K, 2), dtype=np.int32)
+    labels = np.zeros(inst.L * inst.K, dtype=np.int32)
+    iters = np.zeros(1, dtype=np.int32)
+    _check(lib().pa_instance_kmeans_state(inst.h, seed.ctypes.data, cent.ctypes.data,
+                                          labels.ctypes.data, iters.ctypes.data))
+    return seed, cent, labels, int(iters[0])

@@ -1,0 +1,332 @@
+// k_fitness.hip -- population fitness (uplink sum SE, Sec. 3.2 Eq. 5-6).
+//
+// A workgroup stages the FP32 table of the problem in LDS (in tiles of BS
+// rows when it does not fit) and walks over "rounds" of CPR = block/K
+// chromosomes: it inverts their rows into LDS, each lane (c, p) loads its L
+// row offsets into registers, accumulates the per-pilot SE over all BS rows,
+// and one lane per chromosome reduces over pilots.  See fitness_core.h for
+// the canonical arithmetic order.
+//
+// Variants: for L in {7, 19, 37} (the 1-, 2- and 3-ring hexagonal layouts)
+// the BS and cell loops are fully unrolled so every gather is a single
+// ds_read_b32 with an immediate offset and the own-cell term is peeled at
+// compile time; other L use a runtime loop bounded by LMAX.
+#include "fitness_core.h"
+#include "pa_internal.h"
+
+namespace pa {
+
+struct FitArgs {
+  const float *T2;
+  const float *T1;
+  const float *lconst;
+  const uint8_t *pop;
+  float *fit;
+  int n, L, K, TP;
+  float prelog;
+  int tile_rows;  // generic variant: BS rows per LDS tile
+  int inv_off;    // LDS byte offset of the inverse rows
+  int e_off;      // LDS byte offset of the per-(c, p) sums
+};
+
+constexpr int kLdsBytes = 163840;  // LDS per workgroup on gfx950
+
+// LDS plan of the exact variants: INV <= block*L bytes, E <= block*4 bytes.
+template <int LT, int TPT, int MODE, int BLOCK>
+struct ExactPlan {
+  static constexpr int kRowBytes = LT * TPT * 4 * (MODE == 1 ? 2 : 1);
+  static constexpr int kInvBytes = ((BLOCK * LT) + 15) / 16 * 16;
+  static constexpr int kEBytes = BLOCK * 4;
+  static constexpr int kBudget = kLdsBytes - kInvBytes - kEBytes - 256;
+  static constexpr int kMaxRows = kBudget / kRowBytes;
+  static constexpr int kTiles = (LT + kMaxRows - 1) / kMaxRows;
+  static constexpr int kTileRows = (LT + kTiles - 1) / kTiles;
+  static constexpr int kTableBytes = kTileRows * kRowBytes;
+  static constexpr int kInvOff = kTableBytes;
+  static constexpr int kEOff = kInvOff + kInvBytes;
+  static constexpr int kTotal = kEOff + kEBytes;
+  static_assert(kMaxRows >= 1, "one BS row must fit in LDS");
+  static_assert(kTotal <= kLdsBytes, "LDS plan too large");
+};
+
+template <int LT, int TPT, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
+  using P = ExactPlan<LT, TPT, MODE, BLOCK>;
+  constexpr int NT = P::kTiles;
+  constexpr int TR = P::kTileRows;
+  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);  // bytes per (cell, BS row)
+  constexpr int CELLB = TR * ROWB;                      // bytes per cell in the tile
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  float *sT = reinterpret_cast<float *>(smem);
+  uint8_t *sInv = smem + P::kInvOff;
+  float *sE = reinterpret_cast<float *>(smem + P::kEOff);
+  const char *lds = reinterpret_cast<const char *>(smem);
+
+  const int K = a.K;
+  const int LK = LT * K;
+  const int CPR = BLOCK / K;
+  const int q = threadIdx.x;
+  const int myc = q / K;
+  const int myp = q - myc * K;
+  const int rounds = (a.n + CPR - 1) / CPR;
+
+  if constexpr (NT == 1) {
+    load_tile<MODE>(a.T2, a.T1, LT, TPT, 0, LT, TR, sT);
+    __syncthreads();
+  }
+  for (int r = blockIdx.x; r < rounds; r += gridDim.x) {
+    const int c0 = r * CPR;
+    const int nc = min(CPR, a.n - c0);
+    build_inverse(a.pop + (size_t)c0 * LK, nc * LK, LT, K, sInv);
+    __syncthreads();
+    const bool active = myc < nc;
+    const uint8_t *ip = sInv + q * LT;  // inv[myc][myp][.]
+    uint32_t A[LT];
+#pragma unroll
+    for (int j = 0; j < LT; ++j) {
+      const uint32_t v = active ? ip[j] : 0u;
+      A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
+    }
+    float acc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      if constexpr (NT > 1) {
+        __syncthreads();
+        const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
+        load_tile<MODE>(a.T2, a.T1, LT, TPT, t * TR, rows, TR, sT);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int lr = 0; lr < TR; ++lr) {
+        const int l = t * TR + lr;
+        if (l < LT) {
+          float a_l = 0.0f, c2_l = 0.0f;
+          if constexpr (MODE == 1) {
+            a_l = a.lconst[2 * l];
+            c2_l = a.lconst[2 * l + 1];
+          }
+          acc = acc + row_term_exact<LT, MODE>(lds, A, (uint32_t)(lr * ROWB), TPT * 4u, l, a_l,
+                                               c2_l);
+        }
+      }
+    }
+    if (active) sE[q] = acc;
+    __syncthreads();
+    if (q < nc) {
+      tree_sum(sE + q * K, K);
+      a.fit[c0 + q] = a.prelog * sE[q * K];
+    }
+    __syncthreads();
+  }
+}
+
+template <int LMAX, int MODE>
+__global__ __launch_bounds__(1024) void k_fitness_generic(FitArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int L = a.L, K = a.K, TP = a.TP;
+  const int TR = a.tile_rows;
+  const int NT = (L + TR - 1) / TR;
+  const int ROWB = TP * 4 * (MODE == 1 ? 2 : 1);
+  const int CELLB = TR * ROWB;
+  float *sT = reinterpret_cast<float *>(smem);
+  uint8_t *sInv = smem + a.inv_off;
+  float *sE = reinterpret_cast<float *>(smem + a.e_off);
+  const char *lds = reinterpret_cast<const char *>(smem);
+  const int LK = L * K;
+  const int CPR = (int)blockDim.x / K;
+  const int q = threadIdx.x;
+  const int myc = q / K;
+  const int myp = q - myc * K;
+  const int rounds = (a.n + CPR - 1) / CPR;
+
+  if (NT == 1) {
+    load_tile<MODE>(a.T2, a.T1, L, TP, 0, L, TR, sT);
+    __syncthreads();
+  }
+  for (int r = blockIdx.x; r < rounds; r += gridDim.x) {
+    const int c0 = r * CPR;
+    const int nc = min(CPR, a.n - c0);
+    build_inverse(a.pop + (size_t)c0 * LK, nc * LK, L, K, sInv);
+    __syncthreads();
+    const bool active = myc < nc;
+    const uint8_t *ip = sInv + q * L;  // inv[myc][myp][.]
+    uint32_t A[LMAX];
+#pragma unroll
+    for (int j = 0; j < LMAX; ++j) {
+      uint32_t v = 0u;
+      if (active && j < L) v = ip[j];
+      A[j] = (uint32_t)(j * CELLB) + (v & (uint32_t)(TP - 1)) * 4u;
+    }
+    float acc = 0.0f;
+    for (int t = 0; t < NT; ++t) {
+      const int l0 = t * TR;
+      const int rows = min(TR, L - l0);
+      if (NT > 1) {
+        __syncthreads();
+        load_tile<MODE>(a.T2, a.T1, L, TP, l0, rows, TR, sT);
+        __syncthreads();
+      }
+      for (int lr = 0; lr < rows; ++lr) {
+        const int l = l0 + lr;
+        float a_l = 0.0f, c2_l = 0.0f;
+        if (MODE == 1) {
+          a_l = a.lconst[2 * l];
+          c2_l = a.lconst[2 * l + 1];
+        }
+        acc = acc + row_term_generic<LMAX, MODE>(lds, A, (uint32_t)(lr * ROWB), (uint32_t)TP * 4u,
+                                                 L, l, a_l, c2_l);
+      }
+    }
+    if (active) sE[q] = acc;
+    __syncthreads();
+    if (q < nc) {
+      tree_sum(sE + q * K, K);
+      a.fit[c0 + q] = a.prelog * sE[q * K];
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+namespace {
+
+// Raises a kernel's dynamic-LDS limit; a runtime that does not need (or know)
+// the attribute leaves the default, so its error is cleared, not returned.
+void allow_lds(const void *kern, int bytes) {
+  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
+    (void)hipGetLastError();
+}
+
+template <int LT, int TPT, int MODE>
+constexpr int exact_block() {
+  // Small tables: 256 threads so several workgroups share a CU; large ones:
+  // 512 threads (8 waves, up to 256 VGPRs each: the unrolled L = 37 row loop
+  // spills under the 128-register cap of 1024-thread groups).
+  return (LT * LT * TPT * 4 * (MODE == 1 ? 2 : 1) <= 40 * 1024) ? 256 : 512;
+}
+
+template <int LT, int TPT, int MODE>
+hipError_t run_exact(const FitArgs &a0, const DeviceInfo &dev, int grid_cap, hipStream_t s) {
+  constexpr int B = exact_block<LT, TPT, MODE>();
+  using P = ExactPlan<LT, TPT, MODE, B>;
+  FitArgs a = a0;
+  a.inv_off = P::kInvOff;
+  a.e_off = P::kEOff;
+  a.tile_rows = P::kTileRows;
+  const int cpr = B / a.K;
+  const int rounds = (a.n + cpr - 1) / cpr;
+  const int per_cu = P::kTotal > 0 ? (int)(kLdsBytes / P::kTotal) : 1;
+  int grid = dev.cus * (per_cu < 1 ? 1 : per_cu);
+  if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
+  if (grid > rounds) grid = rounds;
+  auto kern = k_fitness_exact<LT, TPT, MODE, B>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    allow_lds(reinterpret_cast<const void *>(kern), P::kTotal);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(B), P::kTotal, s, a);
+  return hipGetLastError();
+}
+
+template <int LT, int MODE>
+hipError_t run_exact_tp(const FitArgs &a, const DeviceInfo &dev, int grid_cap, hipStream_t s,
+                        bool *handled) {
+  *handled = true;
+  switch (a.TP) {
+    case 4: return run_exact<LT, 4, MODE>(a, dev, grid_cap, s);
+    case 8: return run_exact<LT, 8, MODE>(a, dev, grid_cap, s);
+    case 16: return run_exact<LT, 16, MODE>(a, dev, grid_cap, s);
+    case 32: return run_exact<LT, 32, MODE>(a, dev, grid_cap, s);
+    default: *handled = false; return hipSuccess;
+  }
+}
+
+template <int MODE>
+hipError_t run_exact_any(const FitArgs &a, const DeviceInfo &dev, int grid_cap, hipStream_t s,
+                         bool *handled) {
+  *handled = false;
+  switch (a.L) {
+    case 7: return run_exact_tp<7, MODE>(a, dev, grid_cap, s, handled);
+    case 19: return run_exact_tp<19, MODE>(a, dev, grid_cap, s, handled);
+    case 37: return run_exact_tp<37, MODE>(a, dev, grid_cap, s, handled);
+    default: return hipSuccess;
+  }
+}
+
+template <int LMAX, int MODE>
+hipError_t run_generic(const FitArgs &a0, int block, const DeviceInfo &dev, int grid_cap,
+                       hipStream_t s) {
+  FitArgs a = a0;
+  const int inv = (block * a.L + 15) / 16 * 16;
+  const int eb = block * 4;
+  const int row_bytes = a.L * a.TP * 4 * (MODE == 1 ? 2 : 1);
+  const int budget = kLdsBytes - inv - eb - 256;
+  int max_rows = budget / row_bytes;
+  if (max_rows < 1) return hipErrorInvalidValue;
+  const int tiles = (a.L + max_rows - 1) / max_rows;
+  const int tr = (a.L + tiles - 1) / tiles;
+  a.tile_rows = tr;
+  a.inv_off = tr * row_bytes;
+  a.e_off = a.inv_off + inv;
+  const int total = a.e_off + eb;
+  const int cpr = block / a.K;
+  const int rounds = (a.n + cpr - 1) / cpr;
+  int grid = dev.cus * (kLdsBytes / total < 1 ? 1 : kLdsBytes / total);
+  if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
+  if (grid > rounds) grid = rounds;
+  auto kern = k_fitness_generic<LMAX, MODE>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    allow_lds(reinterpret_cast<const void *>(kern), kLdsBytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), total, s, a);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t run_generic_any(const FitArgs &a, int block, const DeviceInfo &dev, int grid_cap,
+                           hipStream_t s) {
+  if (a.L <= 8) return run_generic<8, MODE>(a, block, dev, grid_cap, s);
+  if (a.L <= 16) return run_generic<16, MODE>(a, block, dev, grid_cap, s);
+  if (a.L <= 32) return run_generic<32, MODE>(a, block, dev, grid_cap, s);
+  return run_generic<64, MODE>(a, block, dev, grid_cap, s);
+}
+
+}  // namespace
+
+// shape.block > 0 with shape.grid < 0 forces the generic variant (used by the
+// tests to check that every variant gives the same bits).
+hipError_t launch_fitness(const DevProblem &p, const uint8_t *pop, int n, float *fit,
+                          const FitShape &shape, const DeviceInfo &dev, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  FitArgs a{};
+  a.T2 = p.T2;
+  a.T1 = p.T1;
+  a.lconst = p.lconst;
+  a.pop = pop;
+  a.fit = fit;
+  a.n = n;
+  a.L = p.L;
+  a.K = p.K;
+  a.TP = p.TP;
+  a.prelog = p.prelog;
+  const bool force_generic = shape.grid < 0;
+  const int grid_cap = shape.grid > 0 ? shape.grid : 0;
+  if (!force_generic) {
+    bool handled = false;
+    hipError_t e = p.se_mode == 1 ? run_exact_any<1>(a, dev, grid_cap, s, &handled)
+                                  : run_exact_any<0>(a, dev, grid_cap, s, &handled);
+    if (handled) return e;
+  }
+  int block = shape.block > 0 ? shape.block : 256;
+  if (block < p.K) block = p.K;
+  block = (block + 63) / 64 * 64;
+  if (block > 1024) block = 1024;
+  return p.se_mode == 1 ? run_generic_any<1>(a, block, dev, grid_cap, s)
+                        : run_generic_any<0>(a, block, dev, grid_cap, s);
+}
+
+}  // namespace pa

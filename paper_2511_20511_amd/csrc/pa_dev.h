@@ -1,0 +1,103 @@
+// pa_dev.h -- device helpers shared by the gfx950 kernels: Philox4x32-10
+// random words, bounded draws, ranking keys, wavefront reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pa {
+
+constexpr int kWave = 64;
+
+// Stream tags of the counter word c3 = tag << 24 | block.
+enum : uint32_t {
+  kTagSelect = 0x01u,
+  kTagMutDecide = 0x02u,
+  kTagMutPartner = 0x03u,
+  kTagInitDecide = 0x10u,
+  kTagInitPartner = 0x11u,
+  kTagInitShuffle = 0x12u,
+};
+constexpr uint32_t kInitGeneration = 0xFFFFFFFFu;  // c1 of population-init streams
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64
+// multiplications (words 0 and 2) whose halves are swapped into place and
+// xored with the round key; the key advances by the Weyl increments.
+struct Words4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+    const uint32_t lo0 = m0 * c0, hi0 = __umulhi(m0, c0);
+    const uint32_t lo1 = m1 * c2, hi1 = __umulhi(m1, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t pick(const Words4 &b, uint32_t i) {
+  return i == 0 ? b.x : i == 1 ? b.y : i == 2 ? b.z : b.w;
+}
+
+// Random stream identity: key = seed; counter = (c0, c1, c2, tag<<24 | block).
+struct Stream {
+  uint32_t k0, k1, c0, c1, c2, tag;
+  __device__ __forceinline__ Words4 block(uint32_t b) const {
+    return philox10(c0, c1, c2, (tag << 24) | b, k0, k1);
+  }
+  __device__ __forceinline__ uint32_t word(uint32_t i) const { return pick(block(i >> 2), i & 3u); }
+};
+
+// Lemire multiply-shift onto [0, n).
+__device__ __forceinline__ uint32_t bounded(uint32_t w, uint32_t n) {
+  return __umulhi(w, n);
+}
+// Event test against a threshold floor(p * 2^32) in [0, 2^32].
+__device__ __forceinline__ bool hit(uint32_t w, uint64_t thr) { return (uint64_t)w < thr; }
+
+// Order-preserving map of an FP32 fitness to uint32: larger key = better.
+// NaN maps below everything (0); -0 and +0 get the same key.
+__device__ __forceinline__ uint32_t rank_key(float f) {
+  uint32_t b = __float_as_uint(f);
+  if (f != f) return 0u;
+  if (b == 0x80000000u) b = 0u;
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+// a beats b: larger key, or equal key and lower index.
+__device__ __forceinline__ bool beats(uint32_t ka, uint32_t a, uint32_t kb, uint32_t b) {
+  return ka > kb || (ka == kb && a < b);
+}
+// 64-bit sort key: rank key above, complemented index below (unique per index).
+__device__ __forceinline__ uint64_t full_key(float f, uint32_t idx) {
+  return ((uint64_t)rank_key(f) << 32) | (uint64_t)(0xFFFFFFFFu - idx);
+}
+__device__ __forceinline__ uint32_t key_index(uint64_t k) { return 0xFFFFFFFFu - (uint32_t)k; }
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, kWave);
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const uint64_t o = __shfl_xor(v, off, kWave);
+    v = o < v ? o : v;
+  }
+  return v;
+}
+
+}  // namespace pa

@@ -1,0 +1,73 @@
+// pa_internal.h -- structures shared by the host runtime (api.cpp) and the
+// kernel launchers (k_*.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pa {
+
+constexpr int kMaxL = 64;
+constexpr int kMaxK = 64;
+constexpr int kMaxGenes = kMaxL * kMaxK;  // 4096 genes per chromosome
+
+// Table row padding: the pilot axis of the FP32 tables is padded to 4, 8, 16,
+// 32 or 64 entries so a BS row has a compile-time stride in the kernels.
+inline int pad_pilots(int K) {
+  int p = 4;
+  while (p < K) p <<= 1;
+  return p;
+}
+
+// Device copy of one problem.  All pointers are device memory owned by the
+// instance.
+struct DevProblem {
+  int L = 0, K = 0, TP = 0;  // cells, users (= pilots), padded pilot stride
+  int se_mode = 0;
+  float prelog = 1.0f;       // 1 - tau/T, or 1
+  double *beta = nullptr;    // [L][L][K] FP64 as given
+  float *T2 = nullptr;       // [L(cell j)][L(BS l)][TP] normalised beta squared (FP32)
+  float *T1 = nullptr;       // same layout, normalised beta (finite-M only)
+  float *lconst = nullptr;   // [L][2]: tau*rho_l and (1 + rho_l*B_l)/(M tau rho_l^2)
+  double *user_xy = nullptr; // [L][K][2] or null
+  double *bs_xy = nullptr;   // [L][2] or null
+  uint8_t *seed = nullptr;   // [L][K] K-means seed chromosome
+  int32_t *km_cent = nullptr;   // [K][2]
+  int32_t *km_labels = nullptr; // [L*K]
+  int32_t *km_iters = nullptr;  // [1]
+};
+
+// GA parameters as the kernels need them (thresholds already computed).
+struct DevGa {
+  int N = 0, E = 0, n_km = 0;
+  uint64_t thr_cross = 0, thr_mut = 0, thr_init = 0;
+  uint32_t seed_lo = 0, seed_hi = 0, instance_id = 0;
+};
+
+// Launch-shape knobs of the fitness kernel (never change result bits).
+struct FitShape {
+  int block = 256;  // threads per workgroup
+  int grid = 0;     // 0 = one workgroup per round of chromosomes (capped)
+};
+
+struct DeviceInfo {
+  int cus = 256;
+  size_t lds_per_block = 163840;
+};
+
+// ---- launchers (return hipSuccess or the first HIP error) ----------------
+hipError_t launch_prep(const DevProblem &p, int M, double rho, hipStream_t s);
+hipError_t launch_fitness(const DevProblem &p, const uint8_t *pop, int n, float *fit,
+                          const FitShape &shape, const DeviceInfo &dev, hipStream_t s);
+hipError_t launch_kmeans_seed(const DevProblem &p, hipStream_t s);
+hipError_t launch_init_pop(const DevProblem &p, const DevGa &ga, uint8_t *pop, hipStream_t s);
+// One generation of operators.  fit_out (may be null) receives the elites'
+// fitness in slots 0..E-1; trace (may be null) receives the best fitness of
+// the input population at index `gen`.
+hipError_t launch_ga_step(const DevProblem &p, const DevGa &ga, uint32_t gen, const uint8_t *pin,
+                          const float *fin, uint8_t *pout, float *fit_out, float *trace,
+                          hipStream_t s);
+// Best chromosome of a population: writes best index (int32) and fitness.
+hipError_t launch_best(const float *fit, int N, int32_t *best_idx, float *best_fit,
+                       hipStream_t s);
+
+}  // namespace pa
