@@ -51,6 +51,42 @@ def cpu_baseline(drop, w, budget_s=12.0):
             "sample": f"{solves} full oracle solve(s) of the same workload ({el:.1f} s, FP64, 1 thread)"}
 
 
+def run_batch(pa, scenario, torch, name):
+    """Many independent instances in one graph-captured batch: evals/s and solves/s."""
+    import numpy as np
+    w = dict(scenario.WORKLOADS[name])
+    L, K, N, G, E, n = w["L"], w["K"], w["N"], w["gens"], w["E"], w["instances"]
+    ctx = pa.pa_context_create(0)
+    insts, params = [], []
+    for i in range(n):
+        d = scenario.make_drop(L, K, seed=w["seed"], instance_id=i)
+        insts.append(pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=w["T"], M=w["M"],
+                                           rho=scenario.snr_to_rho(w["snr_db"])))
+        params.append(pa.GaParams(pop=N, gens=G, elite=E, p_cross=w["p_cross"], p_mut=w["p_mut"],
+                                  kmeans_frac=w["kmeans_frac"], p_init=w["p_init"],
+                                  seed=w["seed"], instance_id=i))
+    pa.pa_solve_batch(ctx, insts, params)  # builds and captures the plan
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev = []
+    for _ in range(reps):
+        res = pa.pa_solve_batch(ctx, insts, params)
+        dev.append(res[0].device_ms)
+    wall = (time.perf_counter() - t0) / reps
+    ev = n * evals_per_solve(N, E, G)
+    gathers = n * (N + (N - E) * G) * L * L * K
+    out = {"workload": name, "instances": n, "L": L, "K": K, "pop": N, "gens": G,
+           "ms_per_batch": wall * 1e3, "device_ms": float(np.median(dev)),
+           "evals_per_s": ev / wall, "solves_per_s": n / wall,
+           "lds_gbs": gathers * 4 / wall / 1e9,
+           "lds_frac_of_peak": gathers * 4 / wall / 1e9 / LDS_PEAK_GBS,
+           "best_fit_first": res[0].best_fit}
+    log(f"batch {name}: {wall * 1e3:.1f} ms, {ev / wall:.3e} evals/s, {n / wall:.1f} solves/s, "
+        f"LDS {out['lds_gbs']:.0f} GB/s ({100 * out['lds_frac_of_peak']:.1f}%)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +95,8 @@ def main():
     ap.add_argument("--workload", default="single_L19_K16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
+    ap.add_argument("--batch", default="batch64_L37_K32",
+                    help="also time this batched workload ('' to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -101,28 +139,42 @@ def main():
     log(f"solve: {ms_per_step:.3f} ms/solve wall, device {np.median(dev_ms):.3f} ms, "
         f"best {res.best_fit:.4f}")
 
-    # dominant kernel: population fitness at the solve's launch configuration
-    d_pop = torch.zeros((N, L, K), dtype=torch.uint8, device="cuda")
-    d_fit = torch.zeros(N, dtype=torch.float32, device="cuda")
-    pa.pa_kmeans_init(inst, params, d_pop)
-    for _ in range(10):
-        pa.pa_fitness(inst, d_pop, N, d_fit)
+    # plain comparator: one launch per step, no fusion, no graph
+    pa.pa_solve_plain(inst, params)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plain_steps = max(1, args.steps // 2)
+    for _ in range(plain_steps):
+        pa.pa_solve_plain(inst, params)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t1) * 1e3 / plain_steps
+    log(f"plain solve (one launch per step): {plain_ms:.3f} ms/solve")
+
+    # dominant kernel: the fused generation kernel, one launch per generation,
+    # timed with events on the stream it is launched on
+    pa.pa_solve_begin(inst, params)
+    pa.pa_solve_next(inst, 10)
+    iters = min(args.kernel_iters, G - 10)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    for _ in range(args.kernel_iters):
-        pa.pa_fitness(inst, d_pop, N, d_fit)
+    pa.pa_solve_next(inst, iters)
     e1.record(stream)
     e1.synchronize()
-    k_ms = e0.elapsed_time(e1) / args.kernel_iters
-    lds_bytes = N * L * L * K * 4  # one 4-byte table word per (BS, cell, pilot) per chromosome
+    k_ms = e0.elapsed_time(e1) / iters
+    # algorithmic LDS bytes of one launch: every child reads one 4-byte table
+    # word per (BS, cell, pilot)
+    lds_bytes = (N - E) * L * L * K * 4
     achieved = lds_bytes / (k_ms * 1e-3) / 1e9
-    roofline = {"bound": "lds", "kernel": "k_fitness", "achieved": achieved,
-                "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": achieved / LDS_PEAK_GBS,
-                "traffic": None, "avg_launch_us": k_ms * 1e3,
-                "bytes_per_launch": lds_bytes}
-    log(f"k_fitness n={N}: {k_ms * 1e3:.2f} us/launch, {achieved:.0f} GB/s LDS "
+    roofline = {"bound": "lds", "kernel": f"k_gen_exact<{L},{max(4, 1 << (K - 1).bit_length())},0,*>",
+                "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                "avg_launch_us": k_ms * 1e3, "bytes_per_launch": lds_bytes}
+    log(f"fused generation kernel: {k_ms * 1e3:.2f} us/launch, {achieved:.0f} GB/s LDS "
         f"({100 * achieved / LDS_PEAK_GBS:.1f}% of {LDS_PEAK_GBS:.0f})")
 
+    extra = {}
+    if args.batch:
+        extra["batch"] = run_batch(pa, scenario, torch, args.batch)
     line = {
         "metric": "chromosome fitness evals/s", "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -132,8 +184,10 @@ def main():
                    "pop": N, "gens": G, "elite": E, "instances": 1},
         "solves_per_s": args.steps / wall,
         "solve_device_ms": float(np.median(dev_ms)),
+        "plain_solve_ms": plain_ms,
         "roofline": roofline,
     }
+    line.update(extra)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(drop, w)

@@ -193,9 +193,34 @@ pa_status pa_ga_step(pa_instance *inst, const pa_ga_params *params, int32_t gen,
 
 /* A whole solve: seeding, then `gens` generations of select / evolve /
  * evaluate with the population resident on the device, then the best
- * chromosome of the last population (Alg. 1 "return best assignment").
- * Blocking. */
+ * chromosome of the last population (Alg. 1, which returns the best
+ * assignment).  Each generation is one fused launch (children built,
+ * written and evaluated in LDS); the whole solve is captured once into a
+ * hipGraph and replayed while the parameters stay the same.  Blocking. */
 pa_status pa_solve(pa_instance *inst, const pa_ga_params *params, pa_result *out, void *stream);
+
+/* Many independent solves in one: n instances of the same context, each with
+ * its own parameters (sizes may differ), run generation by generation, each
+ * generation one launch per class of (L, padded K, SE mode) covering every
+ * instance of the class; the whole batch is captured once into a hipGraph
+ * and replayed while (instances, params) stay the same.  results[i] is filled
+ * as pa_solve would fill it and is bit-identical to a pa_solve of instance i
+ * alone; device_ms is the time of the whole batch.  An instance may appear
+ * only once.  Blocking. */
+pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
+                         const pa_ga_params *params, pa_result *results, void *stream);
+
+/* Stepwise solve, for callers that decide themselves when to stop (Alg. 1
+ * loops "while termination not met"); same kernels and bits as pa_solve.
+ *   pa_solve_begin  seeding, initial population and its fitness.  Async.
+ *   pa_solve_next   ngens more generations, one fused launch each; at most
+ *                   params->gens in total since the last begin.  Async.
+ *   pa_solve_state  best chromosome and fitness of the current population,
+ *                   trace[0..gens_done]; *gens_done = generations run so far.
+ *                   device_ms covers only this call.  Blocking. */
+pa_status pa_solve_begin(pa_instance *inst, const pa_ga_params *params, void *stream);
+pa_status pa_solve_next(pa_instance *inst, int32_t ngens, void *stream);
+pa_status pa_solve_state(pa_instance *inst, pa_result *out, int32_t *gens_done, void *stream);
 
 /* The same solve as one launch per step (seeding, fitness, then per
  * generation a pa_ga_step launch and a pa_fitness launch), no fusion and no

@@ -22,7 +22,8 @@ __all__ = [
     "PaError", "GaParams", "Result", "lib", "library_path",
     "pa_context_create", "pa_context_destroy", "pa_instance_create", "pa_instance_destroy",
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
-    "pa_solve_plain", "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
+    "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
+    "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
     "SE_ASYMPTOTIC", "SE_FINITE_M",
 ]
@@ -111,7 +112,12 @@ def lib():
         "pa_ga_step": (st, [vp, ctypes.POINTER(_Params), i32, vp, vp, vp, vp]),
         "pa_solve": (st, [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Result), vp]),
         "pa_solve_plain": (st, [vp, ctypes.POINTER(_Params), ctypes.POINTER(_Result), vp]),
+        "pa_solve_batch": (st, [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(_Params),
+                                ctypes.POINTER(_Result), vp]),
         "pa_instance_kmeans_state": (st, [vp, vp, vp, vp, vp]),
+        "pa_solve_begin": (st, [vp, ctypes.POINTER(_Params), vp]),
+        "pa_solve_next": (st, [vp, i32, vp]),
+        "pa_solve_state": (st, [vp, ctypes.POINTER(_Result), ctypes.POINTER(i32), vp]),
         "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
         "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
         "pa_status_string": (ctypes.c_char_p, [st]),
@@ -290,6 +296,44 @@ def pa_solve(inst: Instance, params: GaParams, stream=None) -> Result:
 
 def pa_solve_plain(inst: Instance, params: GaParams, stream=None) -> Result:
     return _solve(lib().pa_solve_plain, inst, params, stream)
+
+
+def pa_solve_batch(ctx: Context, insts, params, stream=None) -> list:
+    """Solves many instances in one graph-captured batch; one Result per instance."""
+    n = len(insts)
+    if len(params) != n:
+        raise ValueError("one GaParams per instance")
+    handles = (ctypes.c_void_p * max(n, 1))(*[i.h for i in insts])
+    cp = (_Params * max(n, 1))(*[p.to_c() for p in params])
+    bests = [np.zeros((i.L, i.K), dtype=np.uint8) for i in insts]
+    traces = [np.zeros(p.gens + 1, dtype=np.float32) for p in params]
+    cr = (_Result * max(n, 1))(*[_Result(b.ctypes.data, 0.0, 0, t.ctypes.data, 0.0)
+                                 for b, t in zip(bests, traces)])
+    _check(lib().pa_solve_batch(ctx.h, n, handles, cp, cr, _stream(stream)))
+    return [Result(bests[i], float(cr[i].best_fit), int(cr[i].best_index), traces[i],
+                   float(cr[i].device_ms)) for i in range(n)]
+
+
+def pa_solve_begin(inst: Instance, params: GaParams, stream=None):
+    inst._gens = params.gens
+    p = params.to_c()
+    _check(lib().pa_solve_begin(inst.h, ctypes.byref(p), _stream(stream)))
+
+
+def pa_solve_next(inst: Instance, ngens: int = 1, stream=None):
+    _check(lib().pa_solve_next(inst.h, int(ngens), _stream(stream)))
+
+
+def pa_solve_state(inst: Instance, stream=None):
+    """(Result, generations done) of a stepwise solve."""
+    gens = getattr(inst, "_gens", 0)
+    best = np.zeros((inst.L, inst.K), dtype=np.uint8)
+    trace = np.zeros(gens + 1, dtype=np.float32)
+    r = _Result(best.ctypes.data, 0.0, 0, trace.ctypes.data, 0.0)
+    done = ctypes.c_int32(0)
+    _check(lib().pa_solve_state(inst.h, ctypes.byref(r), ctypes.byref(done), _stream(stream)))
+    return Result(best, float(r.best_fit), int(r.best_index), trace[:done.value + 1],
+                  float(r.device_ms)), int(done.value)
 
 
 def pa_instance_kmeans_state(inst: Instance):

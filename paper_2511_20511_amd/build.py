@@ -20,7 +20,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpa_amd.so")
 
-SOURCES = ["api.cpp", "k_prep.hip", "k_fitness.hip", "k_ga.hip", "k_kmeans.hip"]
+SOURCES = ["api.cpp", "k_prep.hip", "k_fitness.hip", "k_ga.hip", "k_kmeans.hip", "k_gen.hip",
+           "k_gen_L7.hip", "k_gen_L19.hip", "k_gen_L37.hip", "solve.cpp"]
 ARCH = "gfx950"
 
 

@@ -12,32 +12,9 @@
 #include <vector>
 
 #include "../../include/pa.h"
-#include "pa_internal.h"
+#include "pa_host.h"
 
 using namespace pa;
-
-struct pa_context {
-  int device = 0;
-  DeviceInfo info;
-  hipStream_t stream = nullptr;  // library-internal work (instance creation)
-};
-
-struct pa_instance {
-  pa_context *ctx = nullptr;
-  DevProblem p;
-  int M = 1;
-  double rho = 1.0;
-  int T = 0;
-  bool has_pos = false;
-  // solve work buffers (grown on demand)
-  int work_N = 0, work_G = -1;
-  uint8_t *popA = nullptr, *popB = nullptr;
-  float *fitA = nullptr, *fitB = nullptr;
-  float *trace = nullptr;
-  int32_t *best_idx = nullptr;
-  float *best_fit = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-};
 
 namespace {
 
@@ -168,7 +145,7 @@ void dfree(void *p) {
   if (p) (void)hipFree(p);
 }
 
-pa_status ensure_work(pa_instance *in, int N, int G) {
+pa_status ensure_work_impl(pa_instance *in, int N, int G) {
   const size_t LK = (size_t)in->p.L * in->p.K;
   if (in->work_N < N) {
     dfree(in->popA);
@@ -234,6 +211,25 @@ pa_status set_device(pa_context *ctx) {
 
 }  // namespace
 
+namespace pa {
+pa_status set_error(pa_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+pa_status hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+pa_status validate_ga(const pa_instance *inst, const pa_ga_params *g) {
+  return validate_params(inst, g);
+}
+DevGa ga_from_params(const pa_ga_params *g) { return make_ga(g); }
+pa_status ensure_work(pa_instance *in, int N, int G) { return ensure_work_impl(in, N, G); }
+pa_status use_device(pa_context *ctx) { return set_device(ctx); }
+}  // namespace pa
+
 extern "C" {
 
 const char *pa_version(void) { return "pa-mi355x 0.1 (gfx950)"; }
@@ -292,6 +288,7 @@ pa_status pa_context_create(int32_t device, pa_context **out) {
 void pa_context_destroy(pa_context *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
+  free_plan(ctx->batch_plan);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -299,8 +296,14 @@ void pa_context_destroy(pa_context *ctx) {
 void pa_instance_destroy(pa_instance *in) {
   if (!in) return;
   (void)hipSetDevice(in->ctx->device);
+  free_plan(in->plan);
+  if (in->ctx->batch_plan) {  // a batch plan may point at this instance's buffers
+    free_plan(in->ctx->batch_plan);
+    in->ctx->batch_plan = nullptr;
+  }
   DevProblem &p = in->p;
-  for (void *ptr : {(void *)p.beta, (void *)p.T2, (void *)p.T1, (void *)p.lconst,
+  for (void *ptr : {(void *)p.beta, (void *)p.T2, (void *)p.T1, (void *)p.T2z, (void *)p.Town,
+                    (void *)p.lconst,
                     (void *)p.user_xy, (void *)p.bs_xy, (void *)p.seed, (void *)p.km_cent,
                     (void *)p.km_labels, (void *)p.km_iters, (void *)in->popA, (void *)in->popB,
                     (void *)in->fitA, (void *)in->fitB, (void *)in->trace, (void *)in->best_idx,
@@ -337,6 +340,8 @@ pa_status pa_instance_create(pa_context *ctx, const pa_problem *prob, pa_instanc
   };
   chk(dalloc(&p.beta, L * L * K));
   chk(dalloc(&p.T2, L * L * TP));
+  chk(dalloc(&p.T2z, L * L * TP));
+  chk(dalloc(&p.Town, L * TP));
   if (p.se_mode == PA_SE_FINITE_M) chk(dalloc(&p.T1, L * L * TP));
   chk(dalloc(&p.lconst, 2 * L));
   chk(dalloc(&p.seed, L * K));
@@ -438,7 +443,7 @@ pa_status pa_solve_plain(pa_instance *in, const pa_ga_params *g, pa_result *out,
   if (st != PA_OK) return st;
   if ((st = set_device(in->ctx)) != PA_OK) return st;
   const int N = g->pop, G = g->gens;
-  if ((st = ensure_work(in, N, G)) != PA_OK) return st;
+  if ((st = ensure_work_impl(in, N, G)) != PA_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const DevGa ga = make_ga(g);
   FitShape shape;
@@ -456,10 +461,6 @@ pa_status pa_solve_plain(pa_instance *in, const pa_ga_params *g, pa_result *out,
     std::swap(in->fitA, in->fitB);
   }
   return finish_solve(in, N, G, out, s);
-}
-
-pa_status pa_solve(pa_instance *in, const pa_ga_params *g, pa_result *out, void *stream) {
-  return pa_solve_plain(in, g, out, stream);
 }
 
 pa_status pa_instance_kmeans_state(pa_instance *in, uint8_t *seed, int32_t *centroids,

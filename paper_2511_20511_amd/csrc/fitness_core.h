@@ -49,16 +49,19 @@ __device__ __forceinline__ void tree_sum(float *seg, int K) {
 
 // Inverse rows of the chromosomes of a round, stored pilot-major:
 // inv[c][s][j] = the user of cell j that sends pilot s in chromosome c, so a
-// lane (c, s) finds its L entries contiguous.  Gene g of the round is
-// (c, j, k) with g = (c*L + j)*K + k.  Pilots >= K (invalid input) are skipped
-// so the LDS write stays inside the chromosome.
-__device__ __forceinline__ void build_inverse(const uint8_t *__restrict__ src, int ngenes, int L,
-                                              int K, uint8_t *sInv) {
-  for (int g = threadIdx.x; g < ngenes; g += blockDim.x) {
-    const int cj = g / K, k = g - cj * K;
-    const int c = cj / L, j = cj - c * L;
-    const int s = src[g];
-    if (s < K) sInv[(c * K + s) * L + j] = (uint8_t)k;
+// lane (c, s) finds its L entries contiguous.  One thread per row (c, j) of
+// the round's bytes `src` (LDS, nrows*K bytes); pilots >= K (invalid input)
+// are skipped so the write stays inside the chromosome.
+__device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int L, int K,
+                                              uint8_t *sInv) {
+  for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
+    const int c = r / L, j = r - c * L;
+    const uint8_t *row = src + r * K;
+    uint8_t *dst = sInv + c * K * L + j;
+    for (int k = 0; k < K; ++k) {
+      const int s = row[k];
+      if (s < K) dst[s * L] = (uint8_t)k;
+    }
   }
 }
 
@@ -116,26 +119,223 @@ __device__ __forceinline__ float row_term_generic(const char *lds, const uint32_
 
 // Copies BS rows [r0, r0 + rows) of the cell-major tables T2[j][l][TP]
 // (and T1) into the LDS tile T[j][lr][..] with rows_alloc rows per cell.
+// Each thread issues up to 8 independent 16-byte loads before storing, so a
+// small workgroup is not bound by one global-memory round trip per element.
 template <int MODE>
 __device__ __forceinline__ void load_tile(const float *__restrict__ T2, const float *__restrict__ T1,
                                           int L, int TP, int r0, int rows, int rows_alloc,
                                           float *dst) {
-  const int q = TP >> 2;                 // float4 per table row
+  constexpr int kBatch = 8;
+  const int q = TP >> 2;  // float4 per table row
   const int per_cell = rows * q;
+  const int total = L * per_cell;
   const float4 *s2 = reinterpret_cast<const float4 *>(T2);
   const float4 *s1 = reinterpret_cast<const float4 *>(T1);
   float4 *d = reinterpret_cast<float4 *>(dst);
-  for (int i = threadIdx.x; i < L * per_cell; i += blockDim.x) {
-    const int j = i / per_cell, rem = i - j * per_cell;
-    const int lr = rem / q, c = rem - lr * q;
-    const size_t src = ((size_t)j * L + r0 + lr) * q + c;
-    if constexpr (MODE == 0) {
-      d[(j * rows_alloc + lr) * q + c] = s2[src];
-    } else {
-      d[((j * rows_alloc + lr) * 2) * q + c] = s2[src];
-      d[((j * rows_alloc + lr) * 2 + 1) * q + c] = s1[src];
+  const int step = (int)blockDim.x;
+  for (int base = threadIdx.x; base < total; base += kBatch * step) {
+    float4 v2[kBatch], v1[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = min(base + u * step, total - 1);  // clamped: every load is in bounds
+      const int j = i / per_cell, rem = i - j * per_cell;
+      const int lr = rem / q, c = rem - lr * q;
+      const size_t src = ((size_t)j * L + r0 + lr) * q + c;
+      v2[u] = s2[src];
+      if constexpr (MODE == 1) v1[u] = s1[src];
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = base + u * step;
+      if (i < total) {
+        const int j = i / per_cell, rem = i - j * per_cell;
+        const int lr = rem / q, c = rem - lr * q;
+        if constexpr (MODE == 0) {
+          d[(j * rows_alloc + lr) * q + c] = v2[u];
+        } else {
+          d[((j * rows_alloc + lr) * 2) * q + c] = v2[u];
+          d[((j * rows_alloc + lr) * 2 + 1) * q + c] = v1[u];
+        }
+      }
     }
   }
+}
+
+constexpr int kLdsBytes = 163840;  // LDS per workgroup on gfx950
+
+// LDS plan: the table tile next to `EXTRA` bytes of other buffers.
+template <int LT, int TPT, int MODE, int EXTRA>
+struct TilePlan {
+  static constexpr int kRowBytes = LT * TPT * 4 * (MODE == 1 ? 2 : 1);  // one BS row, all cells
+  static constexpr int kBudget = kLdsBytes - EXTRA - 256;
+  static constexpr int kMaxRows = kBudget / kRowBytes;
+  static constexpr int kTiles = (LT + kMaxRows - 1) / kMaxRows;
+  static constexpr int kTileRows = (LT + kTiles - 1) / kTiles;
+  static constexpr int kTableBytes = kTileRows * kRowBytes;
+  static_assert(kMaxRows >= 1, "one BS row must fit in LDS");
+};
+
+// Sum over all BS rows of the SE terms of lane (c, p) in the canonical order;
+// `ip` = inv[c][p][0..L).  With more than one tile the tiles are (re)loaded
+// here, so every thread of the workgroup must call this (inactive lanes too).
+template <int LT, int TPT, int MODE, int TR, int NT>
+__device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, float *sT,
+                                                const float *__restrict__ T2,
+                                                const float *__restrict__ T1,
+                                                const float *__restrict__ lconst) {
+  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);  // bytes per (cell, BS row)
+  constexpr int CELLB = TR * ROWB;                      // bytes per cell in the tile
+  const char *lds = reinterpret_cast<const char *>(sT);
+  uint32_t A[LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) {
+    const uint32_t v = active ? ip[j] : 0u;
+    A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if constexpr (NT > 1) {
+      __syncthreads();
+      const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
+      load_tile<MODE>(T2, T1, LT, TPT, t * TR, rows, TR, sT);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int lr = 0; lr < TR; ++lr) {
+      const int l = t * TR + lr;
+      if (l < LT) {
+        float a_l = 0.0f, c2_l = 0.0f;
+        if constexpr (MODE == 1) {
+          a_l = lconst[2 * l];
+          c2_l = lconst[2 * l + 1];
+        }
+        acc = acc + row_term_exact<LT, MODE>(lds, A, (uint32_t)(lr * ROWB), TPT * 4u, l, a_l,
+                                             c2_l);
+      }
+    }
+  }
+  return acc;
+}
+
+// Tiled tables (more BS rows than LDS holds).  The tiles hold the table with
+// its own-cell entries zeroed (T2z[j][l][.] = 0 for j == l) and the own-cell
+// squares come from a small LDS table sOwn[l][p], so the tile loop need not
+// be unrolled: I sums every j in increasing order, and adding the exact +0.0
+// at j == l gives the same bits as skipping it.
+template <int LT, int TPT, int MODE, int TR>
+__device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, float *sT,
+                                                const float *sOwn, const float *__restrict__ T2z,
+                                                const float *__restrict__ T1,
+                                                const float *__restrict__ lconst) {
+  constexpr int NT = (LT + TR - 1) / TR;
+  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
+  constexpr int CELLB = TR * ROWB;
+  const char *lds = reinterpret_cast<const char *>(sT);
+  uint32_t A[LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) {
+    const uint32_t v = active ? ip[j] : 0u;
+    A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
+  }
+  float acc = 0.0f;
+#pragma unroll 1
+  for (int t = 0; t < NT; ++t) {
+    __syncthreads();
+    const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
+    load_tile<MODE>(T2z, T1, LT, TPT, t * TR, rows, TR, sT);
+    __syncthreads();
+    // Branch-free over the tile's rows (a row past the last BS row of a
+    // short final tile reads stale but in-bounds LDS and is not added), so
+    // the rows stay in order instead of being hoisted past per-row branches.
+#pragma unroll
+    for (int lr = 0; lr < TR; ++lr) {
+      const int l = min(t * TR + lr, LT - 1);
+      const uint32_t own = active ? ip[l] : 0u;
+      const float b2 = sOwn[l * TPT + (int)(own & (TPT - 1))];
+      const uint32_t off = (uint32_t)(lr * ROWB);
+      float I = 0.0f;
+#pragma unroll
+      for (int j = 0; j < LT; ++j) I = I + *reinterpret_cast<const float *>(lds + A[j] + off);
+      float se;
+      if constexpr (MODE == 1) {
+        float S = 0.0f;
+#pragma unroll
+        for (int j = 0; j < LT; ++j)
+          S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
+        se = se_finite(b2, I, S, lconst[2 * l], lconst[2 * l + 1]);
+      } else {
+        se = se_asym(b2, I);
+      }
+      const float next = acc + se;
+      acc = lr < rows ? next : acc;
+      // the next row's gathers wait for this row's sum: without this the
+      // compiler hoists every row's loads to the top of the tile and spills
+#pragma unroll
+      for (int j = 0; j < LT; ++j) asm volatile("" : "+v"(A[j]) : "v"(acc));
+    }
+  }
+  return acc;
+}
+
+// Copies the own-cell squares T2[l][l][.] of every BS row into LDS as
+// sOwn[l][p] (L x TP floats).
+__device__ __forceinline__ void load_own(const float *__restrict__ Town, int L, int TP, float *sOwn) {
+  for (int i = threadIdx.x; i < L * TP; i += blockDim.x) sOwn[i] = Town[i];
+}
+
+template <int LMAX, int MODE>
+__device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active, int L, int TP,
+                                                  int TR, float *sT,
+                                                  const float *__restrict__ T2,
+                                                  const float *__restrict__ T1,
+                                                  const float *__restrict__ lconst) {
+  const int NT = (L + TR - 1) / TR;
+  const int ROWB = TP * 4 * (MODE == 1 ? 2 : 1);
+  const int CELLB = TR * ROWB;
+  const char *lds = reinterpret_cast<const char *>(sT);
+  uint32_t A[LMAX];
+#pragma unroll
+  for (int j = 0; j < LMAX; ++j) {
+    uint32_t v = 0u;
+    if (active && j < L) v = ip[j];
+    A[j] = (uint32_t)(j * CELLB) + (v & (uint32_t)(TP - 1)) * 4u;
+  }
+  float acc = 0.0f;
+  for (int t = 0; t < NT; ++t) {
+    const int l0 = t * TR;
+    const int rows = min(TR, L - l0);
+    if (NT > 1) {
+      __syncthreads();
+      load_tile<MODE>(T2, T1, L, TP, l0, rows, TR, sT);
+      __syncthreads();
+    }
+    for (int lr = 0; lr < rows; ++lr) {
+      const int l = l0 + lr;
+      float a_l = 0.0f, c2_l = 0.0f;
+      if (MODE == 1) {
+        a_l = lconst[2 * l];
+        c2_l = lconst[2 * l + 1];
+      }
+      acc = acc + row_term_generic<LMAX, MODE>(lds, A, (uint32_t)(lr * ROWB), (uint32_t)TP * 4u,
+                                               L, l, a_l, c2_l);
+    }
+  }
+  return acc;
+}
+
+// Per-chromosome pairwise tree over pilots of the lanes' sums, then * prelog:
+// fit_out[c] for c < nc.  Called by every thread; ends with a barrier.
+__device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, int nc, int K,
+                                             float prelog, float *fit_out) {
+  const int q = threadIdx.x;
+  if (active) sE[q] = acc;
+  __syncthreads();
+  if (q < nc) {
+    tree_sum(sE + q * K, K);
+    fit_out[q] = prelog * sE[q * K];
+  }
+  __syncthreads();
 }
 
 }  // namespace pa

@@ -19,6 +19,8 @@ namespace pa {
 struct FitArgs {
   const float *T2;
   const float *T1;
+  const float *T2z;
+  const float *Town;
   const float *lconst;
   const uint8_t *pop;
   float *fit;
@@ -27,25 +29,25 @@ struct FitArgs {
   int tile_rows;  // generic variant: BS rows per LDS tile
   int inv_off;    // LDS byte offset of the inverse rows
   int e_off;      // LDS byte offset of the per-(c, p) sums
+  int stage_off;  // LDS byte offset of the round's chromosome bytes
 };
 
-constexpr int kLdsBytes = 163840;  // LDS per workgroup on gfx950
-
-// LDS plan of the exact variants: INV <= block*L bytes, E <= block*4 bytes.
+// LDS plan of the population-fitness kernels: the table tile, then the
+// inverse rows (<= block*L bytes), then the per-(c, p) sums (block*4 bytes).
 template <int LT, int TPT, int MODE, int BLOCK>
 struct ExactPlan {
-  static constexpr int kRowBytes = LT * TPT * 4 * (MODE == 1 ? 2 : 1);
   static constexpr int kInvBytes = ((BLOCK * LT) + 15) / 16 * 16;
   static constexpr int kEBytes = BLOCK * 4;
-  static constexpr int kBudget = kLdsBytes - kInvBytes - kEBytes - 256;
-  static constexpr int kMaxRows = kBudget / kRowBytes;
-  static constexpr int kTiles = (LT + kMaxRows - 1) / kMaxRows;
-  static constexpr int kTileRows = (LT + kTiles - 1) / kTiles;
-  static constexpr int kTableBytes = kTileRows * kRowBytes;
-  static constexpr int kInvOff = kTableBytes;
+  static constexpr int kOwnBytes = LT * TPT * 4;  // own-cell squares (tiled tables)
+  static constexpr int kStageBytes = kInvBytes;     // the round's chromosome bytes
+  using T = TilePlan<LT, TPT, MODE, kInvBytes + kEBytes + kOwnBytes + kStageBytes>;
+  static constexpr int kTiles = T::kTiles;
+  static constexpr int kTileRows = T::kTileRows;
+  static constexpr int kInvOff = T::kTableBytes;
   static constexpr int kEOff = kInvOff + kInvBytes;
-  static constexpr int kTotal = kEOff + kEBytes;
-  static_assert(kMaxRows >= 1, "one BS row must fit in LDS");
+  static constexpr int kOwnOff = kEOff + kEBytes;
+  static constexpr int kStageOff = kOwnOff + kOwnBytes;
+  static constexpr int kTotal = kStageOff + kStageBytes;
   static_assert(kTotal <= kLdsBytes, "LDS plan too large");
 };
 
@@ -54,69 +56,39 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   using P = ExactPlan<LT, TPT, MODE, BLOCK>;
   constexpr int NT = P::kTiles;
   constexpr int TR = P::kTileRows;
-  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);  // bytes per (cell, BS row)
-  constexpr int CELLB = TR * ROWB;                      // bytes per cell in the tile
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   float *sT = reinterpret_cast<float *>(smem);
   uint8_t *sInv = smem + P::kInvOff;
   float *sE = reinterpret_cast<float *>(smem + P::kEOff);
-  const char *lds = reinterpret_cast<const char *>(smem);
-
+  float *sOwn = reinterpret_cast<float *>(smem + P::kOwnOff);
+  uint8_t *sStage = smem + P::kStageOff;
   const int K = a.K;
   const int LK = LT * K;
   const int CPR = BLOCK / K;
   const int q = threadIdx.x;
-  const int myc = q / K;
-  const int myp = q - myc * K;
   const int rounds = (a.n + CPR - 1) / CPR;
 
   if constexpr (NT == 1) {
     load_tile<MODE>(a.T2, a.T1, LT, TPT, 0, LT, TR, sT);
     __syncthreads();
+  } else {
+    load_own(a.Town, LT, TPT, sOwn);  // ordered by the first barrier of lane_sum_tiled
   }
   for (int r = blockIdx.x; r < rounds; r += gridDim.x) {
     const int c0 = r * CPR;
     const int nc = min(CPR, a.n - c0);
-    build_inverse(a.pop + (size_t)c0 * LK, nc * LK, LT, K, sInv);
+    copy_bytes(a.pop + (size_t)c0 * LK, nc * LK, sStage);
     __syncthreads();
-    const bool active = myc < nc;
-    const uint8_t *ip = sInv + q * LT;  // inv[myc][myp][.]
-    uint32_t A[LT];
-#pragma unroll
-    for (int j = 0; j < LT; ++j) {
-      const uint32_t v = active ? ip[j] : 0u;
-      A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
-    }
-    float acc = 0.0f;
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      if constexpr (NT > 1) {
-        __syncthreads();
-        const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
-        load_tile<MODE>(a.T2, a.T1, LT, TPT, t * TR, rows, TR, sT);
-        __syncthreads();
-      }
-#pragma unroll
-      for (int lr = 0; lr < TR; ++lr) {
-        const int l = t * TR + lr;
-        if (l < LT) {
-          float a_l = 0.0f, c2_l = 0.0f;
-          if constexpr (MODE == 1) {
-            a_l = a.lconst[2 * l];
-            c2_l = a.lconst[2 * l + 1];
-          }
-          acc = acc + row_term_exact<LT, MODE>(lds, A, (uint32_t)(lr * ROWB), TPT * 4u, l, a_l,
-                                               c2_l);
-        }
-      }
-    }
-    if (active) sE[q] = acc;
+    build_inverse(sStage, nc * LT, LT, K, sInv);
     __syncthreads();
-    if (q < nc) {
-      tree_sum(sE + q * K, K);
-      a.fit[c0 + q] = a.prelog * sE[q * K];
-    }
-    __syncthreads();
+    const bool active = q / K < nc;
+    float acc;
+    if constexpr (NT == 1)
+      acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst);
+    else
+      acc = lane_sum_tiled<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, a.T2z, a.T1,
+                                              a.lconst);
+    reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0);
   }
 }
 
@@ -126,17 +98,13 @@ __global__ __launch_bounds__(1024) void k_fitness_generic(FitArgs a) {
   const int L = a.L, K = a.K, TP = a.TP;
   const int TR = a.tile_rows;
   const int NT = (L + TR - 1) / TR;
-  const int ROWB = TP * 4 * (MODE == 1 ? 2 : 1);
-  const int CELLB = TR * ROWB;
   float *sT = reinterpret_cast<float *>(smem);
   uint8_t *sInv = smem + a.inv_off;
   float *sE = reinterpret_cast<float *>(smem + a.e_off);
-  const char *lds = reinterpret_cast<const char *>(smem);
+  uint8_t *sStage = smem + a.stage_off;
   const int LK = L * K;
   const int CPR = (int)blockDim.x / K;
   const int q = threadIdx.x;
-  const int myc = q / K;
-  const int myp = q - myc * K;
   const int rounds = (a.n + CPR - 1) / CPR;
 
   if (NT == 1) {
@@ -146,44 +114,14 @@ __global__ __launch_bounds__(1024) void k_fitness_generic(FitArgs a) {
   for (int r = blockIdx.x; r < rounds; r += gridDim.x) {
     const int c0 = r * CPR;
     const int nc = min(CPR, a.n - c0);
-    build_inverse(a.pop + (size_t)c0 * LK, nc * LK, L, K, sInv);
+    copy_bytes(a.pop + (size_t)c0 * LK, nc * LK, sStage);
     __syncthreads();
-    const bool active = myc < nc;
-    const uint8_t *ip = sInv + q * L;  // inv[myc][myp][.]
-    uint32_t A[LMAX];
-#pragma unroll
-    for (int j = 0; j < LMAX; ++j) {
-      uint32_t v = 0u;
-      if (active && j < L) v = ip[j];
-      A[j] = (uint32_t)(j * CELLB) + (v & (uint32_t)(TP - 1)) * 4u;
-    }
-    float acc = 0.0f;
-    for (int t = 0; t < NT; ++t) {
-      const int l0 = t * TR;
-      const int rows = min(TR, L - l0);
-      if (NT > 1) {
-        __syncthreads();
-        load_tile<MODE>(a.T2, a.T1, L, TP, l0, rows, TR, sT);
-        __syncthreads();
-      }
-      for (int lr = 0; lr < rows; ++lr) {
-        const int l = l0 + lr;
-        float a_l = 0.0f, c2_l = 0.0f;
-        if (MODE == 1) {
-          a_l = a.lconst[2 * l];
-          c2_l = a.lconst[2 * l + 1];
-        }
-        acc = acc + row_term_generic<LMAX, MODE>(lds, A, (uint32_t)(lr * ROWB), (uint32_t)TP * 4u,
-                                                 L, l, a_l, c2_l);
-      }
-    }
-    if (active) sE[q] = acc;
+    build_inverse(sStage, nc * L, L, K, sInv);
     __syncthreads();
-    if (q < nc) {
-      tree_sum(sE + q * K, K);
-      a.fit[c0 + q] = a.prelog * sE[q * K];
-    }
-    __syncthreads();
+    const bool active = q / K < nc;
+    const float acc = lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, a.T2,
+                                                   a.T1, a.lconst);
+    reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0);
   }
 }
 
@@ -262,7 +200,7 @@ hipError_t run_generic(const FitArgs &a0, int block, const DeviceInfo &dev, int 
   const int inv = (block * a.L + 15) / 16 * 16;
   const int eb = block * 4;
   const int row_bytes = a.L * a.TP * 4 * (MODE == 1 ? 2 : 1);
-  const int budget = kLdsBytes - inv - eb - 256;
+  const int budget = kLdsBytes - 2 * inv - eb - 256;
   int max_rows = budget / row_bytes;
   if (max_rows < 1) return hipErrorInvalidValue;
   const int tiles = (a.L + max_rows - 1) / max_rows;
@@ -270,7 +208,8 @@ hipError_t run_generic(const FitArgs &a0, int block, const DeviceInfo &dev, int 
   a.tile_rows = tr;
   a.inv_off = tr * row_bytes;
   a.e_off = a.inv_off + inv;
-  const int total = a.e_off + eb;
+  a.stage_off = a.e_off + eb;
+  const int total = a.stage_off + inv;
   const int cpr = block / a.K;
   const int rounds = (a.n + cpr - 1) / cpr;
   int grid = dev.cus * (kLdsBytes / total < 1 ? 1 : kLdsBytes / total);
@@ -305,6 +244,8 @@ hipError_t launch_fitness(const DevProblem &p, const uint8_t *pop, int n, float 
   FitArgs a{};
   a.T2 = p.T2;
   a.T1 = p.T1;
+  a.T2z = p.T2z;
+  a.Town = p.Town;
   a.lconst = p.lconst;
   a.pop = pop;
   a.fit = fit;

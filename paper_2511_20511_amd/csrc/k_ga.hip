@@ -20,64 +20,33 @@ struct GaArgs {
   float *trace;  // may be null: trace[gen] = best fitness of the input
   int L, K, N;
   uint32_t gen;
+  int cpw;       // children per workgroup
   DevGa ga;
 };
 
+// Workgroup 0 copies the elites; workgroup b >= 1 builds the children of
+// slots E + (b-1)*cpw ... with the whole workgroup (ga_core.h) and writes them.
+// Dynamic LDS: children (cpw*L*K) | mutation flags (cpw*L*K) | 2 ints per child
+// | 64 elite indices.
 __global__ __launch_bounds__(kGaBlock) void k_ga_step(GaArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t sbuf[kGaWaves][kMaxGenes];
-  __shared__ int32_t sidx[kGaWaves][kWave];
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const int task = blockIdx.x * kGaWaves + wave;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int L = a.L, K = a.K, N = a.N, E = a.ga.E;
   const int LK = L * K;
-  const int ntasks = 1 + (N - E);
-  uint8_t *buf = sbuf[wave];
-
-  if (task == 0) {
-    // elites in rank order, plus the best fitness for the trace
-    const int Ek = E < 64 ? (E > 1 ? E : 1) : 0;
-    if (Ek > 0) {
-      top_e_wave(a.fin, N, Ek, sidx[wave], lane);
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      if (a.trace && lane == 0) a.trace[a.gen] = a.fin[sidx[wave][0]];
-      for (int e = 0; e < E; ++e) {
-        const int src = sidx[wave][e];
-        for (int i = lane; i < LK; i += kWave) a.pout[(size_t)e * LK + i] = a.pin[(size_t)src * LK + i];
-        if (a.fout && lane == 0) a.fout[e] = a.fin[src];
-      }
-    } else {
-      // E >= 64: every lane ranks its chromosomes by counting who beats them
-      for (int i = lane; i < N; i += kWave) {
-        const int r = rank_of(a.fin, N, i);
-        if (r == 0 && a.trace) a.trace[a.gen] = a.fin[i];
-        if (r < E) {
-          for (int g = 0; g < LK; ++g) a.pout[(size_t)r * LK + g] = a.pin[(size_t)i * LK + g];
-          if (a.fout) a.fout[r] = a.fin[i];
-        }
-      }
-    }
+  const int cb = (a.cpw * LK + 15) / 16 * 16;
+  uint8_t *sChild = smem;
+  uint8_t *sHits = smem + cb;
+  int32_t *sSel = reinterpret_cast<int32_t *>(smem + 2 * cb);
+  int32_t *sIdx = sSel + 2 * a.cpw;
+  if (blockIdx.x == 0) {
+    copy_elites_block(a.pin, a.fin, N, E, LK, a.pout, a.fout, a.trace, (int)a.gen, sIdx);
+    return;
   }
-  const bool child = task >= 1 && task < ntasks;
-  const int s = E + task - 1;
-  if (child) {
-    const int pair_a = E + ((s - E) & ~1);
-    const bool second = ((s - E) & 1) != 0;
-    const Pairing pr = select_parents(a.fin, N, L, a.ga, a.gen, pair_a, lane);
-    const uint8_t *first = a.pin + (size_t)(second ? pr.p2 : pr.p1) * LK;
-    const uint8_t *rest = a.pin + (size_t)(second ? pr.p1 : pr.p2) * LK;
-    const int cutg = pr.cut * K;
-    for (int i = lane; i < LK; i += kWave) buf[i] = i < cutg ? first[i] : rest[i];
-  }
-  __syncthreads();
-  if (child) {
-    const Stream dec{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)s, a.gen, a.ga.instance_id, kTagMutDecide};
-    const Stream par{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)s, a.gen, a.ga.instance_id, kTagMutPartner};
-    mutate_rows(buf, L, K, dec, par, a.ga.thr_mut, lane);
-  }
-  __syncthreads();
-  if (child)
-    for (int i = lane; i < LK; i += kWave) a.pout[(size_t)s * LK + i] = buf[i];
+  const int s0 = E + ((int)blockIdx.x - 1) * a.cpw;
+  const int nc = min(a.cpw, N - s0);
+  build_children_block(a.pin, a.fin, N, E, L, K, a.ga, a.gen, s0, nc, sChild, sHits, sSel,
+                       (int)blockDim.x);
+  uint8_t *dst = a.pout + (size_t)s0 * LK;
+  for (int i = threadIdx.x; i < nc * LK; i += blockDim.x) dst[i] = sChild[i];
 }
 
 struct InitArgs {
@@ -87,43 +56,84 @@ struct InitArgs {
   DevGa ga;
 };
 
+// Individual n of the initial population, built by one wave in `buf`.
+__device__ __forceinline__ void init_individual(const InitArgs &a, int n, uint8_t *buf, int lane) {
+  const int L = a.L, K = a.K, LK = L * K;
+  if (n < a.ga.n_km) {
+    for (int i = lane; i < LK; i += kWave) buf[i] = a.seed[i];
+    wave_sync();
+    if (n >= 1) {
+      const Stream dec{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)n, kInitGeneration,
+                       a.ga.instance_id, kTagInitDecide};
+      const Stream par{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)n, kInitGeneration,
+                       a.ga.instance_id, kTagInitPartner};
+      mutate_rows(buf, L, K, dec, par, a.ga.thr_init, lane);
+    }
+  } else {
+    const Stream shf{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)n, kInitGeneration, a.ga.instance_id,
+                     kTagInitShuffle};
+    shuffle_rows(buf, L, K, shf, lane);
+  }
+  wave_sync();
+  for (int i = lane; i < LK; i += kWave) a.pop[(size_t)n * LK + i] = buf[i];
+}
+
 __global__ __launch_bounds__(kGaBlock) void k_init_pop(InitArgs a) {
   __shared__ __attribute__((aligned(16))) uint8_t sbuf[kGaWaves][kMaxGenes];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int n = blockIdx.x * kGaWaves + wave;
-  const int L = a.L, K = a.K, LK = L * K;
-  uint8_t *buf = sbuf[wave];
-  const bool active = n < a.N;
-  const bool from_seed = active && n < a.ga.n_km;
-  if (from_seed)
-    for (int i = lane; i < LK; i += kWave) buf[i] = a.seed[i];
-  __syncthreads();
-  if (active) {
-    if (from_seed) {
-      if (n >= 1) {
-        const Stream dec{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)n, kInitGeneration,
-                         a.ga.instance_id, kTagInitDecide};
-        const Stream par{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)n, kInitGeneration,
-                         a.ga.instance_id, kTagInitPartner};
-        mutate_rows(buf, L, K, dec, par, a.ga.thr_init, lane);
-      }
-    } else {
-      const Stream shf{a.ga.seed_lo, a.ga.seed_hi, (uint32_t)n, kInitGeneration,
-                       a.ga.instance_id, kTagInitShuffle};
-      shuffle_rows(buf, L, K, shf, lane);
-    }
+  if (n < a.N) init_individual(a, n, sbuf[wave], lane);
+}
+
+// blockIdx.y = instance; individuals beyond an instance's N do nothing.
+__global__ __launch_bounds__(kGaBlock) void k_init_batch(const GenInst *insts) {
+  __shared__ __attribute__((aligned(16))) uint8_t sbuf[kGaWaves][kMaxGenes];
+  const GenInst &I = insts[blockIdx.y];
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int n = blockIdx.x * kGaWaves + wave;
+  if (n < I.N) {
+    InitArgs a{I.seed, I.pop[0], I.L, I.K, I.N, I.ga};
+    init_individual(a, n, sbuf[wave], lane);
   }
-  __syncthreads();
-  if (active)
-    for (int i = lane; i < LK; i += kWave) a.pop[(size_t)n * LK + i] = buf[i];
+}
+
+// One wave per instance: best of its final population, which also closes
+// its trace.
+__global__ __launch_bounds__(kWave) void k_best_batch(const GenInst *insts, int gen) {
+  __shared__ int32_t idx[1];
+  const GenInst &I = insts[blockIdx.x];
+  const int G = gen < 0 ? I.G : (gen < I.G ? gen : I.G);
+  const float *fit = I.fit[G & 1];
+  top_e_wave(fit, I.N, 1, idx, threadIdx.x);
+  wave_sync();
+  if (threadIdx.x == 0) {
+    *I.best_idx = idx[0];
+    *I.best_fit = fit[idx[0]];
+    I.trace[G] = fit[idx[0]];
+  }
+  const int LK = I.L * I.K;
+  const uint8_t *src = I.pop[G & 1] + (size_t)idx[0] * LK;
+  for (int i = threadIdx.x; i < LK; i += kWave) I.best_out[i] = src[i];
+}
+
+hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_batch, dim3((maxN + kGaWaves - 1) / kGaWaves, ninst), dim3(kGaBlock),
+                     0, s, insts);
+  return hipGetLastError();
+}
+
+hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_best_batch, dim3(ninst), dim3(kWave), 0, s, insts, gen);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kWave) void k_best(const float *__restrict__ fit, int N,
                                                 int32_t *best_idx, float *best_fit) {
   __shared__ int32_t idx[1];
   top_e_wave(fit, N, 1, idx, threadIdx.x);
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  wave_sync();
   if (threadIdx.x == 0) {
     *best_idx = idx[0];
     *best_fit = fit[idx[0]];
@@ -133,10 +143,19 @@ __global__ __launch_bounds__(kWave) void k_best(const float *__restrict__ fit, i
 hipError_t launch_ga_step(const DevProblem &p, const DevGa &ga, uint32_t gen, const uint8_t *pin,
                           const float *fin, uint8_t *pout, float *fit_out, float *trace,
                           hipStream_t s) {
-  GaArgs a{pin, fin, pout, fit_out, trace, p.L, p.K, ga.N, gen, ga};
-  const int ntasks = 1 + (ga.N - ga.E);
-  const int grid = (ntasks + kGaWaves - 1) / kGaWaves;
-  hipLaunchKernelGGL(k_ga_step, dim3(grid), dim3(kGaBlock), 0, s, a);
+  const int LK = p.L * p.K;
+  const int nchild = ga.N - ga.E;
+  // enough workgroups to spread the children (and their Philox work) over the
+  // GPU, at most 24 KiB of children per workgroup
+  int cpw = (nchild + 255) / 256;
+  const int cap = 24576 / LK;
+  cpw = cpw > cap ? cap : cpw;
+  cpw = cpw < 1 ? 1 : (cpw > 64 ? 64 : cpw);
+  GaArgs a{pin, fin, pout, fit_out, trace, p.L, p.K, ga.N, gen, cpw, ga};
+  const int grid = 1 + (nchild + cpw - 1) / cpw;
+  const int cb = (cpw * LK + 15) / 16 * 16;
+  const size_t lds = 2 * (size_t)cb + 8 * (size_t)cpw + 256;
+  hipLaunchKernelGGL(k_ga_step, dim3(grid), dim3(kGaBlock), lds, s, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,81 @@
+// k_gen.hip -- runtime-L generation kernels and the dispatch of a class of
+// instances to the unrolled (k_gen_L*.hip) or runtime-L variant.
+#include "gen_core.h"
+
+namespace pa {
+
+namespace {
+
+template <int LMAX, int MODE>
+hipError_t gen_launch_generic(const GenInst *insts, const GenClass &c, int gen, hipStream_t s) {
+  const int n = gen < 0 ? c.neval : c.ntasks;
+  if (n <= 0) return hipSuccess;
+  const int block = c.block;
+  const int L = c.L, TP = c.TP;
+  const int child = (block * L + 15) / 16 * 16;
+  const int eb = block * 4, idxb = 256, selb = block * 8;
+  const int row_bytes = L * TP * 4 * (MODE == 1 ? 2 : 1);
+  const int budget = kLdsBytes - 2 * child - eb - idxb - selb - 256;
+  const int max_rows = budget / row_bytes;
+  if (max_rows < 1) return hipErrorInvalidValue;
+  const int tiles = (L + max_rows - 1) / max_rows;
+  GenGenericPlan pl;
+  pl.tile_rows = (L + tiles - 1) / tiles;
+  pl.child_off = pl.tile_rows * row_bytes;
+  pl.inv_off = pl.child_off + child;
+  pl.e_off = pl.inv_off + child;
+  pl.idx_off = pl.e_off + eb;
+  pl.sel_off = pl.idx_off + idxb;
+  const int total = pl.sel_off + selb;
+  auto kern = k_gen_generic<LMAX, MODE>;
+  static bool attr = false;
+  if (!attr) {
+    gen_allow_lds(reinterpret_cast<const void *>(kern), kLdsBytes);
+    attr = true;
+  }
+  const int grid = c.grid < 1 ? 1 : (c.grid > n ? n : c.grid);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), total, s, gen_args(insts, c, gen, grid), pl);
+  return hipGetLastError();
+}
+
+template <int MODE>
+hipError_t gen_generic_mode(const GenInst *insts, const GenClass &c, int gen, hipStream_t s) {
+  if (c.L <= 8) return gen_launch_generic<8, MODE>(insts, c, gen, s);
+  if (c.L <= 16) return gen_launch_generic<16, MODE>(insts, c, gen, s);
+  if (c.L <= 32) return gen_launch_generic<32, MODE>(insts, c, gen, s);
+  return gen_launch_generic<64, MODE>(insts, c, gen, s);
+}
+
+}  // namespace
+
+hipError_t gen_dispatch_generic(const GenInst *insts, const GenClass &c, int gen, hipStream_t s) {
+  return c.mode == 1 ? gen_generic_mode<1>(insts, c, gen, s) : gen_generic_mode<0>(insts, c, gen, s);
+}
+
+int gen_default_block(int L, int TP, int mode) {
+  const bool exact = (L == 7 || L == 19 || L == 37) && TP <= 32;
+  const long table = (long)L * L * TP * 4 * (mode == 1 ? 2 : 1);
+  if (!exact) return 256;
+  return table <= 40 * 1024 ? 256 : 512;
+}
+
+int gen_children_per_task(int L, int K, int TP, int mode, int block) {
+  (void)L;
+  (void)TP;
+  (void)mode;
+  return block / K;
+}
+
+hipError_t launch_gen(const GenInst *insts, const GenClass &c, int gen, const DeviceInfo &dev,
+                      hipStream_t s) {
+  (void)dev;
+  bool handled = false;
+  hipError_t e = hipSuccess;
+  if (c.L == 7) e = gen_dispatch_L7(insts, c, gen, s, &handled);
+  else if (c.L == 19) e = gen_dispatch_L19(insts, c, gen, s, &handled);
+  else if (c.L == 37) e = gen_dispatch_L37(insts, c, gen, s, &handled);
+  if (handled) return e;
+  return gen_dispatch_generic(insts, c, gen, s);
+}
+
+}  // namespace pa

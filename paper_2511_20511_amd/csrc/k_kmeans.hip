@@ -42,7 +42,7 @@ struct KmArgs {
   int32_t *iters_out;
 };
 
-__global__ __launch_bounds__(kKmBlock) void k_kmeans_seed(KmArgs a) {
+__device__ __forceinline__ void kmeans_body(const KmArgs &a) {
   __shared__ int32_t qx[kMaxGenes], qy[kMaxGenes];
   __shared__ int64_t mind[kMaxGenes];
   __shared__ uint8_t lab[kMaxGenes];
@@ -155,6 +155,22 @@ __global__ __launch_bounds__(kKmBlock) void k_kmeans_seed(KmArgs a) {
   }
   for (int u = tid; u < n; u += kKmBlock) a.labels_out[u] = lab[u];
   if (tid == 0) *a.iters_out = it;
+}
+
+__global__ __launch_bounds__(kKmBlock) void k_kmeans_seed(KmArgs a) { kmeans_body(a); }
+
+// One workgroup per instance listed in `which`.
+__global__ __launch_bounds__(kKmBlock) void k_kmeans_batch(const GenInst *insts,
+                                                            const int32_t *which) {
+  const GenInst &I = insts[which[blockIdx.x]];
+  KmArgs a{I.user_xy, I.bs_xy, I.L, I.K, I.seed, I.km_cent, I.km_labels, I.km_iters};
+  kmeans_body(a);
+}
+
+hipError_t launch_kmeans_batch(const GenInst *insts, const int32_t *which, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_kmeans_batch, dim3(n), dim3(kKmBlock), 0, s, insts, which);
+  return hipGetLastError();
 }
 
 hipError_t launch_kmeans_seed(const DevProblem &p, hipStream_t s) {

@@ -18,6 +18,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(const double *__restrict__ 
                                                       int TP, int finite_m, double rho, int M,
                                                       float *__restrict__ T2,
                                                       float *__restrict__ T1,
+                                                      float *__restrict__ T2z,
+                                                      float *__restrict__ Town,
                                                       float *__restrict__ lconst) {
   __shared__ double red[kPrepBlock];
   const int l = blockIdx.x;
@@ -40,7 +42,10 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(const double *__restrict__ 
     double b = 0.0;
     if (p < K) b = ldexp(row[j * K + p], -e);
     const size_t dst = ((size_t)j * L + l) * TP + p;
-    T2[dst] = (float)(b * b);
+    const float sq = (float)(b * b);
+    T2[dst] = sq;
+    T2z[dst] = j == l ? 0.0f : sq;
+    if (j == l) Town[l * TP + p] = sq;
     if (finite_m) T1[dst] = (float)b;
   }
   if (finite_m && threadIdx.x == 0) {
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(const double *__restrict__ 
 hipError_t launch_prep(const DevProblem &p, int M, double rho, hipStream_t s) {
   const int finite_m = p.se_mode == 1;
   hipLaunchKernelGGL(k_prep, dim3(p.L), dim3(kPrepBlock), 0, s, p.beta, p.L, p.K, p.TP, finite_m,
-                     rho, M, p.T2, p.T1, p.lconst);
+                     rho, M, p.T2, p.T1, p.T2z, p.Town, p.lconst);
   return hipGetLastError();
 }
 

@@ -100,4 +100,52 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
   return v;
 }
 
+// Byte ranges moved with aligned 32-bit loads, up to kCopyBatch loads in
+// flight per thread.  A range [src, src + n) is covered by the aligned words
+// w = 0 .. nwords-1 starting at src rounded down to 4 bytes; each such word
+// holds at least one byte of the range, so it lies in a page the range
+// touches (no fault even when the range ends at an allocation's end).
+constexpr int kCopyBatch = 8;
+
+struct ByteRange {
+  const uint8_t *src;
+  int n;
+  __device__ __forceinline__ int words() const {
+    return ((int)((uintptr_t)src & 3u) + n + 3) >> 2;
+  }
+  __device__ __forceinline__ uint32_t load(int w) const {
+    const uint32_t *base = reinterpret_cast<const uint32_t *>((uintptr_t)src & ~(uintptr_t)3);
+    return base[w];
+  }
+  // byte offset in the range of byte b of word w (may fall outside [0, n))
+  __device__ __forceinline__ int pos(int w, int b) const {
+    return w * 4 + b - (int)((uintptr_t)src & 3u);
+  }
+};
+
+// Copies [src, src + n) to dst (LDS or global, any alignment) with the whole
+// workgroup.
+__device__ __forceinline__ void copy_bytes(const uint8_t *src, int n, uint8_t *dst) {
+  if (n <= 0) return;
+  const ByteRange r{src, n};
+  const int nw = r.words();
+  const int step = (int)blockDim.x;
+  for (int w0 = threadIdx.x; w0 < nw; w0 += kCopyBatch * step) {
+    uint32_t v[kCopyBatch];
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; ++u) v[u] = r.load(min(w0 + u * step, nw - 1));
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; ++u) {
+      const int w = w0 + u * step;
+      if (w < nw) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int g = r.pos(w, b);
+          if (g >= 0 && g < n) dst[g] = (uint8_t)(v[u] >> (8 * b));
+        }
+      }
+    }
+  }
+}
+
 }  // namespace pa

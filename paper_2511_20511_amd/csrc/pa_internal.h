@@ -27,6 +27,8 @@ struct DevProblem {
   double *beta = nullptr;    // [L][L][K] FP64 as given
   float *T2 = nullptr;       // [L(cell j)][L(BS l)][TP] normalised beta squared (FP32)
   float *T1 = nullptr;       // same layout, normalised beta (finite-M only)
+  float *T2z = nullptr;      // T2 with the own-cell entries (j == l) zeroed
+  float *Town = nullptr;     // [L(BS l)][TP] own-cell squares T2[l][l][.]
   float *lconst = nullptr;   // [L][2]: tau*rho_l and (1 + rho_l*B_l)/(M tau rho_l^2)
   double *user_xy = nullptr; // [L][K][2] or null
   double *bs_xy = nullptr;   // [L][2] or null
@@ -54,6 +56,46 @@ struct DeviceInfo {
   size_t lds_per_block = 163840;
 };
 
+// One instance as the batched kernels see it (an array of these lives in
+// device memory).  Populations and fitness are double-buffered: generation g
+// reads buffer g & 1 and writes buffer 1 - (g & 1); the initial population
+// and its fitness live in buffer 0.
+struct GenInst {
+  const float *T2, *T1, *lconst, *T2z, *Town;
+  uint8_t *pop[2];
+  float *fit[2];
+  float *trace;        // [G + 1]
+  int32_t *best_idx;   // [1]
+  float *best_fit;     // [1]
+  uint8_t *best_out;   // [L*K]: copy of the best chromosome of the final population
+  const double *user_xy, *bs_xy;
+  uint8_t *seed;
+  int32_t *km_cent, *km_labels, *km_iters;
+  int L, K, TP, N, E, G;
+  float prelog;
+  int se_mode;
+  DevGa ga;
+};
+
+enum : int32_t { kTaskElite = 0, kTaskChild = 1, kTaskEval = 2 };
+
+// A unit of work of one generation launch: the elites of an instance, or the
+// children (or, before the first generation, the fitness) of slots [s0, s1).
+struct GenTask {
+  int32_t inst, kind, s0, s1;
+};
+
+// A group of instances sharing (L, TP, SE mode) that one kernel variant runs.
+struct GenClass {
+  int L = 0, TP = 0, mode = 0;
+  int block = 0;                  // threads per workgroup of the generation kernel
+  int grid = 0;                   // workgroups
+  const GenTask *tasks = nullptr; // device
+  int ntasks = 0;
+  const GenTask *eval_tasks = nullptr;  // device: initial-population fitness
+  int neval = 0;
+};
+
 // ---- launchers (return hipSuccess or the first HIP error) ----------------
 hipError_t launch_prep(const DevProblem &p, int M, double rho, hipStream_t s);
 hipError_t launch_fitness(const DevProblem &p, const uint8_t *pop, int n, float *fit,
@@ -69,5 +111,19 @@ hipError_t launch_ga_step(const DevProblem &p, const DevGa &ga, uint32_t gen, co
 // Best chromosome of a population: writes best index (int32) and fitness.
 hipError_t launch_best(const float *fit, int N, int32_t *best_idx, float *best_fit,
                        hipStream_t s);
+
+// ---- batched, descriptor-driven launchers ------------------------------
+// Children per task (= chromosomes per LDS round) of the generation kernel
+// for a class, and its workgroup size.
+int gen_children_per_task(int L, int K, int TP, int mode, int block);
+int gen_default_block(int L, int TP, int mode);
+hipError_t launch_kmeans_batch(const GenInst *insts, const int32_t *which, int n, hipStream_t s);
+hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStream_t s);
+// gen = -1: fitness of the initial populations (the class's eval tasks).
+hipError_t launch_gen(const GenInst *insts, const GenClass &c, int gen, const DeviceInfo &dev,
+                      hipStream_t s);
+// Best of each instance's population after generation `gen` (or after its
+// last generation when gen < 0); closes the trace at that generation.
+hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s);
 
 }  // namespace pa

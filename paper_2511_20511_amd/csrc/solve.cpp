@@ -1,0 +1,427 @@
+// solve.cpp -- whole solves of one instance (pa_solve) or many
+// (pa_solve_batch): a plan holds the device descriptors, task lists and
+// double-buffered populations of its instances; the whole solve (K-means
+// seeding, initial population and fitness, every generation, best of the
+// last population) is captured once into a hipGraph and replayed, so a solve
+// is one graph launch plus one copy of the results.
+#include <algorithm>
+#include <cstring>
+
+#include "pa_host.h"
+
+namespace pa {
+
+struct PlanClass {
+  GenClass c;
+  GenTask *d_tasks = nullptr, *d_evals = nullptr;
+};
+
+struct SolvePlan {
+  int device = 0;
+  std::vector<pa_instance *> insts;
+  std::vector<pa_ga_params> params;
+  std::vector<PlanClass> classes;
+  std::vector<void *> owned;  // device allocations
+  GenInst *d_insts = nullptr;
+  int32_t *d_which = nullptr;
+  int nwhich = 0;
+  int Gmax = 0, maxN = 0;
+  int32_t *d_best_idx = nullptr;
+  float *d_best_fit = nullptr;
+  float *d_trace = nullptr;      // [n][Gmax + 1]
+  uint8_t *d_best = nullptr;     // concatenated best chromosomes
+  std::vector<size_t> best_off;  // offsets into d_best
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  int cur_gen = -1;  // stepwise solve: generations done (-1: not started)
+  std::vector<int32_t> h_idx;
+  std::vector<float> h_fit, h_trace;
+  std::vector<uint8_t> h_best;
+};
+
+void free_plan(SolvePlan *plan) {
+  if (!plan) return;
+  (void)hipSetDevice(plan->device);
+  if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+  if (plan->graph) (void)hipGraphDestroy(plan->graph);
+  if (plan->ev0) (void)hipEventDestroy(plan->ev0);
+  if (plan->ev1) (void)hipEventDestroy(plan->ev1);
+  for (void *p : plan->owned)
+    if (p) (void)hipFree(p);
+  delete plan;
+}
+
+namespace {
+
+template <class T>
+hipError_t alloc(SolvePlan *pl, T **p, size_t count) {
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * (count ? count : 1));
+  if (e == hipSuccess) pl->owned.push_back(*p);
+  return e;
+}
+
+#define PTRY(call, what)                             \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_error(e_, what); \
+  } while (0)
+
+bool exact_variant(int L, int TP) { return (L == 7 || L == 19 || L == 37) && TP <= 32; }
+
+// LDS bytes of the generation kernel (mirrors its compile-time plan).
+int gen_lds_bytes(int L, int TP, int mode, int block) {
+  const int child = (block * L + 15) / 16 * 16;
+  const int extra = 2 * child + block * 4 + 256 + L * TP * 4 + block * 8;
+  const int row = L * TP * 4 * (mode == 1 ? 2 : 1);
+  const int budget = 163840 - extra - 256;
+  const int max_rows = budget / row;
+  if (max_rows < 1) return -1;
+  const int tiles = (L + max_rows - 1) / max_rows;
+  const int tr = (L + tiles - 1) / tiles;
+  return tr * row + extra;
+}
+
+bool tiled(int L, int TP, int mode, int block) {
+  const int child = (block * L + 15) / 16 * 16;
+  const int extra = 2 * child + block * 4 + 256 + L * TP * 4 + block * 8;
+  const int row = L * TP * 4 * (mode == 1 ? 2 : 1);
+  return (163840 - extra - 256) / row < L;
+}
+
+struct ClassKey {
+  int L, TP, mode;
+  bool operator<(const ClassKey &o) const {
+    return L != o.L ? L < o.L : TP != o.TP ? TP < o.TP : mode < o.mode;
+  }
+  bool operator==(const ClassKey &o) const { return L == o.L && TP == o.TP && mode == o.mode; }
+};
+
+// Tasks of a class when each task holds ceil(block / K / div) children.
+int count_tasks(const std::vector<int> &members, const std::vector<pa_instance *> &insts,
+                const std::vector<pa_ga_params> &params, int block, int div = 1) {
+  int n = 0;
+  for (int i : members) {
+    const int cpr = std::max(1, (block / insts[i]->p.K + div - 1) / div);
+    n += 1 + (params[i].pop - params[i].elite + cpr - 1) / cpr;
+  }
+  return n;
+}
+
+// Launch shape of a class: threads per workgroup and children per task
+// (<= block / K).  Large tables keep 512 threads and full tasks (one tile load
+// serves 16-32 chromosomes).  When full tasks would leave CUs idle (few,
+// small instances) the tasks shrink so every CU gets one, but the workgroup
+// keeps 256 threads so the GA phases of a task still run on four waves.
+struct Shape {
+  int block, cpt_div;  // cpt = ceil(block / K / cpt_div)
+};
+
+Shape choose_shape(const ClassKey &k, const std::vector<int> &members,
+                   const std::vector<pa_instance *> &insts, const std::vector<pa_ga_params> &params,
+                   int cus) {
+  int maxK = 0;
+  for (int i : members) maxK = std::max(maxK, insts[i]->p.K);
+  if (!exact_variant(k.L, k.TP)) return {std::max(256, (maxK + 63) / 64 * 64), 1};
+  if (tiled(k.L, k.TP, k.mode, 512)) return {512, 1};
+  if (count_tasks(members, insts, params, 512) >= cus) return {512, 1};
+  if (count_tasks(members, insts, params, 256) >= cus) return {256, 1};
+  int div = 1;
+  while (div < 256 / maxK && count_tasks(members, insts, params, 256, div) < cus) div *= 2;
+  return {256, div};
+}
+
+pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
+                     const pa_ga_params *params, SolvePlan **out) {
+  SolvePlan *pl = new (std::nothrow) SolvePlan;
+  if (!pl) return set_error(PA_ENOMEM, "host allocation failed");
+  std::unique_ptr<SolvePlan, void (*)(SolvePlan *)> guard(pl, free_plan);
+  pl->device = ctx->device;
+  pl->insts.assign(insts, insts + n);
+  pl->params.assign(params, params + n);
+  for (int i = 0; i < n; ++i) {
+    pl->Gmax = std::max(pl->Gmax, params[i].gens);
+    pl->maxN = std::max(pl->maxN, params[i].pop);
+  }
+  const int TG = pl->Gmax + 1;
+  PTRY(alloc(pl, &pl->d_best_idx, n), "hipMalloc(plan)");
+  PTRY(alloc(pl, &pl->d_best_fit, n), "hipMalloc(plan)");
+  PTRY(alloc(pl, &pl->d_trace, (size_t)n * TG), "hipMalloc(plan)");
+  size_t best_total = 0;
+  for (int i = 0; i < n; ++i) {
+    pl->best_off.push_back(best_total);
+    best_total += (size_t)insts[i]->p.L * insts[i]->p.K;
+  }
+  PTRY(alloc(pl, &pl->d_best, best_total), "hipMalloc(plan)");
+  std::vector<GenInst> hi(n);
+  std::vector<int32_t> which;
+  for (int i = 0; i < n; ++i) {
+    const DevProblem &p = insts[i]->p;
+    const pa_ga_params &g = params[i];
+    GenInst &I = hi[i];
+    std::memset(&I, 0, sizeof I);
+    const size_t LK = (size_t)p.L * p.K;
+    for (int b = 0; b < 2; ++b) {
+      PTRY(alloc(pl, &I.pop[b], LK * g.pop), "hipMalloc(population)");
+      PTRY(alloc(pl, &I.fit[b], (size_t)g.pop), "hipMalloc(fitness)");
+    }
+    I.T2 = p.T2;
+    I.T1 = p.T1;
+    I.T2z = p.T2z;
+    I.Town = p.Town;
+    I.lconst = p.lconst;
+    I.trace = pl->d_trace + (size_t)i * TG;
+    I.best_idx = pl->d_best_idx + i;
+    I.best_fit = pl->d_best_fit + i;
+    I.best_out = pl->d_best + pl->best_off[i];
+    I.user_xy = p.user_xy;
+    I.bs_xy = p.bs_xy;
+    I.seed = p.seed;
+    I.km_cent = p.km_cent;
+    I.km_labels = p.km_labels;
+    I.km_iters = p.km_iters;
+    I.L = p.L;
+    I.K = p.K;
+    I.TP = p.TP;
+    I.N = g.pop;
+    I.E = g.elite;
+    I.G = g.gens;
+    I.prelog = p.prelog;
+    I.se_mode = p.se_mode;
+    I.ga = ga_from_params(&g);
+    if (I.ga.n_km > 0) which.push_back(i);
+  }
+  PTRY(alloc(pl, &pl->d_insts, (size_t)n), "hipMalloc(plan)");
+  PTRY(hipMemcpy(pl->d_insts, hi.data(), sizeof(GenInst) * n, hipMemcpyHostToDevice), "upload");
+  pl->nwhich = (int)which.size();
+  if (pl->nwhich) {
+    PTRY(alloc(pl, &pl->d_which, which.size()), "hipMalloc(plan)");
+    PTRY(hipMemcpy(pl->d_which, which.data(), sizeof(int32_t) * which.size(),
+                   hipMemcpyHostToDevice),
+         "upload");
+  }
+  // classes of (L, TP, mode), members in input order
+  std::vector<std::pair<ClassKey, std::vector<int>>> groups;
+  for (int i = 0; i < n; ++i) {
+    const ClassKey key{hi[i].L, hi[i].TP, hi[i].se_mode};
+    auto it = std::find_if(groups.begin(), groups.end(),
+                           [&](const std::pair<ClassKey, std::vector<int>> &g) { return g.first == key; });
+    if (it == groups.end()) groups.push_back({key, {i}});
+    else it->second.push_back(i);
+  }
+  const int cus = ctx->info.cus;
+  for (auto &grp : groups) {
+    const ClassKey &key = grp.first;
+    PlanClass pc;
+    pc.c.L = key.L;
+    pc.c.TP = key.TP;
+    pc.c.mode = key.mode;
+    const Shape sh = choose_shape(key, grp.second, pl->insts, pl->params, cus);
+    pc.c.block = sh.block;
+    std::vector<GenTask> tasks, evals;
+    for (int i : grp.second) {
+      const int K = hi[i].K, N = hi[i].N, E = hi[i].E;
+      const int cpr = std::max(1, (pc.c.block / K + sh.cpt_div - 1) / sh.cpt_div);
+      tasks.push_back(GenTask{i, kTaskElite, 0, E});
+      for (int s = E; s < N; s += cpr) tasks.push_back(GenTask{i, kTaskChild, s, std::min(N, s + cpr)});
+      for (int s = 0; s < N; s += cpr) evals.push_back(GenTask{i, kTaskEval, s, std::min(N, s + cpr)});
+    }
+    const int lds = gen_lds_bytes(key.L, key.TP, key.mode, pc.c.block);
+    if (lds < 0) return set_error(PA_EUNSUPPORTED, "table of L=%d does not fit LDS", key.L);
+    int per_cu = 163840 / lds;
+    per_cu = std::max(1, std::min(per_cu, 2048 / pc.c.block));
+    pc.c.grid = std::min((int)tasks.size(), cus * per_cu);
+    pc.c.ntasks = (int)tasks.size();
+    pc.c.neval = (int)evals.size();
+    PTRY(alloc(pl, &pc.d_tasks, tasks.size()), "hipMalloc(tasks)");
+    PTRY(alloc(pl, &pc.d_evals, evals.size()), "hipMalloc(tasks)");
+    PTRY(hipMemcpy(pc.d_tasks, tasks.data(), sizeof(GenTask) * tasks.size(), hipMemcpyHostToDevice),
+         "upload");
+    PTRY(hipMemcpy(pc.d_evals, evals.data(), sizeof(GenTask) * evals.size(), hipMemcpyHostToDevice),
+         "upload");
+    pc.c.tasks = pc.d_tasks;
+    pc.c.eval_tasks = pc.d_evals;
+    pl->classes.push_back(pc);
+  }
+  // capture the whole solve
+  hipStream_t cs = ctx->stream;
+  PTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  hipError_t e = launch_kmeans_batch(pl->d_insts, pl->d_which, pl->nwhich, cs);
+  if (e == hipSuccess) e = launch_init_batch(pl->d_insts, n, pl->maxN, cs);
+  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess; ++c)
+    e = launch_gen(pl->d_insts, pl->classes[c].c, -1, ctx->info, cs);
+  for (int g = 0; g < pl->Gmax && e == hipSuccess; ++g)
+    for (size_t c = 0; c < pl->classes.size() && e == hipSuccess; ++c)
+      e = launch_gen(pl->d_insts, pl->classes[c].c, g, ctx->info, cs);
+  if (e == hipSuccess) e = launch_best_batch(pl->d_insts, n, -1, cs);
+  hipGraph_t graph = nullptr;
+  hipError_t e2 = hipStreamEndCapture(cs, &graph);
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return hip_error(e, "capturing the solve");
+  }
+  PTRY(e2, "hipStreamEndCapture");
+  pl->graph = graph;
+  PTRY(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  PTRY(hipEventCreate(&pl->ev0), "hipEventCreate");
+  PTRY(hipEventCreate(&pl->ev1), "hipEventCreate");
+  pl->h_idx.resize(n);
+  pl->h_fit.resize(n);
+  pl->h_trace.resize((size_t)n * TG);
+  pl->h_best.resize(best_total);
+  *out = guard.release();
+  return PA_OK;
+}
+
+// Copies best index / fitness / trace / chromosome of every instance to the
+// host (after the work enqueued on s) and fills results; `gens_done` limits
+// the trace (< 0: each instance's full trace).
+pa_status copy_results(SolvePlan *pl, hipStream_t s, pa_result *results, int gens_done);
+
+pa_status run_plan(SolvePlan *pl, hipStream_t s, pa_result *results) {
+  PTRY(hipEventRecord(pl->ev0, s), "hipEventRecord");
+  PTRY(hipGraphLaunch(pl->exec, s), "hipGraphLaunch");
+  PTRY(hipEventRecord(pl->ev1, s), "hipEventRecord");
+  return copy_results(pl, s, results, -1);
+}
+
+pa_status copy_results(SolvePlan *pl, hipStream_t s, pa_result *results, int gens_done) {
+  const int n = (int)pl->insts.size();
+  const int TG = pl->Gmax + 1;
+  PTRY(hipMemcpyAsync(pl->h_idx.data(), pl->d_best_idx, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s),
+       "copy results");
+  PTRY(hipMemcpyAsync(pl->h_fit.data(), pl->d_best_fit, sizeof(float) * n, hipMemcpyDeviceToHost, s),
+       "copy results");
+  PTRY(hipMemcpyAsync(pl->h_trace.data(), pl->d_trace, sizeof(float) * n * TG, hipMemcpyDeviceToHost,
+                      s),
+       "copy results");
+  PTRY(hipMemcpyAsync(pl->h_best.data(), pl->d_best, pl->h_best.size(), hipMemcpyDeviceToHost, s),
+       "copy results");
+  PTRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  float ms = 0.0f;
+  PTRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1), "hipEventElapsedTime");
+  for (int i = 0; i < n; ++i) {
+    pa_result &r = results[i];
+    const DevProblem &p = pl->insts[i]->p;
+    const size_t LK = (size_t)p.L * p.K;
+    if (r.best) std::memcpy(r.best, pl->h_best.data() + pl->best_off[i], LK);
+    r.best_fit = pl->h_fit[i];
+    r.best_index = pl->h_idx[i];
+    const int upto = gens_done < 0 ? pl->params[i].gens : std::min(gens_done, pl->params[i].gens);
+    if (r.trace) std::memcpy(r.trace, pl->h_trace.data() + (size_t)i * TG, sizeof(float) * (upto + 1));
+    r.device_ms = ms;
+  }
+  return PA_OK;
+}
+
+bool same_params(const pa_ga_params &a, const pa_ga_params &b) {
+  return a.pop == b.pop && a.gens == b.gens && a.elite == b.elite && a.p_cross == b.p_cross &&
+         a.p_mut == b.p_mut && a.kmeans_frac == b.kmeans_frac && a.p_init == b.p_init &&
+         a.seed == b.seed && a.instance_id == b.instance_id;
+}
+
+bool plan_matches(const SolvePlan *pl, int n, pa_instance *const *insts, const pa_ga_params *params) {
+  if (!pl || (int)pl->insts.size() != n) return false;
+  for (int i = 0; i < n; ++i)
+    if (pl->insts[i] != insts[i] || !same_params(pl->params[i], params[i])) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace pa
+
+using namespace pa;
+
+extern "C" {
+
+pa_status pa_solve(pa_instance *in, const pa_ga_params *g, pa_result *out, void *stream) {
+  if (!in || !out) return set_error(PA_EINVAL, "instance or result is NULL");
+  pa_status st = validate_ga(in, g);
+  if (st != PA_OK) return st;
+  if ((st = use_device(in->ctx)) != PA_OK) return st;
+  if (!plan_matches(in->plan, 1, &in, g)) {
+    free_plan(in->plan);
+    in->plan = nullptr;
+    if ((st = build_plan(in->ctx, 1, &in, g, &in->plan)) != PA_OK) return st;
+  }
+  return run_plan(in->plan, (hipStream_t)stream, out);
+}
+
+pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
+                         const pa_ga_params *params, pa_result *results, void *stream) {
+  if (!ctx || !insts || !params || !results) return set_error(PA_EINVAL, "NULL argument");
+  if (n < 1) return set_error(PA_EINVAL, "n=%d must be >= 1", n);
+  for (int i = 0; i < n; ++i) {
+    if (!insts[i]) return set_error(PA_EINVAL, "instance %d is NULL", i);
+    if (insts[i]->ctx != ctx) return set_error(PA_EINVAL, "instance %d belongs to another context", i);
+    for (int k = 0; k < i; ++k)
+      if (insts[k] == insts[i]) return set_error(PA_EINVAL, "instance %d appears twice", i);
+    pa_status st = validate_ga(insts[i], &params[i]);
+    if (st != PA_OK) return set_error(st, "instance %d: %s", i, pa_last_error());
+  }
+  pa_status st = use_device(ctx);
+  if (st != PA_OK) return st;
+  if (!plan_matches(ctx->batch_plan, n, insts, params)) {
+    free_plan(ctx->batch_plan);
+    ctx->batch_plan = nullptr;
+    if ((st = build_plan(ctx, n, insts, params, &ctx->batch_plan)) != PA_OK) return st;
+  }
+  return run_plan(ctx->batch_plan, (hipStream_t)stream, results);
+}
+
+pa_status pa_solve_begin(pa_instance *in, const pa_ga_params *g, void *stream) {
+  if (!in) return set_error(PA_EINVAL, "instance is NULL");
+  pa_status st = validate_ga(in, g);
+  if (st != PA_OK) return st;
+  if ((st = use_device(in->ctx)) != PA_OK) return st;
+  if (!plan_matches(in->plan, 1, &in, g)) {
+    free_plan(in->plan);
+    in->plan = nullptr;
+    if ((st = build_plan(in->ctx, 1, &in, g, &in->plan)) != PA_OK) return st;
+  }
+  SolvePlan *pl = in->plan;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_kmeans_batch(pl->d_insts, pl->d_which, pl->nwhich, s);
+  if (e == hipSuccess) e = launch_init_batch(pl->d_insts, 1, pl->maxN, s);
+  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess; ++c)
+    e = launch_gen(pl->d_insts, pl->classes[c].c, -1, in->ctx->info, s);
+  if (e != hipSuccess) return hip_error(e, "pa_solve_begin");
+  pl->cur_gen = 0;
+  return PA_OK;
+}
+
+pa_status pa_solve_next(pa_instance *in, int32_t ngens, void *stream) {
+  if (!in) return set_error(PA_EINVAL, "instance is NULL");
+  SolvePlan *pl = in->plan;
+  if (!pl || pl->cur_gen < 0) return set_error(PA_EINVAL, "pa_solve_begin was not called");
+  if (ngens < 0 || pl->cur_gen + ngens > pl->Gmax)
+    return set_error(PA_EINVAL, "%d more generations exceed gens=%d (done %d)", ngens, pl->Gmax,
+                     pl->cur_gen);
+  pa_status st = use_device(in->ctx);
+  if (st != PA_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < ngens; ++k) {
+    for (size_t c = 0; c < pl->classes.size(); ++c) {
+      hipError_t e = launch_gen(pl->d_insts, pl->classes[c].c, pl->cur_gen, in->ctx->info, s);
+      if (e != hipSuccess) return hip_error(e, "pa_solve_next");
+    }
+    ++pl->cur_gen;
+  }
+  return PA_OK;
+}
+
+pa_status pa_solve_state(pa_instance *in, pa_result *out, int32_t *gens_done, void *stream) {
+  if (!in || !out) return set_error(PA_EINVAL, "instance or result is NULL");
+  SolvePlan *pl = in->plan;
+  if (!pl || pl->cur_gen < 0) return set_error(PA_EINVAL, "pa_solve_begin was not called");
+  pa_status st = use_device(in->ctx);
+  if (st != PA_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  PTRY(hipEventRecord(pl->ev0, s), "hipEventRecord");
+  PTRY(launch_best_batch(pl->d_insts, 1, pl->cur_gen, s), "launch best");
+  PTRY(hipEventRecord(pl->ev1, s), "hipEventRecord");
+  if (gens_done) *gens_done = pl->cur_gen;
+  return copy_results(pl, s, out, pl->cur_gen);
+}
+
+}  // extern "C"

@@ -20,7 +20,7 @@ CASES = [
     # (L, K, n): several rounds + a ragged tail for every variant
     (7, 4, 1000), (19, 16, 301), (37, 32, 97), (7, 5, 259), (19, 17, 131), (37, 23, 45),
     (37, 4, 200), (19, 32, 70), (3, 3, 216), (2, 1, 7), (5, 6, 123), (12, 9, 77), (61, 4, 30),
-    (40, 64, 9), (7, 32, 65), (2, 64, 3),
+    (40, 64, 9), (7, 32, 65), (2, 64, 3), (37, 16, 50),
 ]
 
 

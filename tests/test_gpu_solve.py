@@ -86,3 +86,32 @@ def test_solve_random_init_and_zero_generations(oracle_mod):
     assert abs(r.best_fit - f[b]) / f[b] <= 1e-5
     with pytest.raises(pa.PaError):
         pa.pa_solve(inst, pa.GaParams(pop=20, kmeans_frac=0.5))  # no positions
+
+
+def test_stepwise_matches_solve():
+    """Stepping generation by generation (caller-controlled termination) gives the
+    same bits as a whole solve; stopping after k generations equals a solve
+    with gens = k (random words are keyed by generation, not by the total)."""
+    need_gpu()
+    import paper_2511_20511_amd as pa
+    drop = scenario.make_drop(19, 16, seed=4, instance_id=2)
+    inst = pa.pa_instance_create(ctx(), drop.beta, drop.user_xy, drop.bs_xy, T=196)
+    p = pa.GaParams(pop=96, gens=30, elite=4, seed=9, instance_id=2)
+    pa.pa_solve_begin(inst, p)
+    pa.pa_solve_next(inst, 10)
+    r10, done = pa.pa_solve_state(inst)
+    assert done == 10
+    ref10 = pa.pa_solve(inst, pa.GaParams(pop=96, gens=10, elite=4, seed=9, instance_id=2))
+    pa.pa_solve_begin(inst, p)
+    pa.pa_solve_next(inst, 10)
+    r10b, _ = pa.pa_solve_state(inst)
+    pa.pa_solve_next(inst, 20)
+    r30, done = pa.pa_solve_state(inst)
+    assert done == 30
+    ref30 = pa.pa_solve(inst, p)
+    for a, b in ((r10, ref10), (r10b, ref10), (r30, ref30)):
+        assert np.array_equal(a.best, b.best)
+        assert np.float32(a.best_fit).view(np.uint32) == np.float32(b.best_fit).view(np.uint32)
+        assert np.array_equal(a.trace.view(np.uint32), b.trace.view(np.uint32))
+    with pytest.raises(pa.PaError):
+        pa.pa_solve_next(inst, 1)
