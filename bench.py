@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--kernel-iters", type=int, default=200)
     ap.add_argument("--batch", default="batch64_L37_K32",
                     help="also time this batched workload ('' to skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (5 times) and exit: the "
+                         "reference kernel that scales HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -105,6 +108,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy} MiB x 5 (read {n >> 10} KiB, write {n >> 10} KiB per copy)")
+        return
 
     import paper_2511_20511_amd as pa
     from paper_2511_20511_amd import scenario
@@ -150,27 +163,37 @@ def main():
     plain_ms = (time.perf_counter() - t1) * 1e3 / plain_steps
     log(f"plain solve (one launch per step): {plain_ms:.3f} ms/solve")
 
-    # dominant kernel: the fused generation kernel, one launch per generation,
-    # timed with events on the stream it is launched on
-    pa.pa_solve_begin(inst, params)
-    pa.pa_solve_next(inst, 10)
-    iters = min(args.kernel_iters, G - 10)
+    # dominant kernel: the generation kernel, timed with events on the stream
+    # it is launched on.  Persistent form: one launch runs all G generations
+    # (pa_solve_next(G)); graph form: one launch per generation.
+    shape = pa.pa_solve_shape(None, inst)
+    log(f"solve plan: {shape}")
+    TP = max(4, 1 << (K - 1).bit_length())
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pa.pa_solve_begin(inst, params)
+    if shape["persistent"]:
+        gens_per_launch, launches = G, 1
+        kname = f"k_gen_persist<{L},{TP},0,{shape['block']}>"
+    else:
+        pa.pa_solve_next(inst, 10)
+        gens_per_launch, launches = 1, min(args.kernel_iters, G - 10)
+        kname = f"k_gen_exact<{L},{TP},0,{shape['block']}>"
     e0.record(stream)
-    pa.pa_solve_next(inst, iters)
+    pa.pa_solve_next(inst, gens_per_launch * launches)
     e1.record(stream)
     e1.synchronize()
-    k_ms = e0.elapsed_time(e1) / iters
+    k_ms = e0.elapsed_time(e1) / launches
     # algorithmic LDS bytes of one launch: every child reads one 4-byte table
     # word per (BS, cell, pilot)
-    lds_bytes = (N - E) * L * L * K * 4
+    lds_bytes = (N - E) * gens_per_launch * L * L * K * 4
     achieved = lds_bytes / (k_ms * 1e-3) / 1e9
-    roofline = {"bound": "lds", "kernel": f"k_gen_exact<{L},{max(4, 1 << (K - 1).bit_length())},0,*>",
+    roofline = {"bound": "lds", "kernel": kname,
                 "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / LDS_PEAK_GBS, "traffic": None,
-                "avg_launch_us": k_ms * 1e3, "bytes_per_launch": lds_bytes}
-    log(f"fused generation kernel: {k_ms * 1e3:.2f} us/launch, {achieved:.0f} GB/s LDS "
-        f"({100 * achieved / LDS_PEAK_GBS:.1f}% of {LDS_PEAK_GBS:.0f})")
+                "avg_launch_us": k_ms * 1e3, "bytes_per_launch": lds_bytes,
+                "generations_per_launch": gens_per_launch}
+    log(f"generation kernel {kname}: {k_ms * 1e3:.2f} us/launch ({gens_per_launch} generation(s)), "
+        f"{achieved:.0f} GB/s LDS ({100 * achieved / LDS_PEAK_GBS:.1f}% of {LDS_PEAK_GBS:.0f})")
 
     extra = {}
     if args.batch:
@@ -185,6 +208,7 @@ def main():
         "solves_per_s": args.steps / wall,
         "solve_device_ms": float(np.median(dev_ms)),
         "plain_solve_ms": plain_ms,
+        "solve_plan": shape,
         "roofline": roofline,
     }
     line.update(extra)

@@ -194,9 +194,15 @@ pa_status pa_ga_step(pa_instance *inst, const pa_ga_params *params, int32_t gen,
 /* A whole solve: seeding, then `gens` generations of select / evolve /
  * evaluate with the population resident on the device, then the best
  * chromosome of the last population (Alg. 1, which returns the best
- * assignment).  Each generation is one fused launch (children built,
- * written and evaluated in LDS); the whole solve is captured once into a
- * hipGraph and replayed while the parameters stay the same.  Blocking. */
+ * assignment).  Children are built, written and evaluated in LDS by one
+ * fused generation kernel.  The first call with given parameters builds a
+ * plan: when every task of a generation fits on the device at once (small
+ * instances) all generations run in one cooperative launch separated by
+ * grid barriers, with the tasks' size autotuned on the instance itself;
+ * otherwise the whole solve (one launch per generation) is captured into a
+ * hipGraph.  Later calls with the same parameters replay the plan.  The
+ * form and the shape never change a result bit.  PA_EINTERNAL if a grid
+ * barrier wait times out (the results are then invalid).  Blocking. */
 pa_status pa_solve(pa_instance *inst, const pa_ga_params *params, pa_result *out, void *stream);
 
 /* Many independent solves in one: n instances of the same context, each with
@@ -213,7 +219,8 @@ pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
 /* Stepwise solve, for callers that decide themselves when to stop (Alg. 1
  * loops "while termination not met"); same kernels and bits as pa_solve.
  *   pa_solve_begin  seeding, initial population and its fitness.  Async.
- *   pa_solve_next   ngens more generations, one fused launch each; at most
+ *   pa_solve_next   ngens more generations (one cooperative launch for the
+ *                   persistent form, else one fused launch each); at most
  *                   params->gens in total since the last begin.  Async.
  *   pa_solve_state  best chromosome and fitness of the current population,
  *                   trace[0..gens_done]; *gens_done = generations run so far.
@@ -235,6 +242,15 @@ pa_status pa_solve_plain(pa_instance *inst, const pa_ga_params *params, pa_resul
  * Results are bit-identical to pa_fitness for every shape.  Async. */
 pa_status pa_fitness_shaped(pa_instance *inst, const uint8_t *d_pop, int32_t n, float *d_fit,
                             int32_t block, int32_t grid_cap, int32_t generic, void *stream);
+
+/* Execution form of the current solve plan of `inst` (inst != NULL, after
+ * pa_solve or pa_solve_begin) or of the context's batch plan (inst == NULL,
+ * after pa_solve_batch): *persistent = 1 for the single cooperative launch,
+ * 0 for the captured graph; threads per workgroup, children per task (of the
+ * first class, for its first instance's K) and workgroups per launch.  Any
+ * output pointer may be NULL.  PA_EINVAL when there is no plan. */
+pa_status pa_solve_shape(pa_context *ctx, pa_instance *inst, int32_t *persistent, int32_t *block,
+                         int32_t *children_per_task, int32_t *workgroups);
 
 /* ---- diagnostics ------------------------------------------------------ */
 

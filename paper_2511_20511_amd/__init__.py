@@ -23,6 +23,7 @@ __all__ = [
     "pa_context_create", "pa_context_destroy", "pa_instance_create", "pa_instance_destroy",
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
+    "pa_solve_shape",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
     "SE_ASYMPTOTIC", "SE_FINITE_M",
@@ -118,6 +119,8 @@ def lib():
         "pa_solve_begin": (st, [vp, ctypes.POINTER(_Params), vp]),
         "pa_solve_next": (st, [vp, i32, vp]),
         "pa_solve_state": (st, [vp, ctypes.POINTER(_Result), ctypes.POINTER(i32), vp]),
+        "pa_solve_shape": (st, [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
         "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
         "pa_status_string": (ctypes.c_char_p, [st]),
@@ -334,6 +337,17 @@ def pa_solve_state(inst: Instance, stream=None):
     _check(lib().pa_solve_state(inst.h, ctypes.byref(r), ctypes.byref(done), _stream(stream)))
     return Result(best, float(r.best_fit), int(r.best_index), trace[:done.value + 1],
                   float(r.device_ms)), int(done.value)
+
+
+def pa_solve_shape(ctx: Context | None = None, inst: Instance | None = None) -> dict:
+    """Execution form of the solve plan of `inst` (or of the context's batch
+    plan when inst is None): persistent, block, children_per_task, workgroups."""
+    vals = [ctypes.c_int32(0) for _ in range(4)]
+    _check(lib().pa_solve_shape(ctx.h if ctx is not None else None,
+                                inst.h if inst is not None else None,
+                                *[ctypes.byref(v) for v in vals]))
+    return dict(zip(("persistent", "block", "children_per_task", "workgroups"),
+                    (int(v.value) for v in vals)))
 
 
 def pa_instance_kmeans_state(inst: Instance):

@@ -38,29 +38,29 @@ __device__ __forceinline__ float se_finite(float b2, float I, float S, float a, 
   return __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
 }
 
-// In-place pairwise tree of seg[0..K) (result in seg[0]).
-__device__ __forceinline__ void tree_sum(float *seg, int K) {
-  int p2 = 1;
-  while (p2 < K) p2 <<= 1;
-  for (int s = p2 >> 1; s >= 1; s >>= 1)
-    for (int p = 0; p < s; ++p)
-      if (p + s < K) seg[p] = seg[p] + seg[p + s];
-}
-
 // Inverse rows of the chromosomes of a round, stored pilot-major:
 // inv[c][s][j] = the user of cell j that sends pilot s in chromosome c, so a
 // lane (c, s) finds its L entries contiguous.  One thread per row (c, j) of
-// the round's bytes `src` (LDS, nrows*K bytes); pilots >= K (invalid input)
-// are skipped so the write stays inside the chromosome.
+// the round's bytes `src` (LDS, 4-byte aligned, nrows*K bytes), read as
+// aligned 32-bit words; pilots >= K (invalid input) are skipped so the write
+// stays inside the chromosome.
 __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int L, int K,
                                               uint8_t *sInv) {
   for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
     const int c = r / L, j = r - c * L;
-    const uint8_t *row = src + r * K;
+    const int off = r * K, mis = off & 3;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(src + off - mis);
+    const int nw = (mis + K + 3) >> 2;
     uint8_t *dst = sInv + c * K * L + j;
-    for (int k = 0; k < K; ++k) {
-      const int s = row[k];
-      if (s < K) dst[s * L] = (uint8_t)k;
+#pragma unroll 4
+    for (int i = 0; i < nw; ++i) {
+      const uint32_t v = w[i];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int k = 4 * i + b - mis;
+        const int s = (int)((v >> (8 * b)) & 0xFFu);
+        if (k >= 0 && k < K && s < K) dst[s * L] = (uint8_t)k;
+      }
     }
   }
 }
@@ -129,12 +129,13 @@ __device__ __forceinline__ void load_tile(const float *__restrict__ T2, const fl
   const int q = TP >> 2;  // float4 per table row
   const int per_cell = rows * q;
   const int total = L * per_cell;
-  const float4 *s2 = reinterpret_cast<const float4 *>(T2);
-  const float4 *s1 = reinterpret_cast<const float4 *>(T1);
-  float4 *d = reinterpret_cast<float4 *>(dst);
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const gptr<const f4> s2 = gp(reinterpret_cast<const f4 *>(T2));
+  const gptr<const f4> s1 = gp(reinterpret_cast<const f4 *>(T1));
+  f4 *d = reinterpret_cast<f4 *>(dst);
   const int step = (int)blockDim.x;
   for (int base = threadIdx.x; base < total; base += kBatch * step) {
-    float4 v2[kBatch], v1[kBatch];
+    f4 v2[kBatch], v1[kBatch];
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int i = min(base + u * step, total - 1);  // clamped: every load is in bounds
@@ -186,10 +187,14 @@ __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, 
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);  // bytes per (cell, BS row)
   constexpr int CELLB = TR * ROWB;                      // bytes per cell in the tile
   const char *lds = reinterpret_cast<const char *>(sT);
+  // ip lies inside the inverse-row region for inactive lanes too: every lane
+  // loads (no per-element branch, all loads in flight at once), then masks
   uint32_t A[LT];
 #pragma unroll
+  for (int j = 0; j < LT; ++j) A[j] = ip[j];
+#pragma unroll
   for (int j = 0; j < LT; ++j) {
-    const uint32_t v = active ? ip[j] : 0u;
+    const uint32_t v = active ? A[j] : 0u;
     A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
   }
   float acc = 0.0f;
@@ -207,13 +212,67 @@ __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, 
       if (l < LT) {
         float a_l = 0.0f, c2_l = 0.0f;
         if constexpr (MODE == 1) {
-          a_l = lconst[2 * l];
-          c2_l = lconst[2 * l + 1];
+          a_l = gp(lconst)[2 * l];
+          c2_l = gp(lconst)[2 * l + 1];
         }
         acc = acc + row_term_exact<LT, MODE>(lds, A, (uint32_t)(lr * ROWB), TPT * 4u, l, a_l,
                                              c2_l);
       }
     }
+  }
+  return acc;
+}
+
+// Latency form of lane_sum_exact for a whole-table tile: the BS rows are
+// split over RS groups of GS lanes (GS >= 64, so the group index is uniform
+// per wave).  Lane ql of group rg computes the SE terms of rows l = rg,
+// rg + RS, ... and stores them in sSe[ql][l]; after a barrier lane ql of group
+// 0 adds its L terms in increasing l, the canonical order (same bits as
+// lane_sum_exact).  Returns that sum in group 0 (0 elsewhere).  Every thread
+// of the workgroup must call it.
+template <int LT, int TPT, int MODE>
+__device__ __forceinline__ float lane_sum_split(const uint8_t *sInv, int ql, bool active, int rg,
+                                                int RS, const float *sT, float *sSe,
+                                                const float *__restrict__ lconst) {
+  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
+  constexpr int CELLB = LT * ROWB;
+  const char *lds = reinterpret_cast<const char *>(sT);
+  const uint8_t *ip = sInv + ql * LT;  // inside the inverse region for every lane
+  uint32_t A[LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) A[j] = ip[j];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) {
+    const uint32_t v = active ? A[j] : 0u;
+    A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
+  }
+  for (int l = rg; l < LT; l += RS) {
+    const uint32_t off = (uint32_t)(l * ROWB);
+    float I = 0.0f, b2 = 0.0f;
+#pragma unroll
+    for (int j = 0; j < LT; ++j) {
+      const float g = *reinterpret_cast<const float *>(lds + A[j] + off);
+      const bool own = j == l;
+      b2 = own ? g : b2;
+      I = own ? I : I + g;
+    }
+    float se;
+    if constexpr (MODE == 1) {
+      float S = 0.0f;
+#pragma unroll
+      for (int j = 0; j < LT; ++j)
+        S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
+      se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1]);
+    } else {
+      se = se_asym(b2, I);
+    }
+    sSe[ql * LT + l] = se;
+  }
+  __syncthreads();
+  float acc = 0.0f;
+  if (rg == 0) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) acc = acc + sSe[ql * LT + l];
   }
   return acc;
 }
@@ -232,10 +291,14 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   constexpr int CELLB = TR * ROWB;
   const char *lds = reinterpret_cast<const char *>(sT);
+  // ip lies inside the inverse-row region for inactive lanes too: every lane
+  // loads (no per-element branch, all loads in flight at once), then masks
   uint32_t A[LT];
 #pragma unroll
+  for (int j = 0; j < LT; ++j) A[j] = ip[j];
+#pragma unroll
   for (int j = 0; j < LT; ++j) {
-    const uint32_t v = active ? ip[j] : 0u;
+    const uint32_t v = active ? A[j] : 0u;
     A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
   }
   float acc = 0.0f;
@@ -251,7 +314,8 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
 #pragma unroll
     for (int lr = 0; lr < TR; ++lr) {
       const int l = min(t * TR + lr, LT - 1);
-      const uint32_t own = active ? ip[l] : 0u;
+      const uint32_t ownr = ip[l];  // in bounds for inactive lanes too
+      const uint32_t own = active ? ownr : 0u;
       const float b2 = sOwn[l * TPT + (int)(own & (TPT - 1))];
       const uint32_t off = (uint32_t)(lr * ROWB);
       float I = 0.0f;
@@ -263,7 +327,7 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
 #pragma unroll
         for (int j = 0; j < LT; ++j)
           S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
-        se = se_finite(b2, I, S, lconst[2 * l], lconst[2 * l + 1]);
+        se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1]);
       } else {
         se = se_asym(b2, I);
       }
@@ -281,7 +345,7 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
 // Copies the own-cell squares T2[l][l][.] of every BS row into LDS as
 // sOwn[l][p] (L x TP floats).
 __device__ __forceinline__ void load_own(const float *__restrict__ Town, int L, int TP, float *sOwn) {
-  for (int i = threadIdx.x; i < L * TP; i += blockDim.x) sOwn[i] = Town[i];
+  for (int i = threadIdx.x; i < L * TP; i += blockDim.x) sOwn[i] = gp(Town)[i];
 }
 
 template <int LMAX, int MODE>
@@ -296,9 +360,10 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
   const char *lds = reinterpret_cast<const char *>(sT);
   uint32_t A[LMAX];
 #pragma unroll
+  for (int j = 0; j < LMAX; ++j) A[j] = ip[j < L ? j : 0];
+#pragma unroll
   for (int j = 0; j < LMAX; ++j) {
-    uint32_t v = 0u;
-    if (active && j < L) v = ip[j];
+    const uint32_t v = (active && j < L) ? A[j] : 0u;
     A[j] = (uint32_t)(j * CELLB) + (v & (uint32_t)(TP - 1)) * 4u;
   }
   float acc = 0.0f;
@@ -314,8 +379,8 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
       const int l = l0 + lr;
       float a_l = 0.0f, c2_l = 0.0f;
       if (MODE == 1) {
-        a_l = lconst[2 * l];
-        c2_l = lconst[2 * l + 1];
+        a_l = gp(lconst)[2 * l];
+        c2_l = gp(lconst)[2 * l + 1];
       }
       acc = acc + row_term_generic<LMAX, MODE>(lds, A, (uint32_t)(lr * ROWB), (uint32_t)TP * 4u,
                                                L, l, a_l, c2_l);
@@ -326,15 +391,43 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
 
 // Per-chromosome pairwise tree over pilots of the lanes' sums, then * prelog:
 // fit_out[c] for c < nc.  Called by every thread; ends with a barrier.
+template <int S>
+__device__ __forceinline__ float add_from_lane_plus(float v) {
+  // v + (the value of lane + S in the same row of 16 lanes); DPP row_shl:S
+  const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + S, 0xF, 0xF, false);
+  return v + __int_as_float(o);
+}
+
 __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, int nc, int K,
                                              float prelog, float *fit_out) {
+  // pairwise tree over the K pilot sums of a chromosome, one lane per pilot:
+  // for s = P/2, P/4, .., 1 (P = K rounded up to a power of two) lane p < s
+  // adds lane p + s when p + s < K; the result is in lane 0.
   const int q = threadIdx.x;
-  if (active) sE[q] = acc;
-  __syncthreads();
-  if (q < nc) {
-    tree_sum(sE + q * K, K);
-    fit_out[q] = prelog * sE[q * K];
+  const int c = q / K, p = q - c * K;
+  float v = acc;
+  if (K <= 16 && (K & (K - 1)) == 0) {
+    // a chromosome's lanes lie inside one DPP row: the tree in registers
+    if (K >= 16) v = add_from_lane_plus<8>(v);
+    if (K >= 8) v = add_from_lane_plus<4>(v);
+    if (K >= 4) v = add_from_lane_plus<2>(v);
+    if (K >= 2) v = add_from_lane_plus<1>(v);
+    if (active && p == 0 && c < nc) gp(fit_out)[c] = prelog * v;
+    __syncthreads();  // the caller's next LDS writes follow every lane's reads
+    return;
   }
+  // otherwise through LDS, one barrier per stride
+  if (active) sE[q] = v;
+  int p2 = 1;
+  while (p2 < K) p2 <<= 1;
+  for (int s = p2 >> 1; s >= 1; s >>= 1) {
+    __syncthreads();
+    if (active && p < s && p + s < K) {
+      v = v + sE[q + s];
+      sE[q] = v;
+    }
+  }
+  if (active && p == 0 && c < nc) gp(fit_out)[c] = prelog * v;
   __syncthreads();
 }
 

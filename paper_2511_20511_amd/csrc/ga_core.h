@@ -9,6 +9,8 @@
 
 namespace pa {
 
+
+
 // Swap mutation of the rows held in `buf` (LDS, row-major L x K bytes): gene
 // i = j*K + k mutates when decision word i is below thr and then swaps with
 // user k' != k of the same row, k' from partner word i.  Rows are processed
@@ -60,68 +62,48 @@ __device__ __forceinline__ void shuffle_rows(uint8_t *buf, int L, int K, const S
   }
 }
 
-// Parents and cut of the child in slot s (pairs (a, a+1) share their six
-// SELECT words, keyed by slot a).  Lanes 0 and 1 compute the two Philox
-// blocks, every lane gets all words.
-struct Pairing {
-  uint32_t p1, p2;  // parents: child a takes rows [0, cut) of p1, the rest of p2
-  int cut;          // L when there is no crossover
-};
-
-__device__ __forceinline__ Pairing select_parents(const float *__restrict__ fin, int N, int L,
-                                                  const DevGa &ga, uint32_t gen, int pair_a,
-                                                  int lane) {
-  const Stream sel{ga.seed_lo, ga.seed_hi, (uint32_t)pair_a, gen, ga.instance_id, kTagSelect};
-  const Words4 b = sel.block((uint32_t)(lane & 1));
-  const uint32_t w0 = __shfl(b.x, 0), w1 = __shfl(b.y, 0), w2 = __shfl(b.z, 0),
-                 w3 = __shfl(b.w, 0), w4 = __shfl(b.x, 1), w5 = __shfl(b.y, 1);
-  const uint32_t u0 = bounded(w0, (uint32_t)N), v0 = bounded(w1, (uint32_t)N);
-  const uint32_t u1 = bounded(w2, (uint32_t)N), v1 = bounded(w3, (uint32_t)N);
-  const uint32_t ku0 = rank_key(fin[u0]), kv0 = rank_key(fin[v0]);
-  const uint32_t ku1 = rank_key(fin[u1]), kv1 = rank_key(fin[v1]);
-  Pairing pr;
-  pr.p1 = beats(kv0, v0, ku0, u0) ? v0 : u0;
-  pr.p2 = beats(kv1, v1, ku1, u1) ? v1 : u1;
-  const bool cross = L >= 2 && hit(w4, ga.thr_cross);
-  pr.cut = cross ? 1 + (int)bounded(w5, (uint32_t)(L - 1)) : L;
-  return pr;
-}
-
 // Indices of the E best (E <= 64) into idx[0..E) by repeated arg-max over keys
 // strictly below the previous maximum (keys are unique: they embed the index).
-// Populations up to 2048 keep their keys in registers (32 per lane).
+// Populations up to 64*C keep their keys in registers (C per lane).
+template <int C>
+__device__ __forceinline__ void top_e_cached(const float *__restrict__ fin, int N, int E,
+                                             int32_t *idx, int lane) {
+  uint32_t kk[C];
+#pragma unroll
+  for (int u = 0; u < C; ++u) {
+    const int i = lane + u * kWave;
+    kk[u] = i < N ? rank_key(gp(fin)[i]) : 0u;
+  }
+  uint64_t prev = ~0ull;
+  for (int e = 0; e < E; ++e) {
+    uint64_t best = 0;
+#pragma unroll
+    for (int u = 0; u < C; ++u) {
+      const int i = lane + u * kWave;
+      const uint64_t k = ((uint64_t)kk[u] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
+      if (i < N && k < prev && k > best) best = k;
+    }
+    best = wave_max_u64(best);
+    if (lane == 0) idx[e] = (int32_t)key_index(best);
+    prev = best;
+  }
+}
+
 __device__ __forceinline__ void top_e_wave(const float *__restrict__ fin, int N, int E,
                                            int32_t *idx, int lane) {
-  constexpr int kCached = 32;
-  if (N <= kCached * kWave) {
-    uint32_t kk[kCached];
-#pragma unroll
-    for (int u = 0; u < kCached; ++u) {
-      const int i = lane + u * kWave;
-      kk[u] = i < N ? rank_key(fin[i]) : 0u;
-    }
-    uint64_t prev = ~0ull;
-    for (int e = 0; e < E; ++e) {
-      uint64_t best = 0;
-#pragma unroll
-      for (int u = 0; u < kCached; ++u) {
-        const int i = lane + u * kWave;
-        const uint64_t k = ((uint64_t)kk[u] << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
-        if (i < N && k < prev && k > best) best = k;
-      }
-      best = wave_max_u64(best);
-      if (lane == 0) idx[e] = (int32_t)key_index(best);
-      prev = best;
-    }
-    return;
-  }
+  if (N <= 1 * kWave) return top_e_cached<1>(fin, N, E, idx, lane);
+  if (N <= 2 * kWave) return top_e_cached<2>(fin, N, E, idx, lane);
+  if (N <= 4 * kWave) return top_e_cached<4>(fin, N, E, idx, lane);
+  if (N <= 8 * kWave) return top_e_cached<8>(fin, N, E, idx, lane);
+  if (N <= 16 * kWave) return top_e_cached<16>(fin, N, E, idx, lane);
+  if (N <= 32 * kWave) return top_e_cached<32>(fin, N, E, idx, lane);
   uint64_t prev = ~0ull;
   for (int e = 0; e < E; ++e) {
     uint64_t best = 0;
     for (int i0 = lane; i0 < N; i0 += 8 * kWave) {
       float f[8];  // eight loads in flight per lane
 #pragma unroll
-      for (int u = 0; u < 8; ++u) f[u] = fin[min(i0 + u * kWave, N - 1)];
+      for (int u = 0; u < 8; ++u) f[u] = gp(fin)[min(i0 + u * kWave, N - 1)];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int i = i0 + u * kWave;
@@ -137,10 +119,10 @@ __device__ __forceinline__ void top_e_wave(const float *__restrict__ fin, int N,
 
 // Rank of chromosome i = number of chromosomes that beat it (E > 64 path).
 __device__ __forceinline__ int rank_of(const float *__restrict__ fin, int N, int i) {
-  const uint32_t ki = rank_key(fin[i]);
+  const uint32_t ki = rank_key(gp(fin)[i]);
   int r = 0;
   for (int m = 0; m < N; ++m) {
-    const uint32_t km = rank_key(fin[m]);
+    const uint32_t km = rank_key(gp(fin)[m]);
     r += beats(km, (uint32_t)m, ki, (uint32_t)i) ? 1 : 0;
   }
   return r;
@@ -151,62 +133,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Builds the child of slot `slot` (generation `gen`) in the wave's LDS buffer
-// `child` (L*K bytes), using `hit` (L*K bytes of LDS) for the mutation
-// decisions: lanes over genes copy the parents' rows, all lanes draw the
-// decision words (4 genes per Philox block), then one lane per row applies
-// the swaps in increasing k.  Ends with the child complete in LDS.
-__device__ __forceinline__ void build_child(const uint8_t *__restrict__ pin,
-                                            const float *__restrict__ fin, int N, int E, int L,
-                                            int K, const DevGa &ga, uint32_t gen, int slot,
-                                            uint8_t *child, uint8_t *hits, int lane) {
-  const int LK = L * K;
-  const int pair_a = E + ((slot - E) & ~1);
-  const bool second = ((slot - E) & 1) != 0;
-  const Pairing pr = select_parents(fin, N, L, ga, gen, pair_a, lane);
-  const uint8_t *first = pin + (size_t)(second ? pr.p2 : pr.p1) * LK;
-  const uint8_t *rest = pin + (size_t)(second ? pr.p1 : pr.p2) * LK;
-  const int cutg = pr.cut * K;
-  for (int i = lane; i < LK; i += kWave) child[i] = i < cutg ? first[i] : rest[i];
-  const bool mutate = K >= 2 && ga.thr_mut != 0;
-  if (mutate) {
-    const Stream dec{ga.seed_lo, ga.seed_hi, (uint32_t)slot, gen, ga.instance_id, kTagMutDecide};
-    const int nb = (LK + 3) >> 2;
-    for (int b = lane; b < nb; b += kWave) {
-      const Words4 w = dec.block((uint32_t)b);
-      const int i = 4 * b;
-      hits[i] = hit(w.x, ga.thr_mut);
-      if (i + 1 < LK) hits[i + 1] = hit(w.y, ga.thr_mut);
-      if (i + 2 < LK) hits[i + 2] = hit(w.z, ga.thr_mut);
-      if (i + 3 < LK) hits[i + 3] = hit(w.w, ga.thr_mut);
-    }
-  }
-  wave_sync();
-  if (mutate) {
-    const Stream par{ga.seed_lo, ga.seed_hi, (uint32_t)slot, gen, ga.instance_id, kTagMutPartner};
-    for (int j = lane; j < L; j += kWave) {
-      uint8_t *row = child + j * K;
-      const uint8_t *h = hits + j * K;
-      uint32_t cur = 0xFFFFFFFFu;
-      Words4 wb{0, 0, 0, 0};
-      for (int k = 0; k < K; ++k) {
-        if (!h[k]) continue;
-        const uint32_t i = (uint32_t)(j * K + k);
-        if ((i >> 2) != cur) {
-          cur = i >> 2;
-          wb = par.block(cur);
-        }
-        const uint32_t r = bounded(pick(wb, i & 3u), (uint32_t)(K - 1));
-        const int kp = (int)r + ((int)r >= k ? 1 : 0);
-        const uint8_t t = row[k];
-        row[k] = row[kp];
-        row[kp] = t;
-      }
-    }
-  }
-  wave_sync();
 }
 
 // Elitism by one wave: slots 0..E-1 of pout receive the E best chromosomes
@@ -220,136 +146,207 @@ __device__ __forceinline__ void copy_elites(const uint8_t *__restrict__ pin,
     const int Ek = E > 1 ? E : 1;
     top_e_wave(fin, N, Ek, idx, lane);
     wave_sync();
-    if (trace && lane == 0) trace[gen] = fin[idx[0]];
+    if (trace && lane == 0) gp(trace)[gen] = gp(fin)[idx[0]];
     for (int e = 0; e < E; ++e) {
       const int src = idx[e];
-      for (int i = lane; i < LK; i += kWave) pout[(size_t)e * LK + i] = pin[(size_t)src * LK + i];
-      if (fout && lane == 0) fout[e] = fin[src];
+      for (int i = lane; i < LK; i += kWave)
+        gp(pout)[(size_t)e * LK + i] = gp(pin)[(size_t)src * LK + i];
+      if (fout && lane == 0) gp(fout)[e] = gp(fin)[src];
     }
   } else {
     // E >= 64: every lane ranks its chromosomes by counting who beats them
     for (int i = lane; i < N; i += kWave) {
       const int r = rank_of(fin, N, i);
-      if (r == 0 && trace) trace[gen] = fin[i];
+      if (r == 0 && trace) gp(trace)[gen] = gp(fin)[i];
       if (r < E) {
-        for (int g = 0; g < LK; ++g) pout[(size_t)r * LK + g] = pin[(size_t)i * LK + g];
-        if (fout) fout[r] = fin[i];
+        for (int g = 0; g < LK; ++g) gp(pout)[(size_t)r * LK + g] = gp(pin)[(size_t)i * LK + g];
+        if (fout) gp(fout)[r] = gp(fin)[i];
+      }
+    }
+  }
+}
+
+// Mutation codes of genes 4b .. 4b+3 of the child in slot `slot` as one
+// little-endian word: byte u = kp + 1 when gene i = 4b + u (cell j = i / K,
+// user k = i % K) mutates and swaps with user kp of its row, 0 otherwise (and
+// 0 past the chromosome's LK genes).  The decision of gene i is word i of the
+// MUT_DECIDE stream, its partner word i of the MUT_PARTNER stream.
+__device__ __forceinline__ uint32_t mutation_codes(int b, int LK, int K, const DevGa &ga,
+                                                   uint32_t gen, uint32_t slot) {
+  const Stream dec{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutDecide};
+  const Words4 w = dec.block((uint32_t)b);
+  const bool h0 = hit(w.x, ga.thr_mut), h1 = hit(w.y, ga.thr_mut);
+  const bool h2 = hit(w.z, ga.thr_mut), h3 = hit(w.w, ga.thr_mut);
+  if (!(h0 || h1 || h2 || h3)) return 0u;
+  const Stream par{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutPartner};
+  const Words4 pw = par.block((uint32_t)b);
+  uint32_t out = 0u;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = 4 * b + u;
+    const bool h = u == 0 ? h0 : u == 1 ? h1 : u == 2 ? h2 : h3;
+    if (h && i < LK) {
+      const int k = i % K;
+      const uint32_t r = bounded(pick(pw, (uint32_t)u), (uint32_t)(K - 1));
+      out |= (uint32_t)((int)r + ((int)r >= k ? 1 : 0) + 1) << (8 * u);
+    }
+  }
+  return out;
+}
+
+// Applies the swaps of one row (bytes row[0..K) in LDS) given its codes, in
+// increasing k against the current row.  `codes` and `row` sit at the same
+// offset `off` from 4-byte aligned bases, so the codes are read as aligned
+// 32-bit words and only mutating genes touch the row.
+__device__ __forceinline__ void apply_swaps(uint8_t *row, const uint8_t *codes, int off, int K) {
+  const int mis = off & 3;
+  const uint32_t *cw = reinterpret_cast<const uint32_t *>(codes - mis);
+  const int nw = (mis + K + 3) >> 2;
+  uint64_t m = 0;
+#pragma unroll 4
+  for (int w = 0; w < nw; ++w) {
+    const uint32_t v = cw[w];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int k = 4 * w + b - mis;
+      if (k >= 0 && k < K && ((v >> (8 * b)) & 0xFFu) != 0u) m |= 1ull << k;
+    }
+  }
+  while (m != 0ull) {
+    const int k = __builtin_ctzll(m);
+    m &= m - 1ull;
+    const int kp = (int)codes[k] - 1;
+    const uint8_t t = row[k];
+    row[k] = row[kp];
+    row[kp] = t;
+  }
+}
+
+// Copies the byte range r into LDS at dst + off (dst 4-byte aligned) with a
+// team of tpr threads (this thread is member `sub`): aligned 32-bit loads, up
+// to kCopyBatch in flight; whole words are stored as words when source and
+// destination share their alignment, bytes otherwise.
+__device__ __forceinline__ void gather_range(const ByteRange &r, uint8_t *dst, int off, int sub,
+                                             int tpr) {
+  if (r.n <= 0) return;
+  const int nw = r.words();
+  const int smis = (int)((uintptr_t)r.src & 3u);
+  const bool same = ((off - smis) & 3) == 0;
+  for (int w0 = sub; w0 < nw; w0 += kCopyBatch * tpr) {
+    uint32_t v[kCopyBatch];
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; ++u) v[u] = r.load(min(w0 + u * tpr, nw - 1));
+#pragma unroll
+    for (int u = 0; u < kCopyBatch; ++u) {
+      const int w = w0 + u * tpr;
+      if (w < nw) {
+        const int g0 = 4 * w - smis;  // range offset of the word's first byte
+        if (same && g0 >= 0 && g0 + 4 <= r.n) {
+          *reinterpret_cast<uint32_t *>(dst + off + g0) = v[u];
+        } else {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int g = g0 + b;
+            if (g >= 0 && g < r.n) dst[off + g] = (uint8_t)(v[u] >> (8 * b));
+          }
+        }
       }
     }
   }
 }
 
 // Builds the children of slots [s0, s0 + nc) in LDS (child c at child +
-// c*L*K) with the whole workgroup, in phases separated by barriers:
-//   1. one thread per child: its pair's six SELECT words, two tournaments,
-//      crossover decision and cut;
-//   2. all threads over all genes: copy from the parents;
-//      all threads over all (child, Philox block): mutation decisions;
+// c*L*K) with the whole workgroup (nc <= block), in phases separated by
+// barriers:
+//   1. thread c < nc: its pair's six SELECT words and the four fitness loads
+//      of its tournaments; meanwhile every thread computes the mutation codes
+//      of its (child, Philox block) pairs into `codes`; then thread c
+//      resolves the tournaments, crossover decision and cut;
+//   2. all threads over all genes: copy from the parents (aligned words,
+//      several loads in flight);
 //   3. one thread per (child, row): the swaps, in increasing k.
-// Each phase costs about one global-memory round trip however many children
-// the workgroup builds.  sSel: 2 ints per child.  Ends with a barrier.
+// `child` and `codes` are 4-byte aligned LDS buffers of nc*L*K bytes; sSel:
+// 2 ints per child.  Ends with a barrier.
 __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__ pin,
                                                      const float *__restrict__ fin, int N, int E,
                                                      int L, int K, const DevGa &ga, uint32_t gen,
                                                      int s0, int nc, uint8_t *child,
-                                                     uint8_t *hits, int32_t *sSel, int block) {
+                                                     uint8_t *codes, int32_t *sSel, int block) {
   const int LK = L * K;
   const int tid = threadIdx.x;
-  for (int c = tid; c < nc; c += block) {
-    const int slot = s0 + c;
+  const bool sel = tid < nc;
+  const int slot = s0 + tid;
+  uint32_t u0 = 0, v0 = 0, u1 = 0, v1 = 0;
+  float fu0 = 0.0f, fv0 = 0.0f, fu1 = 0.0f, fv1 = 0.0f;
+  Words4 b1{0, 0, 0, 0};
+  if (sel) {
     const int pair_a = E + ((slot - E) & ~1);
-    const bool second = ((slot - E) & 1) != 0;
-    const Stream sel{ga.seed_lo, ga.seed_hi, (uint32_t)pair_a, gen, ga.instance_id, kTagSelect};
-    const Words4 b0 = sel.block(0u), b1 = sel.block(1u);
-    const uint32_t u0 = bounded(b0.x, (uint32_t)N), v0 = bounded(b0.y, (uint32_t)N);
-    const uint32_t u1 = bounded(b0.z, (uint32_t)N), v1 = bounded(b0.w, (uint32_t)N);
-    const uint32_t p1 = beats(rank_key(fin[v0]), v0, rank_key(fin[u0]), u0) ? v0 : u0;
-    const uint32_t p2 = beats(rank_key(fin[v1]), v1, rank_key(fin[u1]), u1) ? v1 : u1;
-    const bool cross = L >= 2 && hit(b1.x, ga.thr_cross);
-    const int cut = cross ? 1 + (int)bounded(b1.y, (uint32_t)(L - 1)) : L;
-    const uint32_t first = second ? p2 : p1, rest = second ? p1 : p2;
-    sSel[2 * c] = (int32_t)(first | (rest << 16));
-    sSel[2 * c + 1] = cut * K;
-  }
-  __syncthreads();
-  // child c = first parent's genes [0, cut) + second's [cut, LK): two byte
-  // ranges per child, moved as aligned words, several loads in flight
-  {
-    const int ws = (LK >> 2) + 2;  // words of a range, upper bound
-    const int items = nc * 2 * ws;
-    for (int i0 = tid; i0 < items; i0 += kCopyBatch * block) {
-      uint32_t v[kCopyBatch];
-#pragma unroll
-      for (int u = 0; u < kCopyBatch; ++u) {
-        const int i = i0 + u * block;
-        const int c = i / (2 * ws), rr = (i / ws) & 1, w = i % ws;
-        const uint32_t pr = (uint32_t)sSel[2 * (c < nc ? c : 0)];
-        const int cutg = sSel[2 * (c < nc ? c : 0) + 1];
-        const ByteRange r = rr == 0 ? ByteRange{pin + (size_t)(pr & 0xFFFFu) * LK, cutg}
-                                    : ByteRange{pin + (size_t)(pr >> 16) * LK + cutg, LK - cutg};
-        const bool ok = i < items && r.n > 0 && w < r.words();
-        v[u] = ok ? r.load(w) : 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < kCopyBatch; ++u) {
-        const int i = i0 + u * block;
-        const int c = i / (2 * ws), rr = (i / ws) & 1, w = i % ws;
-        if (i < items) {
-          const uint32_t pr = (uint32_t)sSel[2 * c];
-          const int cutg = sSel[2 * c + 1];
-          const ByteRange r = rr == 0 ? ByteRange{pin + (size_t)(pr & 0xFFFFu) * LK, cutg}
-                                      : ByteRange{pin + (size_t)(pr >> 16) * LK + cutg, LK - cutg};
-          uint8_t *dst = child + c * LK + (rr == 0 ? 0 : cutg);
-          if (r.n > 0 && w < r.words()) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              const int g = r.pos(w, b);
-              if (g >= 0 && g < r.n) dst[g] = (uint8_t)(v[u] >> (8 * b));
-            }
-          }
-        }
-      }
-    }
+    const Stream st{ga.seed_lo, ga.seed_hi, (uint32_t)pair_a, gen, ga.instance_id, kTagSelect};
+    const Words4 b0 = st.block(0u);
+    b1 = st.block(1u);
+    u0 = bounded(b0.x, (uint32_t)N);
+    v0 = bounded(b0.y, (uint32_t)N);
+    u1 = bounded(b0.z, (uint32_t)N);
+    v1 = bounded(b0.w, (uint32_t)N);
+    fu0 = gp(fin)[u0];
+    fv0 = gp(fin)[v0];
+    fu1 = gp(fin)[u1];
+    fv1 = gp(fin)[v1];
   }
   const bool mutate = K >= 2 && ga.thr_mut != 0;
   if (mutate) {
+    // one thread per (child, Philox block); child c's codes start at byte
+    // c*LK, so its words are written through a byte-aligned window when LK is
+    // not a multiple of 4
     const int nb = (LK + 3) >> 2;
     for (int i = tid; i < nc * nb; i += block) {
       const int c = i / nb, b = i - c * nb;
-      const Stream dec{ga.seed_lo, ga.seed_hi, (uint32_t)(s0 + c), gen, ga.instance_id,
-                       kTagMutDecide};
-      const Words4 w = dec.block((uint32_t)b);
-      uint8_t *h = hits + c * LK + 4 * b;
-      const int g = 4 * b;
-      h[0] = hit(w.x, ga.thr_mut);
-      if (g + 1 < LK) h[1] = hit(w.y, ga.thr_mut);
-      if (g + 2 < LK) h[2] = hit(w.z, ga.thr_mut);
-      if (g + 3 < LK) h[3] = hit(w.w, ga.thr_mut);
+      const uint32_t v = mutation_codes(b, LK, K, ga, gen, (uint32_t)(s0 + c));
+      uint8_t *dst = codes + c * LK + 4 * b;
+      if ((LK & 3) == 0) {
+        *reinterpret_cast<uint32_t *>(dst) = v;
+      } else {
+        const int n = LK - 4 * b < 4 ? LK - 4 * b : 4;
+        for (int u = 0; u < n; ++u) dst[u] = (uint8_t)(v >> (8 * u));
+      }
+    }
+  }
+  if (sel) {
+    const bool second = ((slot - E) & 1) != 0;
+    const uint32_t p1 = beats(rank_key(fv0), v0, rank_key(fu0), u0) ? v0 : u0;
+    const uint32_t p2 = beats(rank_key(fv1), v1, rank_key(fu1), u1) ? v1 : u1;
+    const bool cross = L >= 2 && hit(b1.x, ga.thr_cross);
+    const int cut = cross ? 1 + (int)bounded(b1.y, (uint32_t)(L - 1)) : L;
+    const uint32_t first = second ? p2 : p1, rest = second ? p1 : p2;
+    sSel[2 * tid] = (int32_t)(first | (rest << 16));
+    sSel[2 * tid + 1] = cut * K;
+  }
+  __syncthreads();
+  // child c = first parent's genes [0, cut) + second's [cut, LK): two byte
+  // ranges per child; a power-of-two team of threads per range moves it as
+  // aligned words, several loads in flight per thread
+  {
+    const int nr = 2 * nc;
+    int lg = 0;
+    while ((2 << lg) * nr <= block) ++lg;
+    const int tpr = 1 << lg;  // threads per range
+    const int sub = tid & (tpr - 1);
+    for (int r0 = tid >> lg; r0 < nr; r0 += block >> lg) {
+      const int c = r0 >> 1;
+      const uint32_t pr = (uint32_t)sSel[2 * c];
+      const int cutg = sSel[2 * c + 1];
+      if ((r0 & 1) == 0)
+        gather_range(ByteRange{pin + (size_t)(pr & 0xFFFFu) * LK, cutg}, child, c * LK, sub, tpr);
+      else
+        gather_range(ByteRange{pin + (size_t)(pr >> 16) * LK + cutg, LK - cutg}, child,
+                     c * LK + cutg, sub, tpr);
     }
   }
   __syncthreads();
   if (mutate) {
-    for (int i = tid; i < nc * L; i += block) {
-      const int c = i / L, j = i - c * L;
-      const Stream par{ga.seed_lo, ga.seed_hi, (uint32_t)(s0 + c), gen, ga.instance_id,
-                       kTagMutPartner};
-      uint8_t *row = child + c * LK + j * K;
-      const uint8_t *h = hits + c * LK + j * K;
-      uint32_t cur = 0xFFFFFFFFu;
-      Words4 wb{0, 0, 0, 0};
-      for (int k = 0; k < K; ++k) {
-        if (!h[k]) continue;
-        const uint32_t gi = (uint32_t)(j * K + k);
-        if ((gi >> 2) != cur) {
-          cur = gi >> 2;
-          wb = par.block(cur);
-        }
-        const uint32_t r = bounded(pick(wb, gi & 3u), (uint32_t)(K - 1));
-        const int kp = (int)r + ((int)r >= k ? 1 : 0);
-        const uint8_t t = row[k];
-        row[k] = row[kp];
-        row[kp] = t;
-      }
+    for (int r = tid; r < nc * L; r += block) {
+      const int off = r * K;  // (c*L + j)*K
+      apply_swaps(child + off, codes + off, off, K);
     }
   }
   __syncthreads();
@@ -371,8 +368,8 @@ __device__ __forceinline__ void copy_elites_block(const uint8_t *__restrict__ pi
   }
   if (wave == 0) top_e_wave(fin, N, E > 1 ? E : 1, idx, lane);
   __syncthreads();
-  if (threadIdx.x == 0 && trace) trace[gen] = fin[idx[0]];
-  if (fout && (int)threadIdx.x < E) fout[threadIdx.x] = fin[idx[threadIdx.x]];
+  if (threadIdx.x == 0 && trace) gp(trace)[gen] = gp(fin)[idx[0]];
+  if (fout && (int)threadIdx.x < E) gp(fout)[threadIdx.x] = gp(fin)[idx[threadIdx.x]];
   const int ws = (LK >> 2) + 2;
   const int items = E * ws;
   const int step = (int)blockDim.x;
@@ -396,7 +393,7 @@ __device__ __forceinline__ void copy_elites_block(const uint8_t *__restrict__ pi
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int g = r.pos(w, b);
-            if (g >= 0 && g < LK) dst[g] = (uint8_t)(v[u] >> (8 * b));
+            if (g >= 0 && g < LK) gp(dst)[g] = (uint8_t)(v[u] >> (8 * b));
           }
         }
       }

@@ -23,9 +23,13 @@ struct GenArgs {
 };
 
 // LDS plan: table tile | children (<= block*L) | inverse rows, aliased by the
-// mutation flags while children are built (<= block*L) | sums (block*4) |
-// elite indices (64 ints).
-template <int LT, int TPT, int MODE, int BLOCK>
+// mutation codes while children are built (<= block*L) | sums (block*4) |
+// elite indices (64 ints) | own-cell squares | parents and cut per child,
+// and with PF (persistent form) the tournament candidates of the task's pairs
+// (4 chromosomes per pair; reused for the per-row SE terms of the split lane
+// sum), their selection words (6 ints per pair), their outcome (4 ints per
+// pair) and the children's mutation codes (<= block*L).
+template <int LT, int TPT, int MODE, int BLOCK, bool PF = false>
 struct GenPlan {
   static constexpr int kChildBytes = ((BLOCK * LT) + 15) / 16 * 16;
   static constexpr int kInvBytes = kChildBytes;
@@ -33,8 +37,14 @@ struct GenPlan {
   static constexpr int kIdxBytes = 256;
   static constexpr int kOwnBytes = LT * TPT * 4;  // own-cell squares (tiled tables)
   static constexpr int kSelBytes = BLOCK * 8;     // parents and cut per child
+  static constexpr int kMaxPairs = BLOCK / 2 + 2;
+  static constexpr int kCandBytes = PF ? (2 * BLOCK * LT + 6 * LT * TPT + 15) / 16 * 16 : 0;
+  static constexpr int kPairBytes = PF ? kMaxPairs * 24 : 0;
+  static constexpr int kResBytes = PF ? kMaxPairs * 16 : 0;
+  static constexpr int kCodeBytes = PF ? kChildBytes : 0;  // mutation codes (PF)
   using T = TilePlan<LT, TPT, MODE,
-                     kChildBytes + kInvBytes + kEBytes + kIdxBytes + kOwnBytes + kSelBytes>;
+                     kChildBytes + kInvBytes + kEBytes + kIdxBytes + kOwnBytes + kSelBytes +
+                         kCandBytes + kPairBytes + kResBytes + kCodeBytes>;
   static constexpr int kTiles = T::kTiles;
   static constexpr int kTileRows = T::kTileRows;
   static constexpr int kChildOff = T::kTableBytes;
@@ -43,9 +53,18 @@ struct GenPlan {
   static constexpr int kIdxOff = kEOff + kEBytes;
   static constexpr int kOwnOff = kIdxOff + kIdxBytes;
   static constexpr int kSelOff = kOwnOff + kOwnBytes;
-  static constexpr int kTotal = kSelOff + kSelBytes;
+  static constexpr int kCandOff = kSelOff + kSelBytes;
+  static constexpr int kPairOff = kCandOff + kCandBytes;
+  static constexpr int kResOff = kPairOff + kPairBytes;
+  static constexpr int kCodeOff = kResOff + kResBytes;
+  static constexpr int kTotal = kCodeOff + kCodeBytes;
   static_assert(kTotal <= kLdsBytes, "LDS plan too large");
 };
+
+__device__ __forceinline__ GenTask load_task(const GenTask *tasks, int t) {
+  const gptr<const GenTask> p = gp(tasks) + t;
+  return GenTask{p->inst, p->kind, p->s0, p->s1};
+}
 
 // Everything of a task but the fitness evaluation; returns the number of
 // chromosomes to evaluate (0 for an elite task or a finished instance).
@@ -57,19 +76,18 @@ __device__ __forceinline__ int gen_prepare(const GenInst &I, const GenTask &task
   const int in = gen < 0 ? 0 : (gen & 1);
   const int out = gen < 0 ? 0 : 1 - in;
   if (task.kind == kTaskElite) {
-    copy_elites_block(I.pop[in], I.fit[in], I.N, I.E, LK, I.pop[out], I.fit[out], I.trace, gen,
-                      sIdx);
+    copy_elites_block(pop_buf(I, in), fit_buf(I, in), I.N, I.E, LK, pop_buf(I, out),
+                      fit_buf(I, out), I.trace, gen, sIdx);
     return 0;
   }
   const int nc = task.s1 - task.s0;
   if (task.kind == kTaskChild) {
-    build_children_block(I.pop[in], I.fit[in], I.N, I.E, L, K, I.ga, (uint32_t)gen, task.s0, nc,
-                         sChild, sInv, sSel, block);
-    uint8_t *dst = I.pop[out] + (size_t)task.s0 * LK;
-    for (int i = threadIdx.x; i < nc * LK; i += block) dst[i] = sChild[i];
+    build_children_block(pop_buf(I, in), fit_buf(I, in), I.N, I.E, L, K, I.ga, (uint32_t)gen,
+                         task.s0, nc, sChild, sInv, sSel, block);
+    store_bytes(pop_buf(I, out) + (size_t)task.s0 * LK, sChild, nc * LK);
     build_inverse(sChild, nc * L, L, K, sInv);
   } else {
-    copy_bytes(I.pop[in] + (size_t)task.s0 * LK, nc * LK, sChild);
+    copy_bytes(pop_buf(I, in) + (size_t)task.s0 * LK, nc * LK, sChild);
     __syncthreads();
     build_inverse(sChild, nc * L, L, K, sInv);
   }
@@ -77,12 +95,191 @@ __device__ __forceinline__ int gen_prepare(const GenInst &I, const GenTask &task
   return nc;
 }
 
-template <int LT, int TPT, int MODE, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
-  using P = GenPlan<LT, TPT, MODE, BLOCK>;
+// ---- persistent form: a child task prepared ahead ----------------------
+//
+// Everything of a child task that depends only on (seed, slots, generation)
+// -- its pairs' SELECT words and its children's mutation codes -- is
+// computed before the grid barrier that precedes the generation; after the
+// barrier one round trip fetches the fitness of the tournament candidates
+// together with the candidates' chromosomes (4 per pair), and the children
+// are assembled from LDS.  Same draws, same children as gen_prepare.
+
+struct PairSpan {
+  int pa0, np;  // first pair index (slot E + 2*pa0) and pairs of the task
+};
+__device__ __forceinline__ PairSpan pair_span(const GenInst &I, const GenTask &task) {
+  const int pa0 = (task.s0 - I.E) >> 1;
+  return PairSpan{pa0, ((task.s1 - 1 - I.E) >> 1) - pa0 + 1};
+}
+
+// SELECT words of the task's pairs into sPair (6 per pair: u0, v0, u1, v1,
+// crossover word, cut word) and mutation codes of its children into codes.
+__device__ __forceinline__ void pf_precompute(const GenInst &I, const GenTask &task, int gen,
+                                              uint8_t *codes, int32_t *sPair, int block) {
+  const int N = I.N, K = I.K, LK = I.L * K;
+  const PairSpan ps = pair_span(I, task);
+  const int tid = threadIdx.x;
+  const DevGa &ga = I.ga;
+  if (tid < ps.np) {
+    const uint32_t a = (uint32_t)(I.E + 2 * (ps.pa0 + tid));
+    const Stream st{ga.seed_lo, ga.seed_hi, a, (uint32_t)gen, ga.instance_id, kTagSelect};
+    const Words4 b0 = st.block(0u), b1 = st.block(1u);
+    int32_t *w = sPair + 6 * tid;
+    w[0] = (int32_t)bounded(b0.x, (uint32_t)N);
+    w[1] = (int32_t)bounded(b0.y, (uint32_t)N);
+    w[2] = (int32_t)bounded(b0.z, (uint32_t)N);
+    w[3] = (int32_t)bounded(b0.w, (uint32_t)N);
+    w[4] = (int32_t)b1.x;
+    w[5] = (int32_t)b1.y;
+  }
+  if (K >= 2 && ga.thr_mut != 0) {
+    const int nc = task.s1 - task.s0, nb = (LK + 3) >> 2;
+    for (int i = tid; i < nc * nb; i += block) {
+      const int c = i / nb, b = i - c * nb;
+      const uint32_t v = mutation_codes(b, LK, K, ga, (uint32_t)gen, (uint32_t)(task.s0 + c));
+      uint8_t *dst = codes + c * LK + 4 * b;
+      if ((LK & 3) == 0) {
+        *reinterpret_cast<uint32_t *>(dst) = v;
+      } else {
+        const int n = LK - 4 * b < 4 ? LK - 4 * b : 4;
+        for (int u = 0; u < n; ++u) dst[u] = (uint8_t)(v >> (8 * u));
+      }
+    }
+  }
+}
+
+// The children of a prepared task (pf_precompute of this generation done and
+// followed by a barrier; codes in sCode): tournaments, crossover and swaps,
+// write-out and inverse rows; returns the number of children.  Ends with a
+// barrier.
+__device__ __forceinline__ int pf_build(const GenInst &I, const GenTask &task, int gen,
+                                        uint8_t *sChild, uint8_t *sInv, uint8_t *sCand,
+                                        const int32_t *sPair, int32_t *sRes,
+                                        const uint8_t *sCode, int block) {
+  const int L = I.L, K = I.K, LK = L * K, E = I.E;
+  const int in = gen & 1, out = 1 - in;
+  const uint8_t *pin = pop_buf(I, in);
+  const float *fin = fit_buf(I, in);
+  const PairSpan ps = pair_span(I, task);
+  const int nc = task.s1 - task.s0;
+  const int tid = threadIdx.x;
+  // 1. one round trip: the candidates' fitness and chromosomes
+  float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, f3 = 0.0f;
+  if (tid < ps.np) {
+    const int32_t *w = sPair + 6 * tid;
+    f0 = gp(fin)[w[0]];
+    f1 = gp(fin)[w[1]];
+    f2 = gp(fin)[w[2]];
+    f3 = gp(fin)[w[3]];
+  }
+  {
+    const int nr = 4 * ps.np;
+    int lg = 0;
+    while ((2 << lg) * nr <= block) ++lg;
+    const int tpr = 1 << lg;
+    const int sub = tid & (tpr - 1);
+    for (int r = tid >> lg; r < nr; r += block >> lg) {
+      const int idx = sPair[6 * (r >> 2) + (r & 3)];
+      gather_range(ByteRange{pin + (size_t)idx * LK, LK}, sCand, r * LK, sub, tpr);
+    }
+  }
+  if (tid < ps.np) {
+    const int32_t *w = sPair + 6 * tid;
+    const uint32_t u0 = (uint32_t)w[0], v0 = (uint32_t)w[1];
+    const uint32_t u1 = (uint32_t)w[2], v1 = (uint32_t)w[3];
+    const bool c1 = beats(rank_key(f1), v0, rank_key(f0), u0);
+    const bool c2 = beats(rank_key(f3), v1, rank_key(f2), u1);
+    const bool cross = L >= 2 && hit((uint32_t)w[4], I.ga.thr_cross);
+    const int cut = cross ? 1 + (int)bounded((uint32_t)w[5], (uint32_t)(L - 1)) : L;
+    sRes[4 * tid] = c1 ? 1 : 0;      // candidate slot of parent 1
+    sRes[4 * tid + 1] = c2 ? 3 : 2;  // candidate slot of parent 2
+    sRes[4 * tid + 2] = cut * K;
+  }
+  __syncthreads();
+  // 2. child c = first parent's genes [0, cut) + second's [cut, LK), one
+  // power-of-two team of threads per child, 32-bit words when LK % 4 == 0
+  {
+    int lg = 0;
+    while ((2 << lg) * nc <= block) ++lg;
+    const int tpr = 1 << lg, sub = tid & (tpr - 1);
+    for (int c = tid >> lg; c < nc; c += block >> lg) {
+      const int slot = task.s0 + c;
+      const int lp = ((slot - E) >> 1) - ps.pa0;
+      const bool second = ((slot - E) & 1) != 0;
+      const int32_t *res = sRes + 4 * lp;
+      const int r0 = res[0], r1 = res[1], cutg = res[2];
+      const int fs = second ? r1 : r0, rs = second ? r0 : r1;
+      const uint8_t *cf = sCand + (4 * lp + fs) * LK, *cr = sCand + (4 * lp + rs) * LK;
+      uint8_t *dst = sChild + c * LK;
+      if ((LK & 3) == 0) {
+        for (int w = sub; w < (LK >> 2); w += tpr) {
+          const int g = 4 * w;
+          uint32_t v;
+          if (g + 4 <= cutg) {
+            v = *reinterpret_cast<const uint32_t *>(cf + g);
+          } else if (g >= cutg) {
+            v = *reinterpret_cast<const uint32_t *>(cr + g);
+          } else {
+            const uint32_t a = *reinterpret_cast<const uint32_t *>(cf + g);
+            const uint32_t b = *reinterpret_cast<const uint32_t *>(cr + g);
+            const uint32_t m = 0xFFFFFFFFu >> (8 * (4 - (cutg - g)));  // bytes below cutg
+            v = (a & m) | (b & ~m);
+          }
+          *reinterpret_cast<uint32_t *>(dst + g) = v;
+        }
+      } else {
+        for (int g = sub; g < LK; g += tpr) dst[g] = g < cutg ? cf[g] : cr[g];
+      }
+    }
+  }
+  __syncthreads();
+  // 3. one thread per row: the swaps, then (K % 4 == 0: rows are whole
+  // aligned words) the row's inverse entries and its write-out
+  const bool mutate = K >= 2 && I.ga.thr_mut != 0;
+  uint8_t *pout = pop_buf(I, out) + (size_t)task.s0 * LK;
+  if ((K & 3) == 0) {
+    for (int r = tid; r < nc * L; r += block) {
+      if (mutate) apply_swaps(sChild + r * K, sCode + r * K, r * K, K);
+      const int c = r / L, j = r - c * L;
+      const uint32_t *rw = reinterpret_cast<const uint32_t *>(sChild + r * K);
+      gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)r * K));
+      uint8_t *dst = sInv + c * K * L + j;
+      for (int w = 0; w < (K >> 2); ++w) {
+        const uint32_t v = rw[w];
+        gw[w] = v;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int s = (int)((v >> (8 * b)) & 0xFFu);
+          if (s < K) dst[s * L] = (uint8_t)(4 * w + b);
+        }
+      }
+    }
+    __syncthreads();
+    return nc;
+  }
+  if (mutate) {
+    for (int r = tid; r < nc * L; r += block) apply_swaps(sChild + r * K, sCode + r * K, r * K, K);
+  }
+  __syncthreads();
+  // 4. write-out and inverse rows
+  store_bytes(pout, sChild, nc * LK);
+  build_inverse(sChild, nc * L, L, K, sInv);
+  __syncthreads();
+  return nc;
+}
+
+// One task of one generation for a workgroup of the unrolled kernel.  I is a
+// copy of the instance descriptor in registers, read before the task's first
+// global store: a descriptor field loaded after a store would make its wait
+// (the vector-memory counter is in order) wait for the store as well.
+// `loaded` is the instance whose table sits in LDS (-1: none); `prepared`:
+// the child task's draws were made ahead (persistent form).
+template <int LT, int TPT, int MODE, int BLOCK, bool PF = false>
+__device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task, int gen,
+                                         unsigned char *smem, int &loaded, bool prepared) {
+  using P = GenPlan<LT, TPT, MODE, BLOCK, PF>;
   constexpr int NT = P::kTiles;
   constexpr int TR = P::kTileRows;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   float *sT = reinterpret_cast<float *>(smem);
   uint8_t *sChild = smem + P::kChildOff;
   uint8_t *sInv = smem + P::kInvOff;
@@ -90,35 +287,201 @@ __global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
   int32_t *sIdx = reinterpret_cast<int32_t *>(smem + P::kIdxOff);
   float *sOwn = reinterpret_cast<float *>(smem + P::kOwnOff);
   int32_t *sSel = reinterpret_cast<int32_t *>(smem + P::kSelOff);
+  if (gen >= I.G) return;  // this instance has finished its generations
+  const int out = gen < 0 ? 0 : 1 - (gen & 1);
+  float *const fit_out = fit_buf(I, out) + task.s0;
+  const float prelog = I.prelog;
+  if (task.kind != kTaskElite && task.inst != loaded) {
+    // every thread passed a barrier since the tables were last read
+    if constexpr (NT == 1)
+      load_tile<MODE>(I.T2, I.T1, LT, TPT, 0, LT, TR, sT);
+    else
+      load_own(I.Town, LT, TPT, sOwn);
+    loaded = task.inst;
+  }
+  int nc;
+  if constexpr (PF) {
+    if (task.kind == kTaskChild) {
+      int32_t *sPair = reinterpret_cast<int32_t *>(smem + P::kPairOff);
+      if (!prepared) {
+        pf_precompute(I, task, gen, smem + P::kCodeOff, sPair, BLOCK);
+        __syncthreads();
+      }
+      nc = pf_build(I, task, gen, sChild, sInv, smem + P::kCandOff, sPair,
+                    reinterpret_cast<int32_t *>(smem + P::kResOff), smem + P::kCodeOff, BLOCK);
+    } else {
+      nc = gen_prepare(I, task, gen, sChild, sInv, sIdx, sSel, BLOCK);
+    }
+  } else {
+    nc = gen_prepare(I, task, gen, sChild, sInv, sIdx, sSel, BLOCK);
+  }
+  if (nc == 0) return;
+  const int K = I.K;
+  const int q = threadIdx.x;
+  if constexpr (PF && NT == 1) {
+    // few chromosomes (persistent tasks): split the BS rows over all waves
+    const int lanes = nc * K;
+    int GS = kWave;
+    while (GS < lanes) GS <<= 1;
+    if (GS < BLOCK) {
+      const int rg = __builtin_amdgcn_readfirstlane(q / GS);
+      const int ql = q - rg * GS;
+      const bool act = ql < lanes;
+      const float acc = lane_sum_split<LT, TPT, MODE>(
+          sInv, ql, act, rg, BLOCK / GS, sT, reinterpret_cast<float *>(smem + P::kCandOff),
+          I.lconst);
+      reduce_round(sE, acc, act && rg == 0, nc, K, prelog, fit_out);
+      return;
+    }
+  }
+  const bool active = q / K < nc;
+  float acc;
+  if constexpr (NT == 1)
+    acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, I.T2, I.T1, I.lconst);
+  else
+    acc = lane_sum_tiled<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z, I.T1,
+                                            I.lconst);
+  reduce_round(sE, acc, active, nc, K, prelog, fit_out);
+}
+
+// Tasks [t0, t1) of one generation for a workgroup.
+template <int LT, int TPT, int MODE, int BLOCK, bool PF = false>
+__device__ __forceinline__ void gen_tasks_exact(const GenInst *insts, const GenTask *tasks,
+                                                int t0, int t1, int gen, unsigned char *smem,
+                                                int &loaded) {
+  for (int t = t0; t < t1; ++t) {
+    const GenTask task = load_task(tasks, t);
+    const GenInst I = insts[task.inst];
+    run_task<LT, TPT, MODE, BLOCK, PF>(I, task, gen, smem, loaded, false);
+  }
+}
+
+template <int LT, int TPT, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int t0 = blockIdx.x * a.chunk;
   const int t1 = min(a.ntasks, t0 + a.chunk);
   int loaded = -1;
-  for (int t = t0; t < t1; ++t) {
-    const GenTask task = a.tasks[t];
-    const GenInst &I = a.insts[task.inst];
-    if (a.gen >= I.G) continue;  // this instance has finished its generations
-    if (task.kind != kTaskElite && task.inst != loaded) {
-      // every thread passed a barrier since the tables were last read
-      if constexpr (NT == 1)
-        load_tile<MODE>(I.T2, I.T1, LT, TPT, 0, LT, TR, sT);
-      else
-        load_own(I.Town, LT, TPT, sOwn);
-      loaded = task.inst;
+  gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, loaded);
+}
+
+// ---- persistent form: generations [g0, g1) in one cooperative launch -------
+//
+// Every workgroup keeps the same chunk of tasks in every generation (so the
+// table of its instance stays in LDS) and the generations are separated by a
+// grid barrier: a monotonic arrival counter (zeroed before the launch) that
+// the barrier b waits to reach b * gridDim.x.  Global writes are released at
+// agent scope before the arrival and acquired after it.  A wait that exceeds
+// kBarrierSpins polls sets *err and every workgroup returns at its next
+// barrier, so the grid always drains.
+struct PersistArgs {
+  const GenInst *insts;
+  const GenTask *tasks;
+  int ntasks, chunk;
+  const GenTask *evals;
+  int neval, echunk;
+  int g0, g1;  // generations to run; g0 = -1 starts with the initial fitness
+  int best;    // nonzero: finish with the best of each instance's last population
+  int ninst;
+  uint32_t *bar;
+  int32_t *err;
+};
+
+constexpr uint32_t kBarrierSpins = 1u << 21;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t target, int32_t *err,
+                                             int32_t *sFlag) {
+  // every wave: its global writes complete and written back at agent scope
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int good = 1;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t spins = 0;; ++spins) {
+      if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+      if (spins >= kBarrierSpins ||
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
     }
-    const int nc = gen_prepare(I, task, a.gen, sChild, sInv, sIdx, sSel, BLOCK);
-    if (nc == 0) continue;
-    const int K = I.K;
-    const int q = threadIdx.x;
-    const bool active = q / K < nc;
-    float acc;
-    if constexpr (NT == 1)
-      acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, I.T2, I.T1, I.lconst);
-    else
-      acc = lane_sum_tiled<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z, I.T1,
-                                              I.lconst);
-    const int out = a.gen < 0 ? 0 : 1 - (a.gen & 1);
-    reduce_round(sE, acc, active, nc, K, I.prelog, I.fit[out] + task.s0);
+    *sFlag = good;
   }
+  __syncthreads();
+  const bool ok = *sFlag != 0;
+  // every wave: later reads see what other workgroups wrote before arriving
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return ok;
+}
+
+// Best chromosome of an instance's population after its last generation
+// (the whole workgroup; closes the trace).  idx: LDS.
+__device__ __forceinline__ void best_block(const GenInst &I, int32_t *idx) {
+  const float *fit = fit_buf(I, I.G & 1);
+  if (threadIdx.x < kWave) top_e_wave(fit, I.N, 1, idx, threadIdx.x);
+  __syncthreads();
+  const int b = idx[0];
+  if (threadIdx.x == 0) {
+    *gp(I.best_idx) = b;
+    *gp(I.best_fit) = gp(fit)[b];
+    gp(I.trace)[I.G] = gp(fit)[b];
+  }
+  const int LK = I.L * I.K;
+  const uint8_t *src = pop_buf(I, I.G & 1) + (size_t)b * LK;
+  for (int i = threadIdx.x; i < LK; i += blockDim.x) gp(I.best_out)[i] = gp(src)[i];
+  __syncthreads();
+}
+
+// Prefetching child tasks when the plan with their regions keeps the whole
+// table in LDS.
+template <int LT, int TPT, int MODE, int BLOCK>
+constexpr bool persist_prefetch() {
+  return GenPlan<LT, TPT, MODE, BLOCK, true>::kTiles == 1;
+}
+template <int LT, int TPT, int MODE, int BLOCK>
+using PersistPlan = GenPlan<LT, TPT, MODE, BLOCK, persist_prefetch<LT, TPT, MODE, BLOCK>()>;
+
+template <int LT, int TPT, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_gen_persist(PersistArgs a) {
+  constexpr bool PF = persist_prefetch<LT, TPT, MODE, BLOCK>();
+  using P = PersistPlan<LT, TPT, MODE, BLOCK>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  int32_t *sIdx = reinterpret_cast<int32_t *>(smem + P::kIdxOff);
+  int loaded = -1;
+  uint32_t nbar = 0;
+  // with one task per workgroup (the persistent plans), the workgroup's
+  // generation task and its descriptor are read once, into registers
+  const bool fixed = a.chunk == 1 && (int)blockIdx.x < a.ntasks;
+  GenTask mt{0, kTaskElite, 0, 0};
+  if (fixed) mt = load_task(a.tasks, blockIdx.x);
+  const GenInst mI = a.insts[mt.inst];
+  bool prepared = false;  // the child task of `gen` is prepared
+  for (int gen = a.g0; gen < a.g1; ++gen) {
+    if (gen < 0) {
+      const int t0 = blockIdx.x * a.echunk, t1 = min(a.neval, t0 + a.echunk);
+      gen_tasks_exact<LT, TPT, MODE, BLOCK, PF>(a.insts, a.evals, t0, t1, gen, smem, loaded);
+    } else if (fixed) {
+      run_task<LT, TPT, MODE, BLOCK, PF>(mI, mt, gen, smem, loaded, prepared);
+    } else {
+      const int t0 = blockIdx.x * a.chunk, t1 = min(a.ntasks, t0 + a.chunk);
+      gen_tasks_exact<LT, TPT, MODE, BLOCK, PF>(a.insts, a.tasks, t0, t1, gen, smem, loaded);
+    }
+    prepared = false;
+    if constexpr (PF) {
+      // prepare the next generation's child task while others finish this one
+      if (fixed && gen + 1 < a.g1 && mt.kind == kTaskChild && gen + 1 < mI.G) {
+        pf_precompute(mI, mt, gen + 1, smem + P::kCodeOff,
+                      reinterpret_cast<int32_t *>(smem + P::kPairOff), BLOCK);
+        prepared = true;
+      }
+    }
+    // sIdx[63] is free here: elite tasks use sIdx[0 .. E) with E < 64
+    if (!grid_barrier(a.bar, ++nbar * gridDim.x, a.err, sIdx + 63)) return;
+  }
+  if (a.best)
+    for (int i = blockIdx.x; i < a.ninst; i += gridDim.x) best_block(a.insts[i], sIdx);
 }
 
 // Runtime-L variant: L <= LMAX, any TP; the LDS plan comes from the host.
@@ -139,7 +502,7 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
   const int t1 = min(a.ntasks, t0 + a.chunk);
   int loaded = -1;
   for (int t = t0; t < t1; ++t) {
-    const GenTask task = a.tasks[t];
+    const GenTask task = load_task(a.tasks, t);
     const GenInst &I = a.insts[task.inst];
     if (a.gen >= I.G) continue;
     const int L = I.L, TP = I.TP, TR = pl.tile_rows;
@@ -156,7 +519,7 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
     const float acc =
         lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, I.T2, I.T1, I.lconst);
     const int out = a.gen < 0 ? 0 : 1 - (a.gen & 1);
-    reduce_round(sE, acc, active, nc, K, I.prelog, I.fit[out] + task.s0);
+    reduce_round(sE, acc, active, nc, K, I.prelog, fit_buf(I, out) + task.s0);
   }
 }
 
@@ -196,46 +559,88 @@ hipError_t gen_launch_exact(const GenInst *insts, const GenClass &c, int gen, hi
   return hipGetLastError();
 }
 
+// A persistent launch of a class (PersistArgs with the grid), or, when
+// `capacity` is set, only the query of the largest co-resident grid of the
+// class's persistent kernel.
+struct PersistCall {
+  PersistArgs args;
+  int grid;
+  int cus;
+  int *capacity;
+};
+
+template <int LT, int TPT, int MODE, int BLOCK>
+hipError_t gen_persist_exact(const PersistCall &pc, hipStream_t s) {
+  using P = PersistPlan<LT, TPT, MODE, BLOCK>;
+  auto kern = k_gen_persist<LT, TPT, MODE, BLOCK>;
+  static bool attr = false;
+  if (!attr) {
+    gen_allow_lds(reinterpret_cast<const void *>(kern), P::kTotal);
+    attr = true;
+  }
+  if (pc.capacity) {
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, reinterpret_cast<const void *>(kern), BLOCK, P::kTotal);
+    *pc.capacity = e == hipSuccess ? nb * pc.cus : 0;
+    return e;
+  }
+  PersistArgs a = pc.args;
+  void *args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(pc.grid),
+                                    dim3(BLOCK), args, P::kTotal, s);
+}
+
 template <int LT, int TPT, int MODE>
 hipError_t gen_dispatch_block(const GenInst *insts, const GenClass &c, int gen, hipStream_t s,
-                              bool *handled) {
+                              bool *handled, const PersistCall *pc) {
   *handled = true;
   switch (c.block) {
-    case 64: return gen_launch_exact<LT, TPT, MODE, 64>(insts, c, gen, s);
-    case 256: return gen_launch_exact<LT, TPT, MODE, 256>(insts, c, gen, s);
-    case 512: return gen_launch_exact<LT, TPT, MODE, 512>(insts, c, gen, s);
+    case 64:
+      return pc ? gen_persist_exact<LT, TPT, MODE, 64>(*pc, s)
+                : gen_launch_exact<LT, TPT, MODE, 64>(insts, c, gen, s);
+    case 256:
+      return pc ? gen_persist_exact<LT, TPT, MODE, 256>(*pc, s)
+                : gen_launch_exact<LT, TPT, MODE, 256>(insts, c, gen, s);
+    case 512:
+      return pc ? gen_persist_exact<LT, TPT, MODE, 512>(*pc, s)
+                : gen_launch_exact<LT, TPT, MODE, 512>(insts, c, gen, s);
     default: *handled = false; return hipSuccess;
   }
 }
 
-// Launches the unrolled generation kernel of cell count LT; *handled = false
-// when no unrolled variant serves (TP, mode, block).
+// Launches the unrolled generation kernel of cell count LT (its persistent
+// form when pc is set); *handled = false when no unrolled variant serves
+// (TP, mode, block).
 template <int LT>
 hipError_t gen_dispatch_L(const GenInst *insts, const GenClass &c, int gen, hipStream_t s,
-                          bool *handled) {
+                          bool *handled, const PersistCall *pc) {
   *handled = false;
   if (c.L != LT) return hipSuccess;
   if (c.mode == 0) {
     switch (c.TP) {
-      case 4: return gen_dispatch_block<LT, 4, 0>(insts, c, gen, s, handled);
-      case 8: return gen_dispatch_block<LT, 8, 0>(insts, c, gen, s, handled);
-      case 16: return gen_dispatch_block<LT, 16, 0>(insts, c, gen, s, handled);
-      case 32: return gen_dispatch_block<LT, 32, 0>(insts, c, gen, s, handled);
+      case 4: return gen_dispatch_block<LT, 4, 0>(insts, c, gen, s, handled, pc);
+      case 8: return gen_dispatch_block<LT, 8, 0>(insts, c, gen, s, handled, pc);
+      case 16: return gen_dispatch_block<LT, 16, 0>(insts, c, gen, s, handled, pc);
+      case 32: return gen_dispatch_block<LT, 32, 0>(insts, c, gen, s, handled, pc);
       default: return hipSuccess;
     }
   }
   switch (c.TP) {
-    case 4: return gen_dispatch_block<LT, 4, 1>(insts, c, gen, s, handled);
-    case 8: return gen_dispatch_block<LT, 8, 1>(insts, c, gen, s, handled);
-    case 16: return gen_dispatch_block<LT, 16, 1>(insts, c, gen, s, handled);
-    case 32: return gen_dispatch_block<LT, 32, 1>(insts, c, gen, s, handled);
+    case 4: return gen_dispatch_block<LT, 4, 1>(insts, c, gen, s, handled, pc);
+    case 8: return gen_dispatch_block<LT, 8, 1>(insts, c, gen, s, handled, pc);
+    case 16: return gen_dispatch_block<LT, 16, 1>(insts, c, gen, s, handled, pc);
+    case 32: return gen_dispatch_block<LT, 32, 1>(insts, c, gen, s, handled, pc);
     default: return hipSuccess;
   }
 }
 
-hipError_t gen_dispatch_L7(const GenInst *, const GenClass &, int, hipStream_t, bool *);
-hipError_t gen_dispatch_L19(const GenInst *, const GenClass &, int, hipStream_t, bool *);
-hipError_t gen_dispatch_L37(const GenInst *, const GenClass &, int, hipStream_t, bool *);
+hipError_t gen_dispatch_L7(const GenInst *, const GenClass &, int, hipStream_t, bool *,
+                           const PersistCall *);
+hipError_t gen_dispatch_L19(const GenInst *, const GenClass &, int, hipStream_t, bool *,
+                            const PersistCall *);
+hipError_t gen_dispatch_L37(const GenInst *, const GenClass &, int, hipStream_t, bool *,
+                            const PersistCall *);
 hipError_t gen_dispatch_generic(const GenInst *, const GenClass &, int, hipStream_t);
 
 }  // namespace pa

@@ -45,8 +45,7 @@ __global__ __launch_bounds__(kGaBlock) void k_ga_step(GaArgs a) {
   const int nc = min(a.cpw, N - s0);
   build_children_block(a.pin, a.fin, N, E, L, K, a.ga, a.gen, s0, nc, sChild, sHits, sSel,
                        (int)blockDim.x);
-  uint8_t *dst = a.pout + (size_t)s0 * LK;
-  for (int i = threadIdx.x; i < nc * LK; i += blockDim.x) dst[i] = sChild[i];
+  store_bytes(a.pout + (size_t)s0 * LK, sChild, nc * LK);
 }
 
 struct InitArgs {
@@ -92,7 +91,7 @@ __global__ __launch_bounds__(kGaBlock) void k_init_batch(const GenInst *insts) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int n = blockIdx.x * kGaWaves + wave;
   if (n < I.N) {
-    InitArgs a{I.seed, I.pop[0], I.L, I.K, I.N, I.ga};
+    InitArgs a{I.seed, pop_buf(I, 0), I.L, I.K, I.N, I.ga};
     init_individual(a, n, sbuf[wave], lane);
   }
 }
@@ -103,7 +102,7 @@ __global__ __launch_bounds__(kWave) void k_best_batch(const GenInst *insts, int 
   __shared__ int32_t idx[1];
   const GenInst &I = insts[blockIdx.x];
   const int G = gen < 0 ? I.G : (gen < I.G ? gen : I.G);
-  const float *fit = I.fit[G & 1];
+  const float *fit = fit_buf(I, G & 1);
   top_e_wave(fit, I.N, 1, idx, threadIdx.x);
   wave_sync();
   if (threadIdx.x == 0) {
@@ -112,7 +111,7 @@ __global__ __launch_bounds__(kWave) void k_best_batch(const GenInst *insts, int 
     I.trace[G] = fit[idx[0]];
   }
   const int LK = I.L * I.K;
-  const uint8_t *src = I.pop[G & 1] + (size_t)idx[0] * LK;
+  const uint8_t *src = pop_buf(I, G & 1) + (size_t)idx[0] * LK;
   for (int i = threadIdx.x; i < LK; i += kWave) I.best_out[i] = src[i];
 }
 

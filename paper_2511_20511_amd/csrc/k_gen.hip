@@ -71,11 +71,40 @@ hipError_t launch_gen(const GenInst *insts, const GenClass &c, int gen, const De
   (void)dev;
   bool handled = false;
   hipError_t e = hipSuccess;
-  if (c.L == 7) e = gen_dispatch_L7(insts, c, gen, s, &handled);
-  else if (c.L == 19) e = gen_dispatch_L19(insts, c, gen, s, &handled);
-  else if (c.L == 37) e = gen_dispatch_L37(insts, c, gen, s, &handled);
+  if (c.L == 7) e = gen_dispatch_L7(insts, c, gen, s, &handled, nullptr);
+  else if (c.L == 19) e = gen_dispatch_L19(insts, c, gen, s, &handled, nullptr);
+  else if (c.L == 37) e = gen_dispatch_L37(insts, c, gen, s, &handled, nullptr);
   if (handled) return e;
   return gen_dispatch_generic(insts, c, gen, s);
+}
+
+hipError_t launch_gen_persist(const GenInst *insts, const GenClass &c, const PersistLaunch &pl,
+                              const DeviceInfo &dev, int *capacity, hipStream_t s) {
+  PersistCall pc;
+  pc.args.insts = insts;
+  pc.args.tasks = c.tasks;
+  pc.args.ntasks = c.ntasks;
+  pc.args.chunk = (c.ntasks + pl.grid - 1) / (pl.grid > 0 ? pl.grid : 1);
+  pc.args.evals = c.eval_tasks;
+  pc.args.neval = c.neval;
+  pc.args.echunk = (c.neval + pl.grid - 1) / (pl.grid > 0 ? pl.grid : 1);
+  pc.args.g0 = pl.g0;
+  pc.args.g1 = pl.g1;
+  pc.args.best = pl.best;
+  pc.args.ninst = pl.ninst;
+  pc.args.bar = pl.bar;
+  pc.args.err = pl.err;
+  pc.grid = pl.grid;
+  pc.cus = dev.cus;
+  pc.capacity = capacity;
+  if (capacity) *capacity = 0;
+  bool handled = false;
+  hipError_t e = hipSuccess;
+  if (c.L == 7) e = gen_dispatch_L7(insts, c, 0, s, &handled, &pc);
+  else if (c.L == 19) e = gen_dispatch_L19(insts, c, 0, s, &handled, &pc);
+  else if (c.L == 37) e = gen_dispatch_L37(insts, c, 0, s, &handled, &pc);
+  if (!handled) return capacity ? hipSuccess : hipErrorNotSupported;
+  return e;
 }
 
 }  // namespace pa

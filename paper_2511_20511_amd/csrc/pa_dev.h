@@ -8,6 +8,20 @@ namespace pa {
 
 constexpr int kWave = 64;
 
+// A pointer into global memory that the compiler cannot place (read from a
+// descriptor in memory, or rebuilt from an integer) is generic, and generic
+// accesses become FLAT instructions, which also count against the LDS wait
+// counter: every LDS wait and workgroup barrier would then wait for the
+// outstanding global traffic too.  Accesses to global memory therefore go
+// through gp(p), the same pointer typed as global, which makes them global_*
+// instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> gp(T *p) {
+  return (gptr<T>)p;
+}
+
 // Stream tags of the counter word c3 = tag << 24 | block.
 enum : uint32_t {
   kTagSelect = 0x01u,
@@ -30,9 +44,11 @@ __device__ __forceinline__ Words4 philox10(uint32_t c0, uint32_t c1, uint32_t c2
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-    const uint32_t lo0 = m0 * c0, hi0 = __umulhi(m0, c0);
-    const uint32_t lo1 = m1 * c2, hi1 = __umulhi(m1, c2);
+    // one 32x32->64 multiply per product (both halves at once)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -83,22 +99,44 @@ __device__ __forceinline__ uint64_t full_key(float f, uint32_t idx) {
 }
 __device__ __forceinline__ uint32_t key_index(uint64_t k) { return 0xFFFFFFFFu - (uint32_t)k; }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const uint64_t o = __shfl_xor(v, off, kWave);
-    v = o > v ? o : v;
-  }
-  return v;
+// Wavefront reductions of 64-bit keys; every lane receives the result.  All
+// 64 lanes must be active.  Within each row of 16 lanes a butterfly of DPP
+// moves (quad xor 1, quad xor 2, half-row mirror, row mirror) leaves the row's
+// extremum in every lane of the row; the four row results are then read from
+// lanes 0, 16, 32 and 48.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const uint64_t o = __shfl_xor(v, off, kWave);
-    v = o < v ? o : v;
-  }
-  return v;
+template <int CTRL, bool MAX>
+__device__ __forceinline__ void dpp_step64(uint32_t &hi, uint32_t &lo) {
+  const uint32_t oh = dpp_mov<CTRL>(hi), ol = dpp_mov<CTRL>(lo);
+  const bool take = MAX ? (oh > hi || (oh == hi && ol > lo)) : (oh < hi || (oh == hi && ol < lo));
+  hi = take ? oh : hi;
+  lo = take ? ol : lo;
 }
+__device__ __forceinline__ uint64_t lane_u64(uint32_t hi, uint32_t lo, int lane) {
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, lane) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)lo, lane);
+}
+template <bool MAX>
+__device__ __forceinline__ uint64_t wave_reduce_u64(uint64_t v) {
+  uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+  dpp_step64<0xB1, MAX>(hi, lo);   // quad_perm [1,0,3,2]
+  dpp_step64<0x4E, MAX>(hi, lo);   // quad_perm [2,3,0,1]
+  dpp_step64<0x141, MAX>(hi, lo);  // row_half_mirror
+  dpp_step64<0x140, MAX>(hi, lo);  // row_mirror
+  const uint64_t r0 = lane_u64(hi, lo, 0), r1 = lane_u64(hi, lo, 16);
+  const uint64_t r2 = lane_u64(hi, lo, 32), r3 = lane_u64(hi, lo, 48);
+  if (MAX) {
+    const uint64_t a = r0 > r1 ? r0 : r1, b = r2 > r3 ? r2 : r3;
+    return a > b ? a : b;
+  }
+  const uint64_t a = r0 < r1 ? r0 : r1, b = r2 < r3 ? r2 : r3;
+  return a < b ? a : b;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) { return wave_reduce_u64<true>(v); }
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) { return wave_reduce_u64<false>(v); }
 
 // Byte ranges moved with aligned 32-bit loads, up to kCopyBatch loads in
 // flight per thread.  A range [src, src + n) is covered by the aligned words
@@ -114,8 +152,7 @@ struct ByteRange {
     return ((int)((uintptr_t)src & 3u) + n + 3) >> 2;
   }
   __device__ __forceinline__ uint32_t load(int w) const {
-    const uint32_t *base = reinterpret_cast<const uint32_t *>((uintptr_t)src & ~(uintptr_t)3);
-    return base[w];
+    return gp(reinterpret_cast<const uint32_t *>((uintptr_t)src & ~(uintptr_t)3))[w];
   }
   // byte offset in the range of byte b of word w (may fall outside [0, n))
   __device__ __forceinline__ int pos(int w, int b) const {
@@ -145,6 +182,31 @@ __device__ __forceinline__ void copy_bytes(const uint8_t *src, int n, uint8_t *d
         }
       }
     }
+  }
+}
+
+// Copies n bytes from LDS `src` to global `dst` (any alignment) with the
+// whole workgroup: 32-bit stores wherever dst is aligned, single bytes at the
+// two ends.
+__device__ __forceinline__ void store_bytes(uint8_t *dst, const uint8_t *src, int n) {
+  if (n <= 0) return;
+  const int lead = (int)((4u - ((uint32_t)(uintptr_t)dst & 3u)) & 3u);
+  const int head = lead < n ? lead : n;
+  const int nw = (n - head) >> 2;
+  const int tail0 = head + 4 * nw;
+  const int t = threadIdx.x;
+  if (t < head) gp(dst)[t] = src[t];
+  if (t < n - tail0) gp(dst)[tail0 + t] = src[tail0 + t];
+  gptr<uint32_t> dw = gp(reinterpret_cast<uint32_t *>(dst + head));
+  const uint8_t *s = src + head;
+  if (((uintptr_t)s & 3u) == 0) {
+    for (int w = t; w < nw; w += (int)blockDim.x) dw[w] = reinterpret_cast<const uint32_t *>(s)[w];
+    return;
+  }
+  for (int w = t; w < nw; w += (int)blockDim.x) {
+    const uint8_t *p = s + 4 * w;
+    dw[w] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) |
+            ((uint32_t)p[3] << 24);
   }
 }
 

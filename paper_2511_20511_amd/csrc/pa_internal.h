@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pa_dev.h"
+
 namespace pa {
 
 constexpr int kMaxL = 64;
@@ -77,6 +79,16 @@ struct GenInst {
   DevGa ga;
 };
 
+
+// Buffer b of an instance, by selection (no dynamic index, so a descriptor
+// copied into registers stays in registers).
+__device__ __forceinline__ uint8_t *pop_buf(const GenInst &I, int b) {
+  return b ? I.pop[1] : I.pop[0];
+}
+__device__ __forceinline__ float *fit_buf(const GenInst &I, int b) {
+  return b ? I.fit[1] : I.fit[0];
+}
+
 enum : int32_t { kTaskElite = 0, kTaskChild = 1, kTaskEval = 2 };
 
 // A unit of work of one generation launch: the elites of an instance, or the
@@ -122,6 +134,19 @@ hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStrea
 // gen = -1: fitness of the initial populations (the class's eval tasks).
 hipError_t launch_gen(const GenInst *insts, const GenClass &c, int gen, const DeviceInfo &dev,
                       hipStream_t s);
+// Persistent form: generations [g0, g1) of a class in one cooperative launch
+// of `grid` workgroups separated by grid barriers on the counter `bar`
+// (zeroed before the launch); a barrier wait that times out sets *err.  With
+// best != 0 it ends with the best of each of the first `ninst` instances.
+struct PersistLaunch {
+  int g0, g1, best, ninst, grid;
+  uint32_t *bar;
+  int32_t *err;
+};
+// capacity != null: only stores the largest co-resident grid of the class's
+// persistent kernel (0 when the class has none) and launches nothing.
+hipError_t launch_gen_persist(const GenInst *insts, const GenClass &c, const PersistLaunch &pl,
+                              const DeviceInfo &dev, int *capacity, hipStream_t s);
 // Best of each instance's population after generation `gen` (or after its
 // last generation when gen < 0); closes the trace at that generation.
 hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s);

@@ -1,9 +1,15 @@
 // solve.cpp -- whole solves of one instance (pa_solve) or many
 // (pa_solve_batch): a plan holds the device descriptors, task lists and
-// double-buffered populations of its instances; the whole solve (K-means
-// seeding, initial population and fitness, every generation, best of the
-// last population) is captured once into a hipGraph and replayed, so a solve
-// is one graph launch plus one copy of the results.
+// double-buffered populations of its instances.  Two execution forms:
+//  - graph: the whole solve (K-means seeding, initial population and
+//    fitness, one generation kernel per generation and class, best of the
+//    last population) is captured once into a hipGraph and replayed;
+//  - persistent: when the plan has one class whose tasks all fit on the
+//    device at once (small instances: the generation kernel would be a few
+//    microseconds of latency), every generation runs inside one cooperative
+//    launch separated by grid barriers, so the table stays in LDS and no
+//    per-generation launch is paid.
+// Either way a solve ends with one copy of the results.
 #include <algorithm>
 #include <cstring>
 
@@ -13,6 +19,7 @@ namespace pa {
 
 struct PlanClass {
   GenClass c;
+  int cpt_div = 1;  // children per task = ceil(block / K / cpt_div)
   GenTask *d_tasks = nullptr, *d_evals = nullptr;
 };
 
@@ -33,6 +40,9 @@ struct SolvePlan {
   std::vector<size_t> best_off;  // offsets into d_best
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  bool persist = false;          // persistent form (one class, co-resident tasks)
+  int pgrid = 0;                 // its workgroups
+  uint32_t *d_sync = nullptr;    // [0]: grid-barrier counter, [1]: barrier time-out flag
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int cur_gen = -1;  // stepwise solve: generations done (-1: not started)
   std::vector<int32_t> h_idx;
@@ -131,6 +141,102 @@ Shape choose_shape(const ClassKey &k, const std::vector<int> &members,
   return {256, div};
 }
 
+// Task lists (device) of a class of instances for a launch shape.
+pa_status make_class(SolvePlan *pl, const ClassKey &key, const std::vector<int> &members,
+                     const std::vector<GenInst> &hi, const Shape &sh, int cus, PlanClass *out) {
+  PlanClass pc;
+  pc.c.L = key.L;
+  pc.c.TP = key.TP;
+  pc.c.mode = key.mode;
+  pc.c.block = sh.block;
+  pc.cpt_div = sh.cpt_div;
+  std::vector<GenTask> tasks, evals;
+  for (int i : members) {
+    const int K = hi[i].K, N = hi[i].N, E = hi[i].E;
+    const int cpr = std::max(1, (pc.c.block / K + sh.cpt_div - 1) / sh.cpt_div);
+    tasks.push_back(GenTask{i, kTaskElite, 0, E});
+    for (int s = E; s < N; s += cpr) tasks.push_back(GenTask{i, kTaskChild, s, std::min(N, s + cpr)});
+    for (int s = 0; s < N; s += cpr) evals.push_back(GenTask{i, kTaskEval, s, std::min(N, s + cpr)});
+  }
+  const int lds = gen_lds_bytes(key.L, key.TP, key.mode, pc.c.block);
+  if (lds < 0) return set_error(PA_EUNSUPPORTED, "table of L=%d does not fit LDS", key.L);
+  int per_cu = 163840 / lds;
+  per_cu = std::max(1, std::min(per_cu, 2048 / pc.c.block));
+  pc.c.grid = std::min((int)tasks.size(), cus * per_cu);
+  pc.c.ntasks = (int)tasks.size();
+  pc.c.neval = (int)evals.size();
+  PTRY(alloc(pl, &pc.d_tasks, tasks.size()), "hipMalloc(tasks)");
+  PTRY(alloc(pl, &pc.d_evals, evals.size()), "hipMalloc(tasks)");
+  PTRY(hipMemcpy(pc.d_tasks, tasks.data(), sizeof(GenTask) * tasks.size(), hipMemcpyHostToDevice),
+       "upload");
+  PTRY(hipMemcpy(pc.d_evals, evals.data(), sizeof(GenTask) * evals.size(), hipMemcpyHostToDevice),
+       "upload");
+  pc.c.tasks = pc.d_tasks;
+  pc.c.eval_tasks = pc.d_evals;
+  *out = pc;
+  return PA_OK;
+}
+
+hipError_t launch_start(SolvePlan *pl, hipStream_t s);
+hipError_t launch_persist(SolvePlan *pl, const DeviceInfo &dev, int g0, int g1, bool best,
+                          hipStream_t s);
+
+// Autotuning of the persistent form: every candidate shape (children per
+// task = block / K / div for div = 1, 2, 4, ..., all tasks co-resident) runs
+// the start and the first generations of the plan's own instances; the
+// fastest is kept.  Shapes change the schedule, never a result bit.
+pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
+                          const std::vector<int> &members, const std::vector<GenInst> &hi,
+                          int block, int cap) {
+  int maxK = 0;
+  for (int i : members) maxK = std::max(maxK, hi[i].K);
+  std::vector<PlanClass> cands;
+  int last_tasks = -1;
+  for (int div = 1; div <= std::max(1, block / maxK); div *= 2) {
+    const int nt = count_tasks(members, pl->insts, pl->params, block, div);
+    if (nt > cap) break;
+    if (nt == last_tasks) continue;
+    last_tasks = nt;
+    PlanClass pc;
+    pa_status st = make_class(pl, key, members, hi, Shape{block, div}, ctx->info.cus, &pc);
+    if (st != PA_OK) return st;
+    cands.push_back(pc);
+  }
+  if (cands.empty()) return set_error(PA_EINTERNAL, "no persistent shape");
+  pl->persist = true;
+  size_t best = 0;
+  if (cands.size() > 1) {
+    hipStream_t cs = ctx->stream;
+    const int g1 = std::min(pl->Gmax, 16);
+    float best_ms = 0.0f;
+    for (size_t c = 0; c < cands.size(); ++c) {
+      pl->classes.assign(1, cands[c]);
+      pl->pgrid = cands[c].c.ntasks;
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {
+        PTRY(launch_start(pl, cs), "tuning");
+        PTRY(hipEventRecord(pl->ev0, cs), "hipEventRecord");
+        PTRY(launch_persist(pl, ctx->info, -1, g1, false, cs), "tuning");
+        PTRY(hipEventRecord(pl->ev1, cs), "hipEventRecord");
+        PTRY(hipEventSynchronize(pl->ev1), "hipEventSynchronize");
+        float t = 0.0f;
+        PTRY(hipEventElapsedTime(&t, pl->ev0, pl->ev1), "hipEventElapsedTime");
+        ms = rep == 0 ? t : std::min(ms, t);
+      }
+      uint32_t sync[2] = {0, 0};
+      PTRY(hipMemcpy(sync, pl->d_sync, sizeof sync, hipMemcpyDeviceToHost), "tuning");
+      if (sync[1] != 0) return set_error(PA_EINTERNAL, "persistent solve: a grid barrier wait timed out");
+      if (c == 0 || ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+  }
+  pl->classes.assign(1, cands[best]);
+  pl->pgrid = cands[best].c.ntasks;
+  return PA_OK;
+}
+
 pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
                      const pa_ga_params *params, SolvePlan **out) {
   SolvePlan *pl = new (std::nothrow) SolvePlan;
@@ -210,38 +316,49 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
     else it->second.push_back(i);
   }
   const int cus = ctx->info.cus;
-  for (auto &grp : groups) {
-    const ClassKey &key = grp.first;
-    PlanClass pc;
-    pc.c.L = key.L;
-    pc.c.TP = key.TP;
-    pc.c.mode = key.mode;
-    const Shape sh = choose_shape(key, grp.second, pl->insts, pl->params, cus);
-    pc.c.block = sh.block;
-    std::vector<GenTask> tasks, evals;
-    for (int i : grp.second) {
-      const int K = hi[i].K, N = hi[i].N, E = hi[i].E;
-      const int cpr = std::max(1, (pc.c.block / K + sh.cpt_div - 1) / sh.cpt_div);
-      tasks.push_back(GenTask{i, kTaskElite, 0, E});
-      for (int s = E; s < N; s += cpr) tasks.push_back(GenTask{i, kTaskChild, s, std::min(N, s + cpr)});
-      for (int s = 0; s < N; s += cpr) evals.push_back(GenTask{i, kTaskEval, s, std::min(N, s + cpr)});
+  // persistent form: one class with an unrolled variant whose full tasks
+  // (block / K children each) all fit on the device at once
+  Shape pshape{0, 1};
+  int pcap = 0;
+  if (groups.size() == 1 && exact_variant(groups[0].first.L, groups[0].first.TP)) {
+    const ClassKey &key = groups[0].first;
+    GenClass q;
+    q.L = key.L;
+    q.TP = key.TP;
+    q.mode = key.mode;
+    q.block = tiled(key.L, key.TP, key.mode, 256) ? 512 : 256;
+    int cap = 0;
+    PersistLaunch ql{};
+    ql.grid = 1;
+    PTRY(launch_gen_persist(pl->d_insts, q, ql, ctx->info, &cap, nullptr), "occupancy query");
+    if (cap > 0 && count_tasks(groups[0].second, pl->insts, pl->params, q.block) <= cap) {
+      pshape = Shape{q.block, 1};
+      pcap = cap;
     }
-    const int lds = gen_lds_bytes(key.L, key.TP, key.mode, pc.c.block);
-    if (lds < 0) return set_error(PA_EUNSUPPORTED, "table of L=%d does not fit LDS", key.L);
-    int per_cu = 163840 / lds;
-    per_cu = std::max(1, std::min(per_cu, 2048 / pc.c.block));
-    pc.c.grid = std::min((int)tasks.size(), cus * per_cu);
-    pc.c.ntasks = (int)tasks.size();
-    pc.c.neval = (int)evals.size();
-    PTRY(alloc(pl, &pc.d_tasks, tasks.size()), "hipMalloc(tasks)");
-    PTRY(alloc(pl, &pc.d_evals, evals.size()), "hipMalloc(tasks)");
-    PTRY(hipMemcpy(pc.d_tasks, tasks.data(), sizeof(GenTask) * tasks.size(), hipMemcpyHostToDevice),
-         "upload");
-    PTRY(hipMemcpy(pc.d_evals, evals.data(), sizeof(GenTask) * evals.size(), hipMemcpyHostToDevice),
-         "upload");
-    pc.c.tasks = pc.d_tasks;
-    pc.c.eval_tasks = pc.d_evals;
-    pl->classes.push_back(pc);
+  }
+  PTRY(alloc(pl, &pl->d_sync, 2), "hipMalloc(plan)");
+  PTRY(hipMemset(pl->d_sync, 0, 2 * sizeof(uint32_t)), "hipMemset");
+  PTRY(hipEventCreate(&pl->ev0), "hipEventCreate");
+  PTRY(hipEventCreate(&pl->ev1), "hipEventCreate");
+  if (pshape.block) {
+    pa_status st = tune_persistent(pl, ctx, groups[0].first, groups[0].second, hi, pshape.block, pcap);
+    if (st != PA_OK) return st;
+  } else {
+    for (auto &grp : groups) {
+      const Shape sh = choose_shape(grp.first, grp.second, pl->insts, pl->params, cus);
+      PlanClass pc;
+      pa_status st = make_class(pl, grp.first, grp.second, hi, sh, cus, &pc);
+      if (st != PA_OK) return st;
+      pl->classes.push_back(pc);
+    }
+  }
+  pl->h_idx.resize(n);
+  pl->h_fit.resize(n);
+  pl->h_trace.resize((size_t)n * TG);
+  pl->h_best.resize(best_total);
+  if (pl->persist) {
+    *out = guard.release();
+    return PA_OK;
   }
   // capture the whole solve
   hipStream_t cs = ctx->stream;
@@ -263,12 +380,6 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
   PTRY(e2, "hipStreamEndCapture");
   pl->graph = graph;
   PTRY(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
-  PTRY(hipEventCreate(&pl->ev0), "hipEventCreate");
-  PTRY(hipEventCreate(&pl->ev1), "hipEventCreate");
-  pl->h_idx.resize(n);
-  pl->h_fit.resize(n);
-  pl->h_trace.resize((size_t)n * TG);
-  pl->h_best.resize(best_total);
   *out = guard.release();
   return PA_OK;
 }
@@ -278,9 +389,38 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
 // the trace (< 0: each instance's full trace).
 pa_status copy_results(SolvePlan *pl, hipStream_t s, pa_result *results, int gens_done);
 
-pa_status run_plan(SolvePlan *pl, hipStream_t s, pa_result *results) {
+// Persistent launch of generations [g0, g1) of the plan's single class.
+hipError_t launch_persist(SolvePlan *pl, const DeviceInfo &dev, int g0, int g1, bool best,
+                          hipStream_t s) {
+  hipError_t e = hipMemsetAsync(pl->d_sync, 0, sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
+  PersistLaunch L{};
+  L.g0 = g0;
+  L.g1 = g1;
+  L.best = best ? 1 : 0;
+  L.ninst = (int)pl->insts.size();
+  L.grid = pl->pgrid;
+  L.bar = pl->d_sync;
+  L.err = reinterpret_cast<int32_t *>(pl->d_sync + 1);
+  return launch_gen_persist(pl->d_insts, pl->classes[0].c, L, dev, nullptr, s);
+}
+
+// Seeding, initial population and (persistent form) the time-out flag.
+hipError_t launch_start(SolvePlan *pl, hipStream_t s) {
+  hipError_t e = launch_kmeans_batch(pl->d_insts, pl->d_which, pl->nwhich, s);
+  if (e == hipSuccess) e = launch_init_batch(pl->d_insts, (int)pl->insts.size(), pl->maxN, s);
+  if (e == hipSuccess && pl->persist) e = hipMemsetAsync(pl->d_sync, 0, 2 * sizeof(uint32_t), s);
+  return e;
+}
+
+pa_status run_plan(SolvePlan *pl, const DeviceInfo &dev, hipStream_t s, pa_result *results) {
   PTRY(hipEventRecord(pl->ev0, s), "hipEventRecord");
-  PTRY(hipGraphLaunch(pl->exec, s), "hipGraphLaunch");
+  if (pl->persist) {
+    PTRY(launch_start(pl, s), "launching the solve");
+    PTRY(launch_persist(pl, dev, -1, pl->Gmax, true, s), "persistent generation kernel");
+  } else {
+    PTRY(hipGraphLaunch(pl->exec, s), "hipGraphLaunch");
+  }
   PTRY(hipEventRecord(pl->ev1, s), "hipEventRecord");
   return copy_results(pl, s, results, -1);
 }
@@ -297,7 +437,11 @@ pa_status copy_results(SolvePlan *pl, hipStream_t s, pa_result *results, int gen
        "copy results");
   PTRY(hipMemcpyAsync(pl->h_best.data(), pl->d_best, pl->h_best.size(), hipMemcpyDeviceToHost, s),
        "copy results");
+  uint32_t sync[2] = {0, 0};
+  PTRY(hipMemcpyAsync(sync, pl->d_sync, sizeof sync, hipMemcpyDeviceToHost, s), "copy results");
   PTRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (sync[1] != 0)
+    return set_error(PA_EINTERNAL, "persistent solve: a grid barrier wait timed out");
   float ms = 0.0f;
   PTRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1), "hipEventElapsedTime");
   for (int i = 0; i < n; ++i) {
@@ -344,7 +488,7 @@ pa_status pa_solve(pa_instance *in, const pa_ga_params *g, pa_result *out, void 
     in->plan = nullptr;
     if ((st = build_plan(in->ctx, 1, &in, g, &in->plan)) != PA_OK) return st;
   }
-  return run_plan(in->plan, (hipStream_t)stream, out);
+  return run_plan(in->plan, in->ctx->info, (hipStream_t)stream, out);
 }
 
 pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
@@ -366,7 +510,7 @@ pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
     ctx->batch_plan = nullptr;
     if ((st = build_plan(ctx, n, insts, params, &ctx->batch_plan)) != PA_OK) return st;
   }
-  return run_plan(ctx->batch_plan, (hipStream_t)stream, results);
+  return run_plan(ctx->batch_plan, ctx->info, (hipStream_t)stream, results);
 }
 
 pa_status pa_solve_begin(pa_instance *in, const pa_ga_params *g, void *stream) {
@@ -381,9 +525,9 @@ pa_status pa_solve_begin(pa_instance *in, const pa_ga_params *g, void *stream) {
   }
   SolvePlan *pl = in->plan;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_kmeans_batch(pl->d_insts, pl->d_which, pl->nwhich, s);
-  if (e == hipSuccess) e = launch_init_batch(pl->d_insts, 1, pl->maxN, s);
-  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess; ++c)
+  hipError_t e = launch_start(pl, s);
+  if (e == hipSuccess && pl->persist) e = launch_persist(pl, in->ctx->info, -1, 0, false, s);
+  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess && !pl->persist; ++c)
     e = launch_gen(pl->d_insts, pl->classes[c].c, -1, in->ctx->info, s);
   if (e != hipSuccess) return hip_error(e, "pa_solve_begin");
   pl->cur_gen = 0;
@@ -400,6 +544,13 @@ pa_status pa_solve_next(pa_instance *in, int32_t ngens, void *stream) {
   pa_status st = use_device(in->ctx);
   if (st != PA_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (pl->persist) {
+    if (ngens == 0) return PA_OK;
+    hipError_t e = launch_persist(pl, in->ctx->info, pl->cur_gen, pl->cur_gen + ngens, false, s);
+    if (e != hipSuccess) return hip_error(e, "pa_solve_next");
+    pl->cur_gen += ngens;
+    return PA_OK;
+  }
   for (int k = 0; k < ngens; ++k) {
     for (size_t c = 0; c < pl->classes.size(); ++c) {
       hipError_t e = launch_gen(pl->d_insts, pl->classes[c].c, pl->cur_gen, in->ctx->info, s);
@@ -422,6 +573,19 @@ pa_status pa_solve_state(pa_instance *in, pa_result *out, int32_t *gens_done, vo
   PTRY(hipEventRecord(pl->ev1, s), "hipEventRecord");
   if (gens_done) *gens_done = pl->cur_gen;
   return copy_results(pl, s, out, pl->cur_gen);
+}
+
+pa_status pa_solve_shape(pa_context *ctx, pa_instance *in, int32_t *persistent, int32_t *block,
+                         int32_t *children_per_task, int32_t *workgroups) {
+  const SolvePlan *pl = in ? in->plan : (ctx ? ctx->batch_plan : nullptr);
+  if (!pl) return set_error(PA_EINVAL, "no solve plan (solve first)");
+  const PlanClass &pc = pl->classes[0];
+  const int K = pl->insts[0]->p.K;
+  if (persistent) *persistent = pl->persist ? 1 : 0;
+  if (block) *block = pc.c.block;
+  if (children_per_task) *children_per_task = std::max(1, (pc.c.block / K + pc.cpt_div - 1) / pc.cpt_div);
+  if (workgroups) *workgroups = pl->persist ? pl->pgrid : pc.c.grid;
+  return PA_OK;
 }
 
 }  // extern "C"
