@@ -252,6 +252,58 @@ pa_status pa_fitness_shaped(pa_instance *inst, const uint8_t *d_pop, int32_t n, 
 pa_status pa_solve_shape(pa_context *ctx, pa_instance *inst, int32_t *persistent, int32_t *block,
                          int32_t *children_per_task, int32_t *workgroups);
 
+/* ---- continuous-batching server -------------------------------------- */
+
+/* Many independent solves arriving over time (not in the paper; the serving
+ * form of the batched solve).  A server owns a worker thread, a HIP stream and
+ * `slots` device arenas, each sized for the largest request it accepts
+ * (max_L, max_K, max_pop, max_gens); the number of slots is the smaller of
+ * max_slots and hbm_budget / (bytes of one slot).  Each tick the worker
+ * admits queued requests into free slots, runs ONE generation of every
+ * resident request (each at its own generation; one launch per class of
+ * (L, padded K, SE mode)), and returns the requests that reached their last
+ * generation.  A request's result is bit-identical to pa_solve of the same
+ * problem and parameters.
+ *   max_slots   resident requests at most (0 = 512)
+ *   max_queue   waiting requests at most; beyond, submit returns PA_EAGAIN
+ *               (0 = 1048576)
+ *   max_L, max_K, max_pop, max_gens   largest accepted request
+ *               (0 = 37, 32, 1024, 1000)
+ *   hbm_budget  bytes of device memory for the slots (0 = 80% of free) */
+typedef struct pa_server_cfg {
+  int32_t max_slots, max_queue;
+  int32_t max_L, max_K, max_pop, max_gens;
+  double hbm_budget;
+} pa_server_cfg;
+
+typedef struct pa_server_counters {
+  int32_t slots, resident, queued;
+  uint64_t submitted, completed, ticks;
+  double slot_bytes;
+} pa_server_counters;
+
+/* Creates a server on the context's device (cfg may be NULL for defaults).
+ * PA_ENOMEM when the budget holds no slot.  Blocking. */
+pa_status pa_server_create(pa_context *ctx, const pa_server_cfg *cfg, pa_server **out);
+/* Queues a request: the problem's host arrays are copied, so the caller may
+ * reuse them at once.  *ticket identifies it.  PA_EINVAL for an invalid
+ * problem or parameters or one larger than the slots, PA_EAGAIN when the
+ * queue is full.  Thread-safe. */
+pa_status pa_server_submit(pa_server *srv, const pa_problem *prob, const pa_ga_params *params,
+                           uint64_t *ticket);
+/* Result of a request: fills out as pa_solve would (best and trace are
+ * HOST, caller-allocated, L*K bytes and gens+1 floats, either may be NULL);
+ * device_ms = time from submit to the result being on the host, in ms.
+ * block = 0: PA_EAGAIN while the request runs; block != 0: waits.  A ticket
+ * can be polled successfully once.  Thread-safe. */
+pa_status pa_server_poll(pa_server *srv, uint64_t ticket, pa_result *out, int32_t block);
+/* Counters of the server.  Thread-safe. */
+pa_status pa_server_stats(pa_server *srv, pa_server_counters *out);
+/* Stops the worker after its current tick and frees the server; requests
+ * not yet polled are dropped.  No other call on srv may run concurrently with
+ * or after it. */
+void pa_server_destroy(pa_server *srv);
+
 /* ---- diagnostics ------------------------------------------------------ */
 
 /* After pa_kmeans_init with kmeans_frac > 0: copies the K-means state to

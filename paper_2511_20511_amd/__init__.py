@@ -23,7 +23,8 @@ __all__ = [
     "pa_context_create", "pa_context_destroy", "pa_instance_create", "pa_instance_destroy",
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
-    "pa_solve_shape",
+    "pa_solve_shape", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
+    "pa_server_destroy", "Server",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
     "SE_ASYMPTOTIC", "SE_FINITE_M",
@@ -80,6 +81,20 @@ class GaParams:
                        self.instance_id & 0xFFFFFFFF)
 
 
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("max_queue", ctypes.c_int32),
+                ("max_L", ctypes.c_int32), ("max_K", ctypes.c_int32),
+                ("max_pop", ctypes.c_int32), ("max_gens", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_double)]
+
+
+class _ServerCounters(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("resident", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("submitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("ticks", ctypes.c_uint64),
+                ("slot_bytes", ctypes.c_double)]
+
+
 @dataclass
 class Result:
     best: np.ndarray
@@ -121,6 +136,12 @@ def lib():
         "pa_solve_state": (st, [vp, ctypes.POINTER(_Result), ctypes.POINTER(i32), vp]),
         "pa_solve_shape": (st, [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                 ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "pa_server_create": (st, [vp, ctypes.POINTER(_ServerCfg), ctypes.POINTER(vp)]),
+        "pa_server_submit": (st, [vp, ctypes.POINTER(_Problem), ctypes.POINTER(_Params),
+                                  ctypes.POINTER(ctypes.c_uint64)]),
+        "pa_server_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(_Result), i32]),
+        "pa_server_stats": (st, [vp, ctypes.POINTER(_ServerCounters)]),
+        "pa_server_destroy": (None, [vp]),
         "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
         "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
         "pa_status_string": (ctypes.c_char_p, [st]),
@@ -358,3 +379,73 @@ def pa_instance_kmeans_state(inst: Instance):
     _check(lib().pa_instance_kmeans_state(inst.h, seed.ctypes.data, cent.ctypes.data,
                                           labels.ctypes.data, iters.ctypes.data))
     return seed, cent, labels, int(iters[0])
+
+
+# ---- continuous-batching server ---------------------------------------------
+
+PA_EAGAIN = -4
+
+
+class Server:
+    """Handle of a pa_server; remembers (L, K, gens) of every pending ticket so
+    that poll can size the result arrays."""
+
+    def __init__(self, ctx: Context, max_slots=0, max_queue=0, max_L=0, max_K=0, max_pop=0,
+                 max_gens=0, hbm_budget=0.0):
+        cfg = _ServerCfg(int(max_slots), int(max_queue), int(max_L), int(max_K), int(max_pop),
+                         int(max_gens), float(hbm_budget))
+        self.h = ctypes.c_void_p()
+        _check(lib().pa_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(self.h)))
+        self.ctx = ctx
+        self._shape = {}
+
+    def close(self):
+        if self.h:
+            lib().pa_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pa_server_create(ctx: Context, **cfg) -> Server:
+    return Server(ctx, **cfg)
+
+
+def pa_server_destroy(srv: Server):
+    srv.close()
+
+
+def pa_server_submit(srv: Server, beta, user_xy=None, bs_xy=None, params: GaParams = None, T=0,
+                     M=1, rho=1.0, se_mode=SE_ASYMPTOTIC) -> int:
+    """Queues one solve; returns its ticket (the arrays are copied)."""
+    host = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode)
+    p = params.to_c()
+    t = ctypes.c_uint64(0)
+    _check(lib().pa_server_submit(srv.h, ctypes.byref(host.c), ctypes.byref(p), ctypes.byref(t)))
+    srv._shape[t.value] = (host.L, host.K, params.gens)
+    return int(t.value)
+
+
+def pa_server_poll(srv: Server, ticket: int, block: bool = True):
+    """Result of a ticket (device_ms = submit-to-result time in ms), or None
+    while it runs (block=False)."""
+    L, K, G = srv._shape[ticket]
+    best = np.zeros((L, K), dtype=np.uint8)
+    trace = np.zeros(G + 1, dtype=np.float32)
+    r = _Result(best.ctypes.data, 0.0, 0, trace.ctypes.data, 0.0)
+    st = lib().pa_server_poll(srv.h, ctypes.c_uint64(ticket), ctypes.byref(r), 1 if block else 0)
+    if st == PA_EAGAIN and not block:
+        return None
+    _check(st)
+    del srv._shape[ticket]
+    return Result(best, float(r.best_fit), int(r.best_index), trace, float(r.device_ms))
+
+
+def pa_server_stats(srv: Server) -> dict:
+    c = _ServerCounters()
+    _check(lib().pa_server_stats(srv.h, ctypes.byref(c)))
+    return {f: getattr(c, f) for f, _ in c._fields_}

@@ -18,8 +18,9 @@ struct GenArgs {
   const GenInst *insts;
   const GenTask *tasks;
   int ntasks;
-  int chunk;  // tasks per workgroup
-  int gen;    // -1: fitness of the initial populations
+  int chunk;           // tasks per workgroup
+  int gen;             // -1: fitness of the initial populations
+  const int32_t *gens; // non-null: a task's generation is gens[task.inst] (gen ignored)
 };
 
 // LDS plan: table tile | children (<= block*L) | inverse rows, aliased by the
@@ -344,15 +345,17 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task, 
   reduce_round(sE, acc, active, nc, K, prelog, fit_out);
 }
 
-// Tasks [t0, t1) of one generation for a workgroup.
+// Tasks [t0, t1) of one generation for a workgroup (gens: per-instance
+// generations, or null for `gen`).
 template <int LT, int TPT, int MODE, int BLOCK, bool PF = false>
 __device__ __forceinline__ void gen_tasks_exact(const GenInst *insts, const GenTask *tasks,
                                                 int t0, int t1, int gen, unsigned char *smem,
-                                                int &loaded) {
+                                                int &loaded, const int32_t *gens = nullptr) {
   for (int t = t0; t < t1; ++t) {
     const GenTask task = load_task(tasks, t);
     const GenInst I = insts[task.inst];
-    run_task<LT, TPT, MODE, BLOCK, PF>(I, task, gen, smem, loaded, false);
+    const int g = gens ? gp(gens)[task.inst] : gen;
+    run_task<LT, TPT, MODE, BLOCK, PF>(I, task, g, smem, loaded, false);
   }
 }
 
@@ -362,7 +365,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
   const int t0 = blockIdx.x * a.chunk;
   const int t1 = min(a.ntasks, t0 + a.chunk);
   int loaded = -1;
-  gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, loaded);
+  gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, loaded, a.gens);
 }
 
 // ---- persistent form: generations [g0, g1) in one cooperative launch -------
@@ -504,21 +507,22 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
   for (int t = t0; t < t1; ++t) {
     const GenTask task = load_task(a.tasks, t);
     const GenInst &I = a.insts[task.inst];
-    if (a.gen >= I.G) continue;
+    const int gen = a.gens ? gp(a.gens)[task.inst] : a.gen;
+    if (gen >= I.G) continue;
     const int L = I.L, TP = I.TP, TR = pl.tile_rows;
     if (TR >= L && task.kind != kTaskElite && task.inst != loaded) {
       __syncthreads();
       load_tile<MODE>(I.T2, I.T1, L, TP, 0, L, TR, sT);
       loaded = task.inst;
     }
-    const int nc = gen_prepare(I, task, a.gen, sChild, sInv, sIdx, sSel, (int)blockDim.x);
+    const int nc = gen_prepare(I, task, gen, sChild, sInv, sIdx, sSel, (int)blockDim.x);
     if (nc == 0) continue;
     const int K = I.K;
     const int q = threadIdx.x;
     const bool active = q / K < nc;
     const float acc =
         lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, I.T2, I.T1, I.lconst);
-    const int out = a.gen < 0 ? 0 : 1 - (a.gen & 1);
+    const int out = gen < 0 ? 0 : 1 - (gen & 1);
     reduce_round(sE, acc, active, nc, K, I.prelog, fit_buf(I, out) + task.s0);
   }
 }
@@ -537,8 +541,9 @@ inline GenArgs gen_args(const GenInst *insts, const GenClass &c, int gen, int gr
   GenArgs a;
   a.insts = insts;
   a.gen = gen;
-  a.tasks = gen < 0 ? c.eval_tasks : c.tasks;
-  a.ntasks = gen < 0 ? c.neval : c.ntasks;
+  a.gens = c.gens;
+  a.tasks = (gen < 0 && !c.gens) ? c.eval_tasks : c.tasks;
+  a.ntasks = (gen < 0 && !c.gens) ? c.neval : c.ntasks;
   a.chunk = (a.ntasks + grid - 1) / grid;
   return a;
 }

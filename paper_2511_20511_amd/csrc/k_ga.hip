@@ -85,9 +85,10 @@ __global__ __launch_bounds__(kGaBlock) void k_init_pop(InitArgs a) {
 }
 
 // blockIdx.y = instance; individuals beyond an instance's N do nothing.
-__global__ __launch_bounds__(kGaBlock) void k_init_batch(const GenInst *insts) {
+__global__ __launch_bounds__(kGaBlock) void k_init_batch(const GenInst *insts,
+                                                          const int32_t *which) {
   __shared__ __attribute__((aligned(16))) uint8_t sbuf[kGaWaves][kMaxGenes];
-  const GenInst &I = insts[blockIdx.y];
+  const GenInst &I = insts[which ? which[blockIdx.y] : (int)blockIdx.y];
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int n = blockIdx.x * kGaWaves + wave;
   if (n < I.N) {
@@ -98,9 +99,10 @@ __global__ __launch_bounds__(kGaBlock) void k_init_batch(const GenInst *insts) {
 
 // One wave per instance: best of its final population, which also closes
 // its trace.
-__global__ __launch_bounds__(kWave) void k_best_batch(const GenInst *insts, int gen) {
+__global__ __launch_bounds__(kWave) void k_best_batch(const GenInst *insts, int gen,
+                                                       const int32_t *which) {
   __shared__ int32_t idx[1];
-  const GenInst &I = insts[blockIdx.x];
+  const GenInst &I = insts[which ? which[blockIdx.x] : (int)blockIdx.x];
   const int G = gen < 0 ? I.G : (gen < I.G ? gen : I.G);
   const float *fit = fit_buf(I, G & 1);
   top_e_wave(fit, I.N, 1, idx, threadIdx.x);
@@ -115,16 +117,18 @@ __global__ __launch_bounds__(kWave) void k_best_batch(const GenInst *insts, int 
   for (int i = threadIdx.x; i < LK; i += kWave) I.best_out[i] = src[i];
 }
 
-hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStream_t s) {
+hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStream_t s,
+                             const int32_t *which) {
   if (ninst <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_batch, dim3((maxN + kGaWaves - 1) / kGaWaves, ninst), dim3(kGaBlock),
-                     0, s, insts);
+                     0, s, insts, which);
   return hipGetLastError();
 }
 
-hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s) {
+hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s,
+                             const int32_t *which) {
   if (ninst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_best_batch, dim3(ninst), dim3(kWave), 0, s, insts, gen);
+  hipLaunchKernelGGL(k_best_batch, dim3(ninst), dim3(kWave), 0, s, insts, gen, which);
   return hipGetLastError();
 }
 

@@ -50,4 +50,9 @@ pa_status validate_ga(const pa_instance *inst, const pa_ga_params *g);
 DevGa ga_from_params(const pa_ga_params *g);
 pa_status ensure_work(pa_instance *in, int N, int G);
 pa_status use_device(pa_context *ctx);
+// Launch shape of a class of instances for the generation kernel: threads
+// per workgroup (maxK = the largest K of the class), and workgroups for
+// ntasks tasks (0 when the table does not fit LDS).
+int gen_class_block(int L, int TP, int mode, int maxK);
+int gen_class_grid(int L, int TP, int mode, int block, int ntasks, int cus);
 }  // namespace pa

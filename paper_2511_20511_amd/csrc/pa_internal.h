@@ -106,6 +106,9 @@ struct GenClass {
   int ntasks = 0;
   const GenTask *eval_tasks = nullptr;  // device: initial-population fitness
   int neval = 0;
+  // non-null: the launch runs `tasks` with each instance at its own
+  // generation gens[inst] (device; -1 = the initial fitness, eval tasks)
+  const int32_t *gens = nullptr;
 };
 
 // ---- launchers (return hipSuccess or the first HIP error) ----------------
@@ -130,7 +133,9 @@ hipError_t launch_best(const float *fit, int N, int32_t *best_idx, float *best_f
 int gen_children_per_task(int L, int K, int TP, int mode, int block);
 int gen_default_block(int L, int TP, int mode);
 hipError_t launch_kmeans_batch(const GenInst *insts, const int32_t *which, int n, hipStream_t s);
-hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStream_t s);
+// which (device, may be null = 0..ninst-1): the instances to initialise.
+hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStream_t s,
+                             const int32_t *which = nullptr);
 // gen = -1: fitness of the initial populations (the class's eval tasks).
 hipError_t launch_gen(const GenInst *insts, const GenClass &c, int gen, const DeviceInfo &dev,
                       hipStream_t s);
@@ -149,6 +154,7 @@ hipError_t launch_gen_persist(const GenInst *insts, const GenClass &c, const Per
                               const DeviceInfo &dev, int *capacity, hipStream_t s);
 // Best of each instance's population after generation `gen` (or after its
 // last generation when gen < 0); closes the trace at that generation.
-hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s);
+hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s,
+                             const int32_t *which = nullptr);
 
 }  // namespace pa

@@ -1,0 +1,574 @@
+// server.cpp -- continuous-batching solve server (pa_server_*).
+//
+// Requests (a problem and GA parameters) are queued by any thread; one worker
+// thread per server owns a HIP stream and a fixed set of slots, each a device
+// arena sized for the configured maximum problem.  The number of slots is set
+// by the HBM budget.  Every tick the worker
+//   1. admits queued requests into free slots (upload, per-BS normalisation,
+//      descriptor), and seeds them (K-means, initial population);
+//   2. runs ONE generation for every resident request -- each at its own
+//      generation number, read per task from a device array -- with one
+//      launch of the fused generation kernel per class of (L, padded K, SE
+//      mode) (admitted requests get their initial fitness in the same
+//      launches);
+//   3. for requests that reached their last generation, takes the best
+//      chromosome, copies the result to pinned host memory and frees the
+//      slot.
+// Requests therefore join and leave the running batch between generations.
+// A request's result is bit-identical to pa_solve of the same instance.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "pa_host.h"
+
+namespace pa {
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Request {
+  uint64_t ticket = 0;
+  pa_problem prob{};  // arrays point into the vectors below
+  std::vector<double> beta, user_xy, bs_xy;
+  pa_ga_params params{};
+  bool done = false;
+  pa_status status = PA_OK;
+  std::string error;
+  std::vector<uint8_t> best;
+  std::vector<float> trace;
+  float best_fit = 0.0f;
+  int32_t best_index = 0;
+  double t_submit = 0.0, t_done = 0.0;
+};
+
+// Device arena of one slot (sized for the configured maxima) and the pinned
+// host staging of its result.
+struct Slot {
+  DevProblem p;
+  uint8_t *pop[2] = {nullptr, nullptr};
+  float *fit[2] = {nullptr, nullptr};
+  uint8_t *result = nullptr;  // device: best_idx | best_fit | trace[Gmax+1] | best[Lmax*Kmax]
+  uint8_t *h_result = nullptr;  // pinned copy of `result`
+  Request *req = nullptr;
+  int gen = 0;  // next generation to run (-1: initial fitness)
+};
+
+}  // namespace
+}  // namespace pa
+
+struct pa_server {
+  pa_context *ctx = nullptr;
+  pa_server_cfg cfg{};
+  hipStream_t stream = nullptr;
+  std::vector<pa::Slot> slots;
+  void *arena = nullptr;          // device memory of every slot
+  void *pinned = nullptr;         // pinned staging (results, descriptors, tasks)
+  size_t slot_bytes = 0;
+  size_t result_bytes = 0;        // per slot
+  pa::GenInst *d_insts = nullptr, *h_insts = nullptr;
+  int32_t *d_gens = nullptr, *h_gens = nullptr;
+  int32_t *d_which = nullptr, *h_which = nullptr;  // [3][nslots]: kmeans | init | best lists
+  pa::GenTask *d_tasks = nullptr, *h_tasks = nullptr;
+  size_t task_cap = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<pa::Request *> queue;
+  std::unordered_map<uint64_t, pa::Request *> reqs;
+  uint64_t next_ticket = 1;
+  int resident = 0;
+  bool stop = false;
+  pa_status failed = PA_OK;
+  std::string fail_msg;
+  uint64_t submitted = 0, completed = 0, ticks = 0;
+  std::thread worker;
+};
+
+namespace pa {
+namespace {
+
+// Sub-allocation of a slot's arena (the same layout for every slot).
+struct SlotLayout {
+  size_t beta, T2, T1, T2z, Town, lconst, user_xy, bs_xy, seed, cent, labels, iters, pop0, pop1,
+      fit0, fit1, result, total;
+};
+
+SlotLayout layout(const pa_server_cfg &c, size_t *result_bytes) {
+  const size_t L = c.max_L, K = c.max_K, TP = pad_pilots(c.max_K), N = c.max_pop;
+  SlotLayout a{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += up256(bytes);
+    return at;
+  };
+  a.beta = take(8 * L * L * K);
+  a.T2 = take(4 * L * L * TP);
+  a.T1 = take(4 * L * L * TP);
+  a.T2z = take(4 * L * L * TP);
+  a.Town = take(4 * L * TP);
+  a.lconst = take(4 * 2 * L);
+  a.user_xy = take(8 * L * K * 2);
+  a.bs_xy = take(8 * L * 2);
+  a.seed = take(L * K);
+  a.cent = take(4 * 2 * K);
+  a.labels = take(4 * L * K);
+  a.iters = take(4);
+  a.pop0 = take(N * L * K);
+  a.pop1 = take(N * L * K);
+  a.fit0 = take(4 * N);
+  a.fit1 = take(4 * N);
+  *result_bytes = up256(8 + 4 * ((size_t)c.max_gens + 1) + L * K);
+  a.result = take(*result_bytes);
+  a.total = o;
+  return a;
+}
+
+void fail_all(pa_server *S, pa_status st, const std::string &msg) {
+  // caller holds S->mu
+  for (auto &kv : S->reqs) {
+    pa::Request *r = kv.second;
+    if (!r->done) {
+      r->done = true;
+      r->status = st;
+      r->error = msg;
+      r->t_done = now_s();
+    }
+  }
+  S->queue.clear();
+  for (auto &sl : S->slots) sl.req = nullptr;
+  S->resident = 0;
+}
+
+// Uploads request r into slot i and writes its descriptor.
+hipError_t admit(pa_server *S, int i, Request *r) {
+  Slot &sl = S->slots[i];
+  sl.req = r;
+  sl.gen = -1;
+  const pa_problem &pr = r->prob;
+  DevProblem &p = sl.p;
+  p.L = pr.L;
+  p.K = pr.K;
+  p.TP = pad_pilots(pr.K);
+  p.se_mode = pr.se_mode;
+  p.prelog = pr.T > 0 ? (float)(1.0 - (double)pr.K / (double)pr.T) : 1.0f;
+  const size_t L = p.L, K = p.K;
+  hipStream_t s = S->stream;
+  hipError_t e = hipMemcpyAsync(p.beta, r->beta.data(), 8 * L * L * K, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemsetAsync(p.lconst, 0, 4 * 2 * L, s);
+  if (e == hipSuccess) e = hipMemsetAsync(p.km_iters, 0, 4, s);
+  if (e == hipSuccess && pr.user_xy) {
+    e = hipMemcpyAsync(p.user_xy, r->user_xy.data(), 8 * L * K * 2, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p.bs_xy, r->bs_xy.data(), 8 * L * 2, hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess) e = launch_prep(p, pr.M, pr.rho, s);
+  if (e != hipSuccess) return e;
+  GenInst &I = S->h_insts[i];
+  std::memset(&I, 0, sizeof I);
+  I.T2 = p.T2;
+  I.T1 = p.T1;
+  I.T2z = p.T2z;
+  I.Town = p.Town;
+  I.lconst = p.lconst;
+  I.pop[0] = sl.pop[0];
+  I.pop[1] = sl.pop[1];
+  I.fit[0] = sl.fit[0];
+  I.fit[1] = sl.fit[1];
+  I.best_idx = reinterpret_cast<int32_t *>(sl.result);
+  I.best_fit = reinterpret_cast<float *>(sl.result + 4);
+  I.trace = reinterpret_cast<float *>(sl.result + 8);
+  I.best_out = sl.result + 8 + 4 * ((size_t)S->cfg.max_gens + 1);
+  I.user_xy = pr.user_xy ? p.user_xy : nullptr;
+  I.bs_xy = pr.user_xy ? p.bs_xy : nullptr;
+  I.seed = p.seed;
+  I.km_cent = p.km_cent;
+  I.km_labels = p.km_labels;
+  I.km_iters = p.km_iters;
+  I.L = p.L;
+  I.K = p.K;
+  I.TP = p.TP;
+  I.N = r->params.pop;
+  I.E = r->params.elite;
+  I.G = r->params.gens;
+  I.prelog = p.prelog;
+  I.se_mode = p.se_mode;
+  I.ga = ga_from_params(&r->params);
+  return hipMemcpyAsync(S->d_insts + i, &S->h_insts[i], sizeof(GenInst), hipMemcpyHostToDevice, s);
+}
+
+struct ClassKey {
+  int L, TP, mode;
+  bool operator<(const ClassKey &o) const {
+    return L != o.L ? L < o.L : TP != o.TP ? TP < o.TP : mode < o.mode;
+  }
+};
+
+// One tick; returns the first HIP error.
+hipError_t tick(pa_server *S, std::vector<int> &finished) {
+  const int ns = (int)S->slots.size();
+  hipStream_t s = S->stream;
+  std::vector<int> fresh;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    for (int i = 0; i < ns && !S->queue.empty(); ++i) {
+      if (S->slots[i].req) continue;
+      Request *r = S->queue.front();
+      S->queue.pop_front();
+      S->slots[i].req = r;  // reserved; uploaded below
+      S->slots[i].gen = -1;
+      ++S->resident;
+      fresh.push_back(i);
+    }
+  }
+  hipError_t e = hipSuccess;
+  int nkm = 0;
+  int32_t *kmw = S->h_which, *initw = S->h_which + ns, *bestw = S->h_which + 2 * ns;
+  int maxN = 0;
+  for (int i : fresh) {
+    if (e == hipSuccess) e = admit(S, i, S->slots[i].req);
+    const Request *r = S->slots[i].req;
+    if (r->params.kmeans_frac > 0.0) kmw[nkm++] = i;
+    maxN = std::max(maxN, r->params.pop);
+  }
+  for (size_t k = 0; k < fresh.size(); ++k) initw[k] = fresh[k];
+  if (e == hipSuccess && !fresh.empty()) {
+    e = hipMemcpyAsync(S->d_which, S->h_which, sizeof(int32_t) * 2 * ns, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_kmeans_batch(S->d_insts, S->d_which, nkm, s);
+    if (e == hipSuccess)
+      e = launch_init_batch(S->d_insts, (int)fresh.size(), maxN, s, S->d_which + ns);
+  }
+  // tasks of every resident request at its own generation, by class
+  std::map<ClassKey, std::vector<int>> classes;
+  for (int i = 0; i < ns; ++i) {
+    const Slot &sl = S->slots[i];
+    if (!sl.req) continue;
+    classes[ClassKey{sl.p.L, sl.p.TP, sl.p.se_mode}].push_back(i);
+    S->h_gens[i] = sl.gen;
+  }
+  size_t nt = 0;
+  struct Launch {
+    GenClass c;
+    size_t off;
+  };
+  std::vector<Launch> launches;
+  for (auto &kv : classes) {
+    int maxK = 0;
+    for (int i : kv.second) maxK = std::max(maxK, S->slots[i].p.K);
+    GenClass c;
+    c.L = kv.first.L;
+    c.TP = kv.first.TP;
+    c.mode = kv.first.mode;
+    c.block = gen_class_block(c.L, c.TP, c.mode, maxK);
+    const size_t off = nt;
+    for (int i : kv.second) {
+      const Slot &sl = S->slots[i];
+      const int N = sl.req->params.pop, E = sl.req->params.elite, K = sl.p.K;
+      const int cpr = std::max(1, c.block / K);
+      if (sl.gen < 0) {
+        for (int a = 0; a < N; a += cpr)
+          S->h_tasks[nt++] = GenTask{i, kTaskEval, a, std::min(N, a + cpr)};
+      } else {
+        S->h_tasks[nt++] = GenTask{i, kTaskElite, 0, E};
+        for (int a = E; a < N; a += cpr)
+          S->h_tasks[nt++] = GenTask{i, kTaskChild, a, std::min(N, a + cpr)};
+      }
+    }
+    c.ntasks = (int)(nt - off);
+    c.grid = gen_class_grid(c.L, c.TP, c.mode, c.block, c.ntasks, S->ctx->info.cus);
+    launches.push_back(Launch{c, off});
+  }
+  if (e == hipSuccess && nt > 0) {
+    e = hipMemcpyAsync(S->d_tasks, S->h_tasks, sizeof(GenTask) * nt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(S->d_gens, S->h_gens, sizeof(int32_t) * ns, hipMemcpyHostToDevice, s);
+    for (auto &L : launches) {
+      if (e != hipSuccess) break;
+      L.c.tasks = S->d_tasks + L.off;
+      L.c.gens = S->d_gens;
+      e = launch_gen(S->d_insts, L.c, 0, S->ctx->info, s);
+    }
+  }
+  // advance; requests past their last generation finish
+  int nb = 0;
+  finished.clear();
+  for (int i = 0; i < ns; ++i) {
+    Slot &sl = S->slots[i];
+    if (!sl.req) continue;
+    ++sl.gen;
+    if (sl.gen >= sl.req->params.gens) {
+      bestw[nb++] = i;
+      finished.push_back(i);
+    }
+  }
+  if (e == hipSuccess && nb > 0) {
+    e = hipMemcpyAsync(S->d_which + 2 * ns, bestw, sizeof(int32_t) * nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_best_batch(S->d_insts, nb, -1, s, S->d_which + 2 * ns);
+    for (int i : finished) {
+      if (e != hipSuccess) break;
+      const Slot &sl = S->slots[i];
+      e = hipMemcpyAsync(sl.h_result, sl.result, S->result_bytes, hipMemcpyDeviceToHost, s);
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+void complete(pa_server *S, const std::vector<int> &finished) {
+  const double t = now_s();
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (int i : finished) {
+    Slot &sl = S->slots[i];
+    Request *r = sl.req;
+    const size_t LK = (size_t)sl.p.L * sl.p.K;
+    const uint8_t *h = sl.h_result;
+    std::memcpy(&r->best_index, h, 4);
+    std::memcpy(&r->best_fit, h + 4, 4);
+    r->trace.assign(reinterpret_cast<const float *>(h + 8),
+                    reinterpret_cast<const float *>(h + 8) + r->params.gens + 1);
+    const uint8_t *b = h + 8 + 4 * ((size_t)S->cfg.max_gens + 1);
+    r->best.assign(b, b + LK);
+    r->done = true;
+    r->t_done = t;
+    sl.req = nullptr;
+    --S->resident;
+    ++S->completed;
+  }
+  S->cv_done.notify_all();
+}
+
+void worker_main(pa_server *S) {
+  (void)hipSetDevice(S->ctx->device);
+  std::vector<int> finished;
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || S->resident > 0; });
+      if (S->stop) return;
+    }
+    const hipError_t e = tick(S, finished);
+    if (e != hipSuccess) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->failed = PA_EDEVICE;
+      S->fail_msg = std::string("server worker: ") + hipGetErrorString(e);
+      fail_all(S, PA_EDEVICE, S->fail_msg);
+      S->cv_done.notify_all();
+      return;
+    }
+    ++S->ticks;
+    if (!finished.empty()) complete(S, finished);
+  }
+}
+
+void free_server(pa_server *S) {
+  if (!S) return;
+  if (S->ctx) (void)hipSetDevice(S->ctx->device);
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  if (S->arena) (void)hipFree(S->arena);
+  if (S->d_insts) (void)hipFree(S->d_insts);
+  if (S->d_gens) (void)hipFree(S->d_gens);
+  if (S->d_which) (void)hipFree(S->d_which);
+  if (S->d_tasks) (void)hipFree(S->d_tasks);
+  if (S->pinned) (void)hipHostFree(S->pinned);
+  if (S->stream) (void)hipStreamDestroy(S->stream);
+  for (auto &kv : S->reqs) delete kv.second;
+  delete S;
+}
+
+}  // namespace
+}  // namespace pa
+
+using namespace pa;
+
+extern "C" {
+
+pa_status pa_server_create(pa_context *ctx, const pa_server_cfg *cfg, pa_server **out) {
+  if (!ctx || !out) return set_error(PA_EINVAL, "context or out is NULL");
+  *out = nullptr;
+  pa_server_cfg c{};
+  if (cfg) c = *cfg;
+  if (c.max_slots == 0) c.max_slots = 512;
+  if (c.max_queue == 0) c.max_queue = 1 << 20;
+  if (c.max_L == 0) c.max_L = 37;
+  if (c.max_K == 0) c.max_K = 32;
+  if (c.max_pop == 0) c.max_pop = 1024;
+  if (c.max_gens == 0) c.max_gens = 1000;
+  if (c.max_slots < 1 || c.max_queue < 1 || c.max_L < 1 || c.max_L > kMaxL || c.max_K < 1 ||
+      c.max_K > kMaxK || c.max_pop < 2 || c.max_pop > 65536 || c.max_gens < 1 ||
+      c.hbm_budget < 0.0)
+    return set_error(PA_EINVAL, "server configuration out of range");
+  pa_status st = use_device(ctx);
+  if (st != PA_OK) return st;
+  pa_server *S = new (std::nothrow) pa_server;
+  if (!S) return set_error(PA_ENOMEM, "host allocation failed");
+  std::unique_ptr<pa_server, void (*)(pa_server *)> guard(S, free_server);
+  S->ctx = ctx;
+  size_t result_bytes = 0;
+  const SlotLayout lay = layout(c, &result_bytes);
+  S->slot_bytes = lay.total;
+  S->result_bytes = result_bytes;
+  double budget = c.hbm_budget;
+  if (budget == 0.0) {
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return set_error(PA_EDEVICE, "hipMemGetInfo");
+    budget = 0.8 * (double)freeb;
+  }
+  const long fit = (long)(budget / (double)lay.total);
+  if (fit < 1) return set_error(PA_ENOMEM, "HBM budget %.0f B holds no slot of %zu B", budget, lay.total);
+  const int ns = (int)std::min<long>(c.max_slots, fit);
+  c.max_slots = ns;
+  c.hbm_budget = budget;
+  S->cfg = c;
+  S->slots.resize(ns);
+  S->task_cap = (size_t)ns * (c.max_pop + 1);
+  hipError_t e = hipMalloc(&S->arena, lay.total * ns);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_insts), sizeof(GenInst) * ns);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_gens), sizeof(int32_t) * ns);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_which), sizeof(int32_t) * 3 * ns);
+  if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_tasks), sizeof(GenTask) * S->task_cap);
+  const size_t pin_bytes = up256(result_bytes * ns) + up256(sizeof(GenInst) * ns) +
+                           up256(sizeof(int32_t) * 4 * ns) + sizeof(GenTask) * S->task_cap;
+  if (e == hipSuccess) e = hipHostMalloc(&S->pinned, pin_bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_error(e, "server allocation");
+  uint8_t *pin = static_cast<uint8_t *>(S->pinned);
+  uint8_t *h_results = pin;
+  pin += up256(result_bytes * ns);
+  S->h_insts = reinterpret_cast<GenInst *>(pin);
+  pin += up256(sizeof(GenInst) * ns);
+  S->h_gens = reinterpret_cast<int32_t *>(pin);
+  S->h_which = S->h_gens + ns;
+  pin += up256(sizeof(int32_t) * 4 * ns);
+  S->h_tasks = reinterpret_cast<GenTask *>(pin);
+  for (int i = 0; i < ns; ++i) {
+    uint8_t *b = static_cast<uint8_t *>(S->arena) + lay.total * i;
+    Slot &sl = S->slots[i];
+    sl.p.beta = reinterpret_cast<double *>(b + lay.beta);
+    sl.p.T2 = reinterpret_cast<float *>(b + lay.T2);
+    sl.p.T1 = reinterpret_cast<float *>(b + lay.T1);
+    sl.p.T2z = reinterpret_cast<float *>(b + lay.T2z);
+    sl.p.Town = reinterpret_cast<float *>(b + lay.Town);
+    sl.p.lconst = reinterpret_cast<float *>(b + lay.lconst);
+    sl.p.user_xy = reinterpret_cast<double *>(b + lay.user_xy);
+    sl.p.bs_xy = reinterpret_cast<double *>(b + lay.bs_xy);
+    sl.p.seed = b + lay.seed;
+    sl.p.km_cent = reinterpret_cast<int32_t *>(b + lay.cent);
+    sl.p.km_labels = reinterpret_cast<int32_t *>(b + lay.labels);
+    sl.p.km_iters = reinterpret_cast<int32_t *>(b + lay.iters);
+    sl.pop[0] = b + lay.pop0;
+    sl.pop[1] = b + lay.pop1;
+    sl.fit[0] = reinterpret_cast<float *>(b + lay.fit0);
+    sl.fit[1] = reinterpret_cast<float *>(b + lay.fit1);
+    sl.result = b + lay.result;
+    sl.h_result = h_results + result_bytes * i;
+  }
+  S->worker = std::thread(worker_main, S);
+  *out = guard.release();
+  return PA_OK;
+}
+
+pa_status pa_server_submit(pa_server *S, const pa_problem *prob, const pa_ga_params *params,
+                           uint64_t *ticket) {
+  if (!S || !prob || !params || !ticket) return set_error(PA_EINVAL, "NULL argument");
+  pa_status st = pa_params_check(prob, params);
+  if (st != PA_OK) return st;
+  if (prob->L > S->cfg.max_L || prob->K > S->cfg.max_K || params->pop > S->cfg.max_pop ||
+      params->gens > S->cfg.max_gens)
+    return set_error(PA_EINVAL, "request (L=%d K=%d pop=%d gens=%d) exceeds the server's slots "
+                     "(L<=%d K<=%d pop<=%d gens<=%d)", prob->L, prob->K, params->pop,
+                     params->gens, S->cfg.max_L, S->cfg.max_K, S->cfg.max_pop, S->cfg.max_gens);
+  Request *r = new (std::nothrow) Request;
+  if (!r) return set_error(PA_ENOMEM, "host allocation failed");
+  const size_t L = prob->L, K = prob->K;
+  r->beta.assign(prob->beta, prob->beta + L * L * K);
+  if (prob->user_xy) {
+    r->user_xy.assign(prob->user_xy, prob->user_xy + L * K * 2);
+    r->bs_xy.assign(prob->bs_xy, prob->bs_xy + L * 2);
+  }
+  r->prob = *prob;
+  r->prob.beta = r->beta.data();
+  r->prob.user_xy = prob->user_xy ? r->user_xy.data() : nullptr;
+  r->prob.bs_xy = prob->user_xy ? r->bs_xy.data() : nullptr;
+  r->params = *params;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->failed != PA_OK) {
+      delete r;
+      return set_error(S->failed, "%s", S->fail_msg.c_str());
+    }
+    if ((long)S->queue.size() >= S->cfg.max_queue) {
+      delete r;
+      return set_error(PA_EAGAIN, "queue full (%d requests)", S->cfg.max_queue);
+    }
+    r->ticket = S->next_ticket++;
+    r->t_submit = now_s();
+    S->queue.push_back(r);
+    S->reqs[r->ticket] = r;
+    ++S->submitted;
+    *ticket = r->ticket;
+  }
+  S->cv_work.notify_one();
+  return PA_OK;
+}
+
+pa_status pa_server_poll(pa_server *S, uint64_t ticket, pa_result *out, int32_t block) {
+  if (!S || !out) return set_error(PA_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return set_error(PA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  Request *r = it->second;
+  if (!r->done) {
+    if (!block) return set_error(PA_EAGAIN, "ticket %llu not done", (unsigned long long)ticket);
+    S->cv_done.wait(lk, [&] { return r->done; });
+  }
+  const pa_status st = r->status;
+  if (st == PA_OK) {
+    if (out->best) std::memcpy(out->best, r->best.data(), r->best.size());
+    if (out->trace) std::memcpy(out->trace, r->trace.data(), sizeof(float) * r->trace.size());
+    out->best_fit = r->best_fit;
+    out->best_index = r->best_index;
+    out->device_ms = (r->t_done - r->t_submit) * 1e3;
+  }
+  const std::string msg = r->error;
+  S->reqs.erase(it);
+  delete r;
+  if (st != PA_OK) return set_error(st, "%s", msg.c_str());
+  return PA_OK;
+}
+
+pa_status pa_server_stats(pa_server *S, pa_server_counters *out) {
+  if (!S || !out) return set_error(PA_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out->slots = (int32_t)S->slots.size();
+  out->resident = S->resident;
+  out->queued = (int32_t)S->queue.size();
+  out->submitted = S->submitted;
+  out->completed = S->completed;
+  out->ticks = S->ticks;
+  out->slot_bytes = (double)S->slot_bytes;
+  return PA_OK;
+}
+
+void pa_server_destroy(pa_server *S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();  // finishes its current tick
+  free_server(S);
+}
+
+}  // extern "C"

@@ -472,6 +472,22 @@ bool plan_matches(const SolvePlan *pl, int n, pa_instance *const *insts, const p
 }
 
 }  // namespace
+
+int gen_class_block(int L, int TP, int mode, int maxK) {
+  if (!exact_variant(L, TP)) return std::max(256, (maxK + 63) / 64 * 64);
+  return tiled(L, TP, mode, 256) ? 512 : 256;
+}
+
+int gen_class_grid(int L, int TP, int mode, int block, int ntasks, int cus) {
+  const int lds = gen_lds_bytes(L, TP, mode, block);
+  if (lds < 0) return 0;
+  int per_cu = 163840 / lds;
+  per_cu = std::max(1, std::min(per_cu, 2048 / block));
+  return std::max(1, std::min(ntasks, cus * per_cu));
+}
+
+namespace {
+}  // namespace
 }  // namespace pa
 
 using namespace pa;
