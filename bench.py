@@ -51,21 +51,31 @@ def cpu_baseline(drop, w, budget_s=12.0):
             "sample": f"{solves} full oracle solve(s) of the same workload ({el:.1f} s, FP64, 1 thread)"}
 
 
+def workload_sizes(scenario, w, n):
+    """(L, K, N) of the n instances of a workload (uniform, or the uneven size mix)."""
+    if w.get("mix"):
+        return scenario.size_mix(n, w["seed"])
+    return [(w["L"], w["K"], w["N"])] * n
+
+
 def run_batch(pa, scenario, torch, name):
     """Many independent instances in one graph-captured batch: evals/s and solves/s."""
     import numpy as np
     w = dict(scenario.WORKLOADS[name])
-    L, K, N, G, E, n = w["L"], w["K"], w["N"], w["gens"], w["E"], w["instances"]
+    G, E, n = w["gens"], w["E"], w["instances"]
+    sizes = workload_sizes(scenario, w, n)
     ctx = pa.pa_context_create(0)
     insts, params = [], []
-    for i in range(n):
+    for i, (L, K, N) in enumerate(sizes):
         d = scenario.make_drop(L, K, seed=w["seed"], instance_id=i)
         insts.append(pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=w["T"], M=w["M"],
                                            rho=scenario.snr_to_rho(w["snr_db"])))
         params.append(pa.GaParams(pop=N, gens=G, elite=E, p_cross=w["p_cross"], p_mut=w["p_mut"],
                                   kmeans_frac=w["kmeans_frac"], p_init=w["p_init"],
                                   seed=w["seed"], instance_id=i))
+    t0 = time.perf_counter()
     pa.pa_solve_batch(ctx, insts, params)  # builds and captures the plan
+    plan_s = time.perf_counter() - t0
     reps = 3
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -74,16 +84,136 @@ def run_batch(pa, scenario, torch, name):
         res = pa.pa_solve_batch(ctx, insts, params)
         dev.append(res[0].device_ms)
     wall = (time.perf_counter() - t0) / reps
-    ev = n * evals_per_solve(N, E, G)
-    gathers = n * (N + (N - E) * G) * L * L * K
-    out = {"workload": name, "instances": n, "L": L, "K": K, "pop": N, "gens": G,
+    ev = sum(evals_per_solve(N, E, G) for (_, _, N) in sizes)
+    gathers = sum((N + (N - E) * G) * L * L * K for (L, K, N) in sizes)
+    out = {"workload": name, "instances": n, "gens": G,
+           "sizes": "size_mix: L {7,19,37}, K [4,32], N [128,1024]" if w.get("mix") else
+           f"L={sizes[0][0]} K={sizes[0][1]} N={sizes[0][2]}",
            "ms_per_batch": wall * 1e3, "device_ms": float(np.median(dev)),
+           "plan_build_s": plan_s,
            "evals_per_s": ev / wall, "solves_per_s": n / wall,
            "lds_gbs": gathers * 4 / wall / 1e9,
            "lds_frac_of_peak": gathers * 4 / wall / 1e9 / LDS_PEAK_GBS,
-           "best_fit_first": res[0].best_fit}
+           "solve_plan": pa.pa_solve_shape(ctx, None)}
     log(f"batch {name}: {wall * 1e3:.1f} ms, {ev / wall:.3e} evals/s, {n / wall:.1f} solves/s, "
         f"LDS {out['lds_gbs']:.0f} GB/s ({100 * out['lds_frac_of_peak']:.1f}%)")
+    for inst in insts:
+        inst.close()
+    return out
+
+
+def run_serve(pa, scenario, torch, name, seconds, plain_sample):
+    """Poisson arrivals of uneven solves through the continuous-batching server:
+    solves/s and p50/p99 latency (scheduled arrival -> result on the host),
+    beside a FIFO one-instance-at-a-time plain path on the same arrival trace."""
+    import numpy as np
+    w = dict(scenario.WORKLOADS[name])
+    G, E, P = w["gens"], w["E"], w["pool"]
+    sizes = scenario.size_mix(P, w["seed"])
+    drops = [scenario.make_drop(L, K, seed=w["seed"], instance_id=i)
+             for i, (L, K, N) in enumerate(sizes)]
+    rho = scenario.snr_to_rho(w["snr_db"])
+    arrivals = scenario.poisson_arrivals(w["rate"], seconds, w["seed"])
+    n = len(arrivals)
+
+    def params(i):
+        return pa.GaParams(pop=sizes[i % P][2], gens=G, elite=E, p_cross=w["p_cross"],
+                           p_mut=w["p_mut"], kmeans_frac=w["kmeans_frac"], p_init=w["p_init"],
+                           seed=w["seed"] + i, instance_id=i)
+
+    ctx = pa.pa_context_create(0)
+    srv = pa.pa_server_create(ctx, max_L=37, max_K=32, max_pop=1024, max_gens=G)
+    # warm-up: one request of each size class
+    for i in range(min(P, 16)):
+        d = drops[i]
+        t = pa.pa_server_submit(srv, d.beta, d.user_xy, d.bs_xy, params(i), T=w["T"], M=w["M"],
+                                rho=rho)
+        pa.pa_server_poll(srv, t)
+    tickets = []
+    t_submit = np.zeros(n)
+    t0 = time.perf_counter()
+    for i in range(n):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        d = drops[i % P]
+        t_submit[i] = time.perf_counter() - t0
+        tickets.append(pa.pa_server_submit(srv, d.beta, d.user_xy, d.bs_xy, params(i), T=w["T"],
+                                           M=w["M"], rho=rho))
+    lat = np.zeros(n)
+    for i, t in enumerate(tickets):
+        r = pa.pa_server_poll(srv, t)
+        lat[i] = (t_submit[i] - arrivals[i]) + r.device_ms * 1e-3
+    t_end = time.perf_counter() - t0
+    stats = pa.pa_server_stats(srv)
+    srv.close()
+    done = arrivals + lat
+    solves_per_s = n / (done.max() - arrivals[0])
+    # plain comparator: measured pa_solve_plain service time of each pool entry,
+    # FIFO over the same arrival trace
+    svc = np.zeros(P)
+    m = min(P, plain_sample)
+    for i in range(m):
+        d = drops[i]
+        inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=w["T"], M=w["M"], rho=rho)
+        pa.pa_solve_plain(inst, params(i))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pa.pa_solve_plain(inst, params(i))
+        svc[i] = time.perf_counter() - t1
+        inst.close()
+    if m < P:
+        svc[m:] = np.resize(svc[:m], P - m)
+    fin = 0.0
+    plat = np.zeros(n)
+    for i in range(n):
+        fin = max(arrivals[i], fin) + svc[i % P]
+        plat[i] = fin - arrivals[i]
+    out = {"workload": name, "rate_per_s": w["rate"], "seconds": seconds, "requests": n,
+           "gens": G, "sizes": "size_mix: L {7,19,37}, K [4,32], N [128,1024]",
+           "solves_per_s": solves_per_s,
+           "p50_ms": float(np.percentile(lat, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "slots": stats["slots"], "ticks": stats["ticks"],
+           "plain": {"kind": "FIFO pa_solve_plain, one instance at a time, same arrival trace "
+                             "(measured service time per pool entry)",
+                     "mean_service_ms": float(svc.mean() * 1e3),
+                     "solves_per_s": n / (fin - arrivals[0]) if n else 0.0,
+                     "p50_ms": float(np.percentile(plat, 50) * 1e3),
+                     "p99_ms": float(np.percentile(plat, 99) * 1e3)}}
+    log(f"serve {name}: {n} requests in {t_end:.1f} s, {solves_per_s:.0f} solves/s, "
+        f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms; plain FIFO: "
+        f"{out['plain']['solves_per_s']:.0f} solves/s, p99 {out['plain']['p99_ms']:.0f} ms")
+    return out
+
+
+def run_fitness(pa, scenario, torch, stream):
+    """pa_fitness alone on a resident population: evals/s and LDS roofline."""
+    out = []
+    for (L, K, n) in ((37, 32, 16384), (19, 16, 65536)):
+        d = scenario.make_drop(L, K, seed=1, instance_id=0)
+        ctx = pa.pa_context_create(0)
+        inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=196)
+        pop = torch.empty((n, L, K), dtype=torch.uint8, device="cuda")
+        pa.pa_kmeans_init(inst, pa.GaParams(pop=n, kmeans_frac=0.0, seed=3), pop)
+        fit = torch.empty(n, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            pa.pa_fitness(inst, pop, n, fit)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        iters = 20
+        e0.record(stream)
+        for _ in range(iters):
+            pa.pa_fitness(inst, pop, n, fit)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / iters
+        gbs = n * L * L * K * 4 / (ms * 1e-3) / 1e9
+        TP = max(4, 1 << (K - 1).bit_length())
+        out.append({"kernel": f"k_fitness_exact<{L},{TP},0,*>", "L": L, "K": K, "n": n,
+                    "avg_launch_us": ms * 1e3, "evals_per_s": n / (ms * 1e-3),
+                    "achieved_gbs": gbs, "frac": gbs / LDS_PEAK_GBS})
+        log(f"pa_fitness L={L} K={K} n={n}: {ms * 1e3:.1f} us, {n / (ms * 1e-3):.3e} evals/s, "
+            f"{gbs:.0f} GB/s LDS ({100 * gbs / LDS_PEAK_GBS:.1f}%)")
+        inst.close()
     return out
 
 
@@ -95,8 +225,14 @@ def main():
     ap.add_argument("--workload", default="single_L19_K16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-iters", type=int, default=200)
-    ap.add_argument("--batch", default="batch64_L37_K32",
-                    help="also time this batched workload ('' to skip)")
+    ap.add_argument("--batch", default="batch64_L37_K32,batch512_mix",
+                    help="also time these batched workloads (comma-separated, '' to skip)")
+    ap.add_argument("--serve", default="serve_mix_2000rps",
+                    help="also run this served workload ('' to skip)")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--plain-sample", type=int, default=64,
+                    help="pool entries whose plain service time is measured for the comparator")
+    ap.add_argument("--no-fitness", action="store_true", help="skip the pa_fitness roofline lines")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (5 times) and exit: the "
                          "reference kernel that scales HBM byte counters")
@@ -196,8 +332,13 @@ def main():
         f"{achieved:.0f} GB/s LDS ({100 * achieved / LDS_PEAK_GBS:.1f}% of {LDS_PEAK_GBS:.0f})")
 
     extra = {}
+    if not args.no_fitness:
+        extra["fitness"] = run_fitness(pa, scenario, torch, stream)
     if args.batch:
-        extra["batch"] = run_batch(pa, scenario, torch, args.batch)
+        extra["batch"] = [run_batch(pa, scenario, torch, b) for b in args.batch.split(",") if b]
+    if args.serve:
+        extra["serve"] = run_serve(pa, scenario, torch, args.serve, args.serve_seconds,
+                                   args.plain_sample)
     line = {
         "metric": "chromosome fitness evals/s", "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,

@@ -137,4 +137,11 @@ WORKLOADS = {
     "batch64_L37_K32": dict(L=37, K=32, M=256, T=196, snr_db=10.0, N=1024, gens=200, E=8,
                             p_cross=0.8, p_mut=0.05, kmeans_frac=0.5, p_init=0.1, seed=1,
                             instances=64),
+    # uneven sizes from size_mix (L in {7, 19, 37}, K in [4, 32], N in [128, 1024])
+    "batch512_mix": dict(mix=True, M=256, T=196, snr_db=10.0, gens=200, E=8, p_cross=0.8,
+                         p_mut=0.05, kmeans_frac=0.5, p_init=0.1, seed=1, instances=512),
+    # Poisson arrivals of size_mix solves with 50 generations each
+    "serve_mix_2000rps": dict(mix=True, M=256, T=196, snr_db=10.0, gens=50, E=8, p_cross=0.8,
+                              p_mut=0.05, kmeans_frac=0.5, p_init=0.1, seed=1, rate=2000.0,
+                              pool=64),
 }
