@@ -29,6 +29,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def source_sha256():
+    """Hash of the kernel sources and the C ABI header (the HBM counters in
+    profiles/ are valid only for the sources they were taken from)."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in ("paper_2511_20511_amd/csrc", "include"):
+        for f in sorted(os.listdir(os.path.join(ROOT, d))):
+            h.update(f.encode())
+            with open(os.path.join(ROOT, d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, gens_per_launch):
+    """HBM bytes per launch from the committed rocprofv3 counter passes, or None
+    when they were taken for another kernel, workload or source version."""
+    path = os.path.join(ROOT, "profiles", f"k_gen_persist_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if (rec.get("kernel") != kernel or rec.get("generations_per_launch") != gens_per_launch
+            or rec.get("source_sha256") != source_sha256()):
+        return None
+    return float(rec["bytes_per_launch"])
+
+
 def evals_per_solve(N, E, G):
     return N + (N - E) * G
 
@@ -325,7 +352,8 @@ def main():
     achieved = lds_bytes / (k_ms * 1e-3) / 1e9
     roofline = {"bound": "lds", "kernel": kname,
                 "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / LDS_PEAK_GBS, "traffic": None,
+                "frac": achieved / LDS_PEAK_GBS,
+                "traffic": measured_traffic(kname, args.workload, gens_per_launch),
                 "avg_launch_us": k_ms * 1e3, "bytes_per_launch": lds_bytes,
                 "generations_per_launch": gens_per_launch}
     log(f"generation kernel {kname}: {k_ms * 1e3:.2f} us/launch ({gens_per_launch} generation(s)), "
