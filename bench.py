@@ -60,10 +60,16 @@ def evals_per_solve(N, E, G):
     return N + (N - E) * G
 
 
-def cpu_baseline(drop, w, budget_s=12.0):
-    """The FP64 oracle, single-threaded, on whole solves of the same workload."""
+def cpu_baseline(drop, w, best=None, best_fit=None, budget_s=12.0):
+    """The FP64 oracle, single-threaded, on whole solves of the same workload;
+    also the FP64 fitness of the GPU's best chromosome (its FP32 error)."""
+    import numpy as np
     import oracle
     oracle.build(force=False)
+    err = None
+    if best is not None:
+        f64 = float(oracle.fitness(drop.beta, best[None].astype(np.uint8), T=w["T"])[0])
+        err = abs(best_fit - f64) / abs(f64)
     t0 = time.perf_counter()
     solves = 0
     while True:
@@ -75,7 +81,8 @@ def cpu_baseline(drop, w, budget_s=12.0):
             break
     ev = solves * evals_per_solve(w["N"], w["E"], w["gens"])
     return {"value": ev / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{solves} full oracle solve(s) of the same workload ({el:.1f} s, FP64, 1 thread)"}
+            "sample": f"{solves} full oracle solve(s) of the same workload ({el:.1f} s, FP64, 1 thread)",
+            "best_fp32_rel_err_vs_fp64": err}
 
 
 def workload_sizes(scenario, w, n):
@@ -383,7 +390,7 @@ def main():
     line.update(extra)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(drop, w)
+        line["cpu_baseline"] = cpu_baseline(drop, w, res.best, res.best_fit)
         log(f"oracle: {line['cpu_baseline']['value']:.0f} evals/s")
     print(json.dumps(line), flush=True)
 

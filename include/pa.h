@@ -252,6 +252,22 @@ pa_status pa_fitness_shaped(pa_instance *inst, const uint8_t *d_pop, int32_t n, 
 pa_status pa_solve_shape(pa_context *ctx, pa_instance *inst, int32_t *persistent, int32_t *block,
                          int32_t *children_per_task, int32_t *workgroups);
 
+/* ---- exhaustive search ------------------------------------------------ */
+
+/* Exhaustive search (the EX-PA reference, Sec. 3.3 and Sec. 6): every
+ * assignment with cell 0's pilots fixed to the identity (the sum SE is
+ * invariant under a global relabelling of pilots, so each class of K!
+ * equivalent assignments is visited once), i.e. K!^(L-1) chromosomes in
+ * odometer order (cell L-1 fastest, each cell's permutations in
+ * lexicographic order), scored by the pa_fitness kernel.  Fills out->best
+ * (HOST, L*K bytes, may be NULL), out->best_fit (FP32; ties to the lowest
+ * rank), out->device_ms; out->best_index = -1 and out->trace is untouched;
+ * *best_rank = the enumeration rank of the best, *count = K!^(L-1) (either
+ * may be NULL).  PA_EINVAL when K > 12 or K!^(L-1) > max_count (0 = 2^32).
+ * Blocking. */
+pa_status pa_exhaustive(pa_instance *inst, int64_t max_count, pa_result *out, int64_t *best_rank,
+                        int64_t *count, void *stream);
+
 /* ---- continuous-batching server -------------------------------------- */
 
 /* Many independent solves arriving over time (not in the paper; the serving

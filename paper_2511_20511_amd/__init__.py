@@ -24,7 +24,7 @@ __all__ = [
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
     "pa_solve_shape", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
-    "pa_server_destroy", "Server",
+    "pa_server_destroy", "Server", "pa_exhaustive",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
     "SE_ASYMPTOTIC", "SE_FINITE_M",
@@ -142,6 +142,8 @@ def lib():
         "pa_server_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(_Result), i32]),
         "pa_server_stats": (st, [vp, ctypes.POINTER(_ServerCounters)]),
         "pa_server_destroy": (None, [vp]),
+        "pa_exhaustive": (st, [vp, ctypes.c_int64, ctypes.POINTER(_Result),
+                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp]),
         "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
         "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
         "pa_status_string": (ctypes.c_char_p, [st]),
@@ -379,6 +381,17 @@ def pa_instance_kmeans_state(inst: Instance):
     _check(lib().pa_instance_kmeans_state(inst.h, seed.ctypes.data, cent.ctypes.data,
                                           labels.ctypes.data, iters.ctypes.data))
     return seed, cent, labels, int(iters[0])
+
+
+def pa_exhaustive(inst: Instance, max_count: int = 0, stream=None):
+    """Exhaustive search: (Result with best and best_fit, best enumeration rank, count)."""
+    best = np.zeros((inst.L, inst.K), dtype=np.uint8)
+    r = _Result(best.ctypes.data, 0.0, 0, None, 0.0)
+    rank, cnt = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().pa_exhaustive(inst.h, int(max_count), ctypes.byref(r), ctypes.byref(rank),
+                               ctypes.byref(cnt), _stream(stream)))
+    return (Result(best, float(r.best_fit), int(r.best_index), np.zeros(0, np.float32),
+                   float(r.device_ms)), int(rank.value), int(cnt.value))
 
 
 # ---- continuous-batching server ---------------------------------------------

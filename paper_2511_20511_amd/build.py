@@ -21,7 +21,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpa_amd.so")
 
 SOURCES = ["api.cpp", "k_prep.hip", "k_fitness.hip", "k_ga.hip", "k_kmeans.hip", "k_gen.hip",
-           "k_gen_L7.hip", "k_gen_L19.hip", "k_gen_L37.hip", "solve.cpp", "server.cpp"]
+           "k_gen_L7.hip", "k_gen_L19.hip", "k_gen_L37.hip", "solve.cpp", "server.cpp",
+           "k_exhaustive.hip"]
 ARCH = "gfx950"
 
 
