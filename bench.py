@@ -220,6 +220,64 @@ def run_serve(pa, scenario, torch, name, seconds, plain_sample):
     return out
 
 
+def run_convergence(pa, scenario, torch, drops, gens):
+    """K-means-seeded (kmeans_frac = 0.5) vs randomly initialised (0) GA on the
+    same drops (L=19, K=16, N=256, E=8): best sum SE at the end, generations
+    until the trace reaches 99% of its final value, and the distribution of
+    the final best next to a random pilot assignment (one random chromosome)
+    and the K-means seed alone."""
+    import numpy as np
+    L, K, N, E = 19, 16, 256, 8
+    ctx = pa.pa_context_create(0)
+    rho = scenario.snr_to_rho(10.0)
+    insts, params, rpa, seed_fit = [], [], [], []
+    pop = torch.empty((N, L, K), dtype=torch.uint8, device="cuda")
+    fit = torch.empty(N, dtype=torch.float32, device="cuda")
+    for i in range(drops):
+        d = scenario.make_drop(L, K, seed=7, instance_id=i)
+        inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=196, M=256, rho=rho)
+        for km in (0.5, 0.0):
+            insts.append(inst)
+            params.append(pa.GaParams(pop=N, gens=gens, elite=E, p_cross=0.8, p_mut=0.05,
+                                      kmeans_frac=km, p_init=0.1, seed=100 + i, instance_id=i))
+        # slot 0 of a random population: one random assignment; of a K-means
+        # population: the seed itself
+        for km, dst in ((0.0, rpa), (0.5, seed_fit)):
+            pa.pa_kmeans_init(inst, pa.GaParams(pop=N, kmeans_frac=km, seed=100 + i,
+                                                instance_id=i), pop)
+            pa.pa_fitness(inst, pop, 1, fit)
+            torch.cuda.synchronize()
+            dst.append(float(fit[0].item()))
+    # a batch may hold an instance once: run the two initialisations apart
+    res_km = pa.pa_solve_batch(ctx, insts[0::2], params[0::2])
+    res_rd = pa.pa_solve_batch(ctx, insts[1::2], params[1::2])
+
+    def to99(tr):
+        target = 0.99 * tr[-1]
+        return int(np.argmax(tr >= target))
+
+    out = {"workload": f"{drops} drops, L={L} K={K} N={N} G={gens} E={E}, M=256, T=196, SNR 10 dB"}
+    for name, res in (("kmeans_init", res_km), ("random_init", res_rd)):
+        best = np.array([r.best_fit for r in res])
+        g99 = np.array([to99(r.trace) for r in res])
+        out[name] = {"best_mean": float(best.mean()),
+                     "best_p10_p50_p90": [float(x) for x in np.percentile(best, [10, 50, 90])],
+                     "gens_to_99pct_mean": float(g99.mean()),
+                     "gens_to_99pct_median": float(np.median(g99)),
+                     "initial_best_mean": float(np.mean([r.trace[0] for r in res]))}
+    for name, vals in (("random_assignment", rpa), ("kmeans_seed_only", seed_fit)):
+        v = np.array(vals)
+        out[name] = {"mean": float(v.mean()),
+                     "p10_p50_p90": [float(x) for x in np.percentile(v, [10, 50, 90])]}
+    g_km = np.array([to99(r.trace) for r in res_km])
+    g_rd = np.array([to99(r.trace) for r in res_rd])
+    out["kmeans_reaches_99pct_first_frac"] = float(np.mean(g_km < g_rd))
+    out["reduction_of_mean_gens_to_99pct"] = float(1.0 - g_km.mean() / max(g_rd.mean(), 1e-9))
+    out["kmeans_final_better_frac"] = float(np.mean(
+        np.array([r.best_fit for r in res_km]) > np.array([r.best_fit for r in res_rd])))
+    return out
+
+
 def run_fitness(pa, scenario, torch, stream):
     """pa_fitness alone on a resident population: evals/s and LDS roofline."""
     out = []
@@ -267,6 +325,10 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=64,
                     help="pool entries whose plain service time is measured for the comparator")
     ap.add_argument("--no-fitness", action="store_true", help="skip the pa_fitness roofline lines")
+    ap.add_argument("--experiment", default="", choices=["", "convergence"],
+                    help="only run this experiment and print its JSON line")
+    ap.add_argument("--drops", type=int, default=256)
+    ap.add_argument("--exp-gens", type=int, default=200)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (5 times) and exit: the "
                          "reference kernel that scales HBM byte counters")
@@ -291,6 +353,12 @@ def main():
 
     import paper_2511_20511_amd as pa
     from paper_2511_20511_amd import scenario
+
+    if args.experiment == "convergence":
+        print(json.dumps({"experiment": "convergence",
+                          **run_convergence(pa, scenario, torch, args.drops, args.exp_gens)}),
+              flush=True)
+        return
 
     w = dict(scenario.WORKLOADS[args.workload])
     L, K, N, G, E = w["L"], w["K"], w["N"], w["gens"], w["E"]
