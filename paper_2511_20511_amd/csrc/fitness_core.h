@@ -282,18 +282,13 @@ __device__ __forceinline__ float lane_sum_split(const uint8_t *sInv, int ql, boo
 // squares come from a small LDS table sOwn[l][p], so the tile loop need not
 // be unrolled: I sums every j in increasing order, and adding the exact +0.0
 // at j == l gives the same bits as skipping it.
+
+// A lane's base offsets into a tile of TR BS rows (cell-major).
 template <int LT, int TPT, int MODE, int TR>
-__device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, float *sT,
-                                                const float *sOwn, const float *__restrict__ T2z,
-                                                const float *__restrict__ T1,
-                                                const float *__restrict__ lconst) {
-  constexpr int NT = (LT + TR - 1) / TR;
+__device__ __forceinline__ void tiled_offsets(const uint8_t *ip, bool active, uint32_t (&A)[LT]) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   constexpr int CELLB = TR * ROWB;
-  const char *lds = reinterpret_cast<const char *>(sT);
-  // ip lies inside the inverse-row region for inactive lanes too: every lane
-  // loads (no per-element branch, all loads in flight at once), then masks
-  uint32_t A[LT];
+  // ip lies inside the inverse-row region for inactive lanes too
 #pragma unroll
   for (int j = 0; j < LT; ++j) A[j] = ip[j];
 #pragma unroll
@@ -301,6 +296,63 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
     const uint32_t v = active ? A[j] : 0u;
     A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
   }
+}
+
+// Adds the SE terms of the BS rows of tile t (already in LDS) to acc, in
+// increasing l.
+template <int LT, int TPT, int MODE, int TR>
+__device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip, bool active,
+                                            const float *sT, const float *sOwn,
+                                            const float *__restrict__ lconst, int t, float acc) {
+  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
+  const char *lds = reinterpret_cast<const char *>(sT);
+  const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
+  // Branch-free over the tile's rows (a row past the last BS row of a short
+  // final tile reads stale but in-bounds LDS and is not added), so the rows
+  // stay in order instead of being hoisted past per-row branches.
+#pragma unroll
+  for (int lr = 0; lr < TR; ++lr) {
+    const int l = min(t * TR + lr, LT - 1);
+    const uint32_t ownr = ip[l];  // in bounds for inactive lanes too
+    const uint32_t own = active ? ownr : 0u;
+    const float b2 = sOwn[l * TPT + (int)(own & (TPT - 1))];
+    const uint32_t off = (uint32_t)(lr * ROWB);
+    float I = 0.0f;
+#pragma unroll
+    for (int j = 0; j < LT; ++j) I = I + *reinterpret_cast<const float *>(lds + A[j] + off);
+    float se;
+    if constexpr (MODE == 1) {
+      float S = 0.0f;
+#pragma unroll
+      for (int j = 0; j < LT; ++j)
+        S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
+      se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1]);
+    } else {
+      se = se_asym(b2, I);
+    }
+    const float next = acc + se;
+    acc = lr < rows ? next : acc;
+    // the gathers of rows lr + 2, lr + 3 wait for the sum up to this row (two
+    // rows in flight): without this the compiler hoists every row's loads to
+    // the top of the tile and spills
+    if (lr % 2 == 1) {
+#pragma unroll
+      for (int j = 0; j < LT; ++j) asm volatile("" : "+v"(A[j]) : "v"(acc));
+    }
+  }
+  return acc;
+}
+
+// The whole sum for one round, (re)loading every tile.  Every thread of the
+// workgroup must call it (inactive lanes too).
+template <int LT, int TPT, int MODE, int TR>
+__device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, float *sT,
+                                                const float *sOwn, const float *__restrict__ T2z,
+                                                const float *__restrict__ T1,
+                                                const float *__restrict__ lconst) {
+  constexpr int NT = (LT + TR - 1) / TR;
+  uint32_t A[LT];
+  tiled_offsets<LT, TPT, MODE, TR>(ip, active, A);
   float acc = 0.0f;
 #pragma unroll 1
   for (int t = 0; t < NT; ++t) {
@@ -308,36 +360,7 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
     const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
     load_tile<MODE>(T2z, T1, LT, TPT, t * TR, rows, TR, sT);
     __syncthreads();
-    // Branch-free over the tile's rows (a row past the last BS row of a
-    // short final tile reads stale but in-bounds LDS and is not added), so
-    // the rows stay in order instead of being hoisted past per-row branches.
-#pragma unroll
-    for (int lr = 0; lr < TR; ++lr) {
-      const int l = min(t * TR + lr, LT - 1);
-      const uint32_t ownr = ip[l];  // in bounds for inactive lanes too
-      const uint32_t own = active ? ownr : 0u;
-      const float b2 = sOwn[l * TPT + (int)(own & (TPT - 1))];
-      const uint32_t off = (uint32_t)(lr * ROWB);
-      float I = 0.0f;
-#pragma unroll
-      for (int j = 0; j < LT; ++j) I = I + *reinterpret_cast<const float *>(lds + A[j] + off);
-      float se;
-      if constexpr (MODE == 1) {
-        float S = 0.0f;
-#pragma unroll
-        for (int j = 0; j < LT; ++j)
-          S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
-        se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1]);
-      } else {
-        se = se_asym(b2, I);
-      }
-      const float next = acc + se;
-      acc = lr < rows ? next : acc;
-      // the next row's gathers wait for this row's sum: without this the
-      // compiler hoists every row's loads to the top of the tile and spills
-#pragma unroll
-      for (int j = 0; j < LT; ++j) asm volatile("" : "+v"(A[j]) : "v"(acc));
-    }
+    acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, lconst, t, acc);
   }
   return acc;
 }

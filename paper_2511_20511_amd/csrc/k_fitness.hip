@@ -33,26 +33,40 @@ struct FitArgs {
 };
 
 // LDS plan of the population-fitness kernels: the table tile, then the
-// inverse rows (<= block*L bytes), then the per-(c, p) sums (block*4 bytes).
+// inverse rows (<= block*L bytes), then the per-(c, p) sums (block*4 bytes),
+// the own-cell squares, the round's chromosome bytes and, for tiled tables,
+// the partial sums of a group of kGroup rounds (kGroup*block floats).
 template <int LT, int TPT, int MODE, int BLOCK>
 struct ExactPlan {
   static constexpr int kInvBytes = ((BLOCK * LT) + 15) / 16 * 16;
   static constexpr int kEBytes = BLOCK * 4;
   static constexpr int kOwnBytes = LT * TPT * 4;  // own-cell squares (tiled tables)
   static constexpr int kStageBytes = kInvBytes;     // the round's chromosome bytes
-  using T = TilePlan<LT, TPT, MODE, kInvBytes + kEBytes + kOwnBytes + kStageBytes>;
+  static constexpr int kBase = kInvBytes + kEBytes + kOwnBytes + kStageBytes;
+  static constexpr int kGroup = 8;
+  static constexpr int kAccBytes = TilePlan<LT, TPT, MODE, kBase>::kTiles > 1 ? kGroup * BLOCK * 4 : 0;
+  using T = TilePlan<LT, TPT, MODE, kBase + kAccBytes>;
   static constexpr int kTiles = T::kTiles;
   static constexpr int kTileRows = T::kTileRows;
   static constexpr int kInvOff = T::kTableBytes;
   static constexpr int kEOff = kInvOff + kInvBytes;
   static constexpr int kOwnOff = kEOff + kEBytes;
   static constexpr int kStageOff = kOwnOff + kOwnBytes;
-  static constexpr int kTotal = kStageOff + kStageBytes;
+  static constexpr int kAccOff = kStageOff + kStageBytes;
+  static constexpr int kTotal = kAccOff + kAccBytes;
   static_assert(kTotal <= kLdsBytes, "LDS plan too large");
 };
 
+// Words of a round's chromosome bytes one thread prefetches (a round is at
+// most block * L bytes, i.e. at most L / 4 + 1 words per thread).
+template <int LT>
+constexpr int stage_words() {
+  return LT / 4 + 2;
+}
+
 template <int LT, int TPT, int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
+  constexpr int kStagePF = stage_words<LT>();
   using P = ExactPlan<LT, TPT, MODE, BLOCK>;
   constexpr int NT = P::kTiles;
   constexpr int TR = P::kTileRows;
@@ -68,26 +82,76 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   const int q = threadIdx.x;
   const int rounds = (a.n + CPR - 1) / CPR;
 
-  if constexpr (NT == 1) {
+  if constexpr (NT > 1) {
+    // Tiled table: tiles outermost.  The workgroup's rounds are taken in
+    // groups of kGroup; each tile is loaded once per group and every round of
+    // the group is restaged, inverted and summed over the tile's rows, the
+    // partial sums kept in LDS between tiles (the same per-lane order of
+    // additions as lane_sum_tiled, so the same bits).
+    float *sAcc = reinterpret_cast<float *>(smem + P::kAccOff);
+    load_own(a.Town, LT, TPT, sOwn);  // ordered by the first barrier below
+    const int mine = rounds > (int)blockIdx.x ? (rounds - 1 - (int)blockIdx.x) / (int)gridDim.x + 1 : 0;
+    for (int i0 = 0; i0 < mine; i0 += P::kGroup) {
+      const int ng = min(P::kGroup, mine - i0);
+      for (int t = 0; t < NT; ++t) {
+        __syncthreads();  // every lane is done with the previous tile
+        const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
+        load_tile<MODE>(a.T2z, a.T1, LT, TPT, t * TR, rows, TR, sT);
+        // the next round's chromosome bytes are loaded during this round
+        uint32_t pf[kStagePF];
+        auto range = [&](int g) {
+          const int c0 = ((int)blockIdx.x + (i0 + g) * (int)gridDim.x) * CPR;
+          return ByteRange{a.pop + (size_t)c0 * LK, min(CPR, a.n - c0) * LK};
+        };
+        prefetch_issue(range(0), pf);
+        for (int g = 0; g < ng; ++g) {
+          const int r = (int)blockIdx.x + (i0 + g) * (int)gridDim.x;
+          const int c0 = r * CPR;
+          const int nc = min(CPR, a.n - c0);
+          prefetch_store(range(g), pf, sStage);
+          if (g + 1 < ng) prefetch_issue(range(g + 1), pf);
+          __syncthreads();
+          build_inverse(sStage, nc * LT, LT, K, sInv);
+          __syncthreads();
+          const bool active = q / K < nc;
+          const uint8_t *ip = sInv + q * LT;
+          uint32_t A[LT];
+          tiled_offsets<LT, TPT, MODE, TR>(ip, active, A);
+          float acc = t == 0 ? 0.0f : sAcc[g * BLOCK + q];
+          acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, a.lconst, t, acc);
+          if (t + 1 < NT) {
+            // (the barrier after the next round's staging orders this
+            // round's sInv reads before that round's inverse rows)
+            sAcc[g * BLOCK + q] = acc;
+          } else {
+            reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0);  // ends with a barrier
+          }
+        }
+      }
+    }
+    return;
+  } else {
     load_tile<MODE>(a.T2, a.T1, LT, TPT, 0, LT, TR, sT);
     __syncthreads();
-  } else {
-    load_own(a.Town, LT, TPT, sOwn);  // ordered by the first barrier of lane_sum_tiled
   }
+  // the next round's chromosome bytes are loaded during this round
+  uint32_t pf[kStagePF];
+  auto range = [&](int r) {
+    const int c0 = r * CPR;
+    return ByteRange{a.pop + (size_t)c0 * LK, r < rounds ? min(CPR, a.n - c0) * LK : 0};
+  };
+  prefetch_issue(range(blockIdx.x), pf);
   for (int r = blockIdx.x; r < rounds; r += gridDim.x) {
     const int c0 = r * CPR;
     const int nc = min(CPR, a.n - c0);
-    copy_bytes(a.pop + (size_t)c0 * LK, nc * LK, sStage);
+    prefetch_store(range(r), pf, sStage);
+    prefetch_issue(range(r + gridDim.x), pf);
     __syncthreads();
     build_inverse(sStage, nc * LT, LT, K, sInv);
     __syncthreads();
     const bool active = q / K < nc;
-    float acc;
-    if constexpr (NT == 1)
-      acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst);
-    else
-      acc = lane_sum_tiled<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, a.T2z, a.T1,
-                                              a.lconst);
+    const float acc =
+        lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst);
     reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0);
   }
 }

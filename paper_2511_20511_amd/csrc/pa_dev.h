@@ -185,6 +185,39 @@ __device__ __forceinline__ void copy_bytes(const uint8_t *src, int n, uint8_t *d
   }
 }
 
+// Two-step copy of a global byte range [src, src + n) into LDS, so that the
+// loads of one range can fly while the workgroup computes on the previous
+// one: prefetch_issue loads this thread's aligned words (at most PF per
+// thread: the range must satisfy words() <= PF * blockDim.x) into registers,
+// prefetch_store writes them to dst (LDS, any alignment).
+template <int PF>
+__device__ __forceinline__ void prefetch_issue(const ByteRange &r, uint32_t (&v)[PF]) {
+  const int nw = r.n > 0 ? r.words() : 0;
+  const int step = (int)blockDim.x;
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const int w = (int)threadIdx.x + u * step;
+    v[u] = w < nw ? r.load(w) : 0u;
+  }
+}
+template <int PF>
+__device__ __forceinline__ void prefetch_store(const ByteRange &r, const uint32_t (&v)[PF],
+                                               uint8_t *dst) {
+  const int nw = r.n > 0 ? r.words() : 0;
+  const int step = (int)blockDim.x;
+#pragma unroll
+  for (int u = 0; u < PF; ++u) {
+    const int w = (int)threadIdx.x + u * step;
+    if (w < nw) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int g = r.pos(w, b);
+        if (g >= 0 && g < r.n) dst[g] = (uint8_t)(v[u] >> (8 * b));
+      }
+    }
+  }
+}
+
 // Copies n bytes from LDS `src` to global `dst` (any alignment) with the
 // whole workgroup: 32-bit stores wherever dst is aligned, single bytes at the
 // two ends.
