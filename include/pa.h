@@ -73,6 +73,14 @@ enum {
  *   I = sum_{j != i} beta_ijk'^2, B_i = sum over all users of beta_i..   */
 enum { PA_SE_ASYMPTOTIC = 0, PA_SE_FINITE_M = 1 };
 
+/* Objectives (the GA maximises the fitness).
+ * PA_OBJ_SUM_SE: Eq. 7, the sum over all users of their SE, x pre-log.
+ * PA_OBJ_MIN_SINR: the smallest SINR of any user (SIR in asymptotic mode):
+ *   the max-min SIR criterion the paper names beside the sum (Sec. 2).  SE is
+ *   monotone in SINR, so this is also the max-min SE assignment; the SINR
+ *   keeps FP32 precision where log2(1 + SINR) of a weak user would not. */
+enum { PA_OBJ_SUM_SE = 0, PA_OBJ_MIN_SINR = 1 };
+
 typedef struct pa_context pa_context;
 typedef struct pa_instance pa_instance;
 typedef struct pa_server pa_server;
@@ -87,6 +95,7 @@ typedef struct pa_server pa_server;
  *   M        BS antennas (finite-M mode), >= 1
  *   rho      transmit SNR (finite-M mode), > 0
  *   se_mode  PA_SE_ASYMPTOTIC or PA_SE_FINITE_M
+ *   objective  PA_OBJ_SUM_SE (0) or PA_OBJ_MIN_SINR
  *   beta     HOST [L][L][K] FP64, finite; > 0 in asymptotic mode, >= 0 in
  *            finite-M mode; per BS l the ratio max/min over the nonzero
  *            entries must not exceed 2^60 (FP32 range after normalisation)
@@ -100,6 +109,7 @@ typedef struct pa_problem {
   const double *beta;
   const double *user_xy;
   const double *bs_xy;
+  int32_t objective;
 } pa_problem;
 
 /* GA parameters.

@@ -67,6 +67,7 @@ def lib():
         L.pao_threshold.argtypes = [f64]
         L.pao_threshold.restype = u64
         L.pao_fitness.argtypes = [i32, i32, i32, i32, f64, f64, f64p, u8p, i32, f64p]
+        L.pao_fitness_obj.argtypes = [i32, i32, i32, i32, f64, f64, i32, f64p, u8p, i32, f64p]
         L.pao_se_terms.argtypes = [i32, i32, i32, f64, f64, f64p, u8p, f64p]
         L.pao_rank.argtypes = [f64p, i32, i32p]
         L.pao_kmeans_seed.argtypes = [i32, i32, f64p, f64p, u8p, i32p, i32p, i32p]
@@ -75,7 +76,7 @@ def lib():
         L.pao_solve.argtypes = [i32, i32, i32, i32, f64, f64, f64p, f64p, f64p, i32, i32, i32,
                                 f64, f64, f64, f64, u64, u32, u8p, f64p, f64p, u8p]
         L.pao_bruteforce.argtypes = [i32, i32, i32, i32, f64, f64, f64p, u8p, f64p, i64p]
-        for name in ("pao_fitness", "pao_se_terms", "pao_rank", "pao_kmeans_seed",
+        for name in ("pao_fitness", "pao_fitness_obj", "pao_se_terms", "pao_rank", "pao_kmeans_seed",
                      "pao_init_pop", "pao_ga_step", "pao_solve", "pao_bruteforce"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -114,16 +115,18 @@ def threshold(p):
     return int(lib().pao_threshold(p))
 
 
-def fitness(beta, pop, T=0, se_mode=SE_ASYMPTOTIC, M=1, rho=1.0):
-    """Sum SE (Eq. 5-7) x pre-log (Sec. 3) of each chromosome; beta [L][L][K], pop [n][L][K]."""
+def fitness(beta, pop, T=0, se_mode=SE_ASYMPTOTIC, M=1, rho=1.0, objective=0):
+    """Sum SE (Eq. 5-7) x pre-log (Sec. 3) of each chromosome, or with objective 1
+    the smallest per-user SINR (max-min SIR); beta [L][L][K], pop [n][L][K]."""
     beta = np.ascontiguousarray(beta, dtype=np.float64)
     L, L2, K = beta.shape
     assert L == L2
     pop = np.ascontiguousarray(pop, dtype=np.uint8).reshape(-1, L, K)
     n = pop.shape[0]
     fit = np.zeros(n, dtype=np.float64)
-    rc = lib().pao_fitness(L, K, T, se_mode, M, rho, _p(beta, ctypes.c_double),
-                           _p(pop, ctypes.c_uint8), n, _p(fit, ctypes.c_double))
+    rc = lib().pao_fitness_obj(L, K, T, se_mode, M, rho, int(objective),
+                               _p(beta, ctypes.c_double), _p(pop, ctypes.c_uint8), n,
+                               _p(fit, ctypes.c_double))
     _check(rc, "fitness")
     return fit
 

@@ -101,8 +101,9 @@ static int invert_rows(int L, int K, const uint8_t *chrom, int *inv) {
  *   S = sum_j beta_ijk' (own user included), I = sum_{j != i} beta_ijk'^2,
  *   B_i = sum_j sum_k beta_ijk (every user heard at BS i).
  */
-int pao_se_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
-                 const double *beta, const uint8_t *chrom, double *se) {
+/* Per-user SINR (want_sinr != 0) or SE = log2(1 + SINR) of one chromosome. */
+static int user_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
+                      const double *beta, const uint8_t *chrom, int want_sinr, double *se) {
   if (L < 1 || K < 1) return -1;
   int *inv = (int *)malloc(sizeof(int) * (size_t)L * K);
   if (!inv) return -2;
@@ -131,31 +132,54 @@ int pao_se_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
       } else {
         sinr = own * own / I;
       }
-      se[i * K + k] = log2(1.0 + sinr);
+      se[i * K + k] = want_sinr ? sinr : log2(1.0 + sinr);
     }
   }
   free(inv);
   return 0;
 }
 
+int pao_se_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
+                 const double *beta, const uint8_t *chrom, double *se) {
+  return user_terms(L, K, se_mode, M, rho, beta, chrom, 0, se);
+}
+
+int pao_sinr_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
+                   const double *beta, const uint8_t *chrom, double *sinr) {
+  return user_terms(L, K, se_mode, M, rho, beta, chrom, 1, sinr);
+}
+
 /* Sum SE (Eq. 6), scaled by the share of the coherence interval left after
  * uplink training (Sec. 3): 1 - tau/T, or 1 when T == 0. */
-int pao_fitness(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
-                const double *beta, const uint8_t *pop, int32_t n, double *fit) {
-  if (L < 1 || K < 1 || n < 0) return -1;
+/* objective 0: the sum over users of Eq. 7 times the pre-log; objective 1:
+ * the smallest SINR of any user (the max-min SIR criterion the paper names
+ * beside the sum, Sec. 2; SE is monotone in SINR, so it has the same optimum
+ * as max-min SE). */
+int pao_fitness_obj(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
+                    int32_t objective, const double *beta, const uint8_t *pop, int32_t n,
+                    double *fit) {
+  if (L < 1 || K < 1 || n < 0 || objective < 0 || objective > 1) return -1;
   double prelog = (T > 0) ? 1.0 - (double)K / (double)T : 1.0;
   double *se = (double *)malloc(sizeof(double) * (size_t)L * K);
   if (!se) return -2;
   for (int c = 0; c < n; ++c) {
-    int rc = pao_se_terms(L, K, se_mode, M, rho, beta, pop + (size_t)c * L * K, se);
+    int rc = user_terms(L, K, se_mode, M, rho, beta, pop + (size_t)c * L * K, objective, se);
     if (rc != 0) { free(se); return rc; }
-    double sum = 0.0;
+    double v = objective == 0 ? 0.0 : INFINITY;
     for (int i = 0; i < L; ++i)
-      for (int k = 0; k < K; ++k) sum += se[i * K + k];
-    fit[c] = prelog * sum;
+      for (int k = 0; k < K; ++k) {
+        if (objective == 0) v += se[i * K + k];
+        else if (se[i * K + k] < v) v = se[i * K + k];
+      }
+    fit[c] = objective == 0 ? prelog * v : v;
   }
   free(se);
   return 0;
+}
+
+int pao_fitness(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
+                const double *beta, const uint8_t *pop, int32_t n, double *fit) {
+  return pao_fitness_obj(L, K, T, se_mode, M, rho, 0, beta, pop, n, fit);
 }
 
 /* ------------------------------------------------------------------------ */

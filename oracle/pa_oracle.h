@@ -48,9 +48,16 @@ uint64_t pao_threshold(double p);
 /* Sum spectral efficiency (Eq. 5-7) of n chromosomes, FP64. */
 int pao_fitness(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
                 const double *beta, const uint8_t *pop, int32_t n, double *fit);
+/* objective 0 = pao_fitness; 1 = the smallest per-user SINR (max-min SIR). */
+int pao_fitness_obj(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
+                    int32_t objective, const double *beta, const uint8_t *pop, int32_t n,
+                    double *fit);
 /* Per-(cell, user) SE terms of one chromosome, [L][K], before the pre-log. */
 int pao_se_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
                  const double *beta, const uint8_t *chrom, double *se);
+/* Per-(cell, user) SINR of one chromosome, [L][K]. */
+int pao_sinr_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
+                   const double *beta, const uint8_t *chrom, double *sinr);
 
 /* Ranking: order[0..n) = indices best first; returns 0. */
 int pao_rank(const double *fit, int32_t n, int32_t *order);

@@ -32,6 +32,8 @@ __all__ = [
 
 SE_ASYMPTOTIC = 0
 SE_FINITE_M = 1
+OBJ_SUM_SE = 0
+OBJ_MIN_SINR = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libpa_amd.so")
@@ -47,7 +49,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("K", ctypes.c_int32), ("tau", ctypes.c_int32),
                 ("T", ctypes.c_int32), ("M", ctypes.c_int32), ("rho", ctypes.c_double),
                 ("se_mode", ctypes.c_int32), ("beta", ctypes.c_void_p),
-                ("user_xy", ctypes.c_void_p), ("bs_xy", ctypes.c_void_p)]
+                ("user_xy", ctypes.c_void_p), ("bs_xy", ctypes.c_void_p),
+                ("objective", ctypes.c_int32)]
 
 
 class _Params(ctypes.Structure):
@@ -184,7 +187,7 @@ def _dev(t, dtype):
 class _Host:
     """Keeps the host arrays of a pa_problem alive while the C struct points at them."""
 
-    def __init__(self, beta, user_xy, bs_xy, T, M, rho, se_mode):
+    def __init__(self, beta, user_xy, bs_xy, T, M, rho, se_mode, objective=0):
         self.beta = np.ascontiguousarray(beta, dtype=np.float64)
         L, L2, K = self.beta.shape
         if L != L2:
@@ -194,7 +197,8 @@ class _Host:
         self.c = _Problem(L, K, K, int(T), int(M), float(rho), int(se_mode),
                           self.beta.ctypes.data,
                           None if self.user_xy is None else self.user_xy.ctypes.data,
-                          None if self.bs_xy is None else self.bs_xy.ctypes.data)
+                          None if self.bs_xy is None else self.bs_xy.ctypes.data,
+                          int(objective))
         self.L, self.K = L, K
 
 
@@ -242,9 +246,9 @@ class Context:
 
 class Instance:
     def __init__(self, ctx: Context, beta, user_xy=None, bs_xy=None, T=0, M=1, rho=1.0,
-                 se_mode=SE_ASYMPTOTIC):
+                 se_mode=SE_ASYMPTOTIC, objective=0):
         self.ctx = ctx
-        host = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode)
+        host = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode, objective)
         self.L, self.K = host.L, host.K
         self.h = ctypes.c_void_p()
         _check(lib().pa_instance_create(ctx.h, ctypes.byref(host.c), ctypes.byref(self.h)))
@@ -270,8 +274,8 @@ def pa_context_destroy(ctx: Context):
 
 
 def pa_instance_create(ctx: Context, beta, user_xy=None, bs_xy=None, T=0, M=1, rho=1.0,
-                       se_mode=SE_ASYMPTOTIC) -> Instance:
-    return Instance(ctx, beta, user_xy, bs_xy, T, M, rho, se_mode)
+                       se_mode=SE_ASYMPTOTIC, objective=0) -> Instance:
+    return Instance(ctx, beta, user_xy, bs_xy, T, M, rho, se_mode, objective)
 
 
 def pa_instance_destroy(inst: Instance):
@@ -433,9 +437,9 @@ def pa_server_destroy(srv: Server):
 
 
 def pa_server_submit(srv: Server, beta, user_xy=None, bs_xy=None, params: GaParams = None, T=0,
-                     M=1, rho=1.0, se_mode=SE_ASYMPTOTIC) -> int:
+                     M=1, rho=1.0, se_mode=SE_ASYMPTOTIC, objective=0) -> int:
     """Queues one solve; returns its ticket (the arrays are copied)."""
-    host = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode)
+    host = _Host(beta, user_xy, bs_xy, T, M, rho, se_mode, objective)
     p = params.to_c()
     t = ctypes.c_uint64(0)
     _check(lib().pa_server_submit(srv.h, ctypes.byref(host.c), ctypes.byref(p), ctypes.byref(t)))

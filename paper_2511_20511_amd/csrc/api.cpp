@@ -58,6 +58,8 @@ pa_status validate_problem(const pa_problem *pr) {
   if (pr->T < 0) return fail(PA_EINVAL, "T=%d is negative", pr->T);
   if (pr->se_mode != PA_SE_ASYMPTOTIC && pr->se_mode != PA_SE_FINITE_M)
     return fail(PA_EINVAL, "unknown se_mode %d", pr->se_mode);
+  if (pr->objective != PA_OBJ_SUM_SE && pr->objective != PA_OBJ_MIN_SINR)
+    return fail(PA_EINVAL, "unknown objective %d", pr->objective);
   const bool asym = pr->se_mode == PA_SE_ASYMPTOTIC;
   if (asym && pr->L < 2)
     return fail(PA_EINVAL, "asymptotic SE needs L >= 2 (one cell has no interference)");
@@ -332,6 +334,7 @@ pa_status pa_instance_create(pa_context *ctx, const pa_problem *prob, pa_instanc
   p.K = prob->K;
   p.TP = pad_pilots(prob->K);
   p.se_mode = prob->se_mode;
+  p.objective = prob->objective;
   p.prelog = prob->T > 0 ? (float)(1.0 - (double)prob->K / (double)prob->T) : 1.0f;
   const size_t L = p.L, K = p.K, TP = p.TP;
   hipError_t e = hipSuccess;

@@ -26,16 +26,26 @@
 
 namespace pa {
 
-__device__ __forceinline__ float se_asym(float b2, float I) {
-  const float r = __builtin_amdgcn_rcpf(I);
-  return __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
+// Objective: the sum of the SE terms (Eq. 7), or with mn the minimum of the
+// users' SINR (max-min SIR; the SINR is b2 * rcp(den), about 1e-7 relative,
+// where log2(1 + x) in FP32 would lose the small terms).  Both reductions are
+// taken in the canonical order.
+__device__ __forceinline__ float obj_init(bool mn) { return mn ? __builtin_inff() : 0.0f; }
+__device__ __forceinline__ float obj_add(float acc, float se, bool mn) {
+  return mn ? __builtin_fminf(acc, se) : acc + se;
 }
 
-__device__ __forceinline__ float se_finite(float b2, float I, float S, float a, float c2) {
+__device__ __forceinline__ float se_asym(float b2, float I, bool mn = false) {
+  const float r = __builtin_amdgcn_rcpf(I);
+  return mn ? b2 * r : __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
+}
+
+__device__ __forceinline__ float se_finite(float b2, float I, float S, float a, float c2,
+                                           bool mn = false) {
   const float t = __builtin_fmaf(a, S, 1.0f);
   const float den = __builtin_fmaf(c2, t, I);
   const float r = __builtin_amdgcn_rcpf(den);
-  return __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
+  return mn ? b2 * r : __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
 }
 
 // Inverse rows of the chromosomes of a round, stored pilot-major:
@@ -75,7 +85,7 @@ __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int
 template <int LT, int MODE>
 __device__ __forceinline__ float row_term_exact(const char *lds, const uint32_t (&A)[LT],
                                                 uint32_t off, uint32_t t1_bytes, int l,
-                                                float a_l, float c2_l) {
+                                                float a_l, float c2_l, bool mn = false) {
   float I = 0.0f, b2 = 0.0f;
 #pragma unroll
   for (int j = 0; j < LT; ++j) {
@@ -90,9 +100,9 @@ __device__ __forceinline__ float row_term_exact(const char *lds, const uint32_t 
 #pragma unroll
     for (int j = 0; j < LT; ++j)
       S = S + *reinterpret_cast<const float *>(lds + A[j] + off + t1_bytes);
-    return se_finite(b2, I, S, a_l, c2_l);
+    return se_finite(b2, I, S, a_l, c2_l, mn);
   } else {
-    return se_asym(b2, I);
+    return se_asym(b2, I, mn);
   }
 }
 
@@ -100,7 +110,7 @@ __device__ __forceinline__ float row_term_exact(const char *lds, const uint32_t 
 template <int LMAX, int MODE>
 __device__ __forceinline__ float row_term_generic(const char *lds, const uint32_t (&A)[LMAX],
                                                   uint32_t off, uint32_t t1_bytes, int L, int l,
-                                                  float a_l, float c2_l) {
+                                                  float a_l, float c2_l, bool mn = false) {
   float I = 0.0f, b2 = 0.0f, S = 0.0f;
 #pragma unroll
   for (int j = 0; j < LMAX; ++j) {
@@ -113,8 +123,8 @@ __device__ __forceinline__ float row_term_generic(const char *lds, const uint32_
       if constexpr (MODE == 1) S = S + *reinterpret_cast<const float *>(lds + A[j] + off + t1_bytes);
     }
   }
-  if constexpr (MODE == 1) return se_finite(b2, I, S, a_l, c2_l);
-  return se_asym(b2, I);
+  if constexpr (MODE == 1) return se_finite(b2, I, S, a_l, c2_l, mn);
+  return se_asym(b2, I, mn);
 }
 
 // Copies BS rows [r0, r0 + rows) of the cell-major tables T2[j][l][TP]
@@ -183,7 +193,7 @@ template <int LT, int TPT, int MODE, int TR, int NT>
 __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, float *sT,
                                                 const float *__restrict__ T2,
                                                 const float *__restrict__ T1,
-                                                const float *__restrict__ lconst) {
+                                                const float *__restrict__ lconst, bool mn = false) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);  // bytes per (cell, BS row)
   constexpr int CELLB = TR * ROWB;                      // bytes per cell in the tile
   const char *lds = reinterpret_cast<const char *>(sT);
@@ -197,7 +207,7 @@ __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, 
     const uint32_t v = active ? A[j] : 0u;
     A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * 4u;
   }
-  float acc = 0.0f;
+  float acc = obj_init(mn);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     if constexpr (NT > 1) {
@@ -215,8 +225,10 @@ __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, 
           a_l = gp(lconst)[2 * l];
           c2_l = gp(lconst)[2 * l + 1];
         }
-        acc = acc + row_term_exact<LT, MODE>(lds, A, (uint32_t)(lr * ROWB), TPT * 4u, l, a_l,
-                                             c2_l);
+        acc = obj_add(acc,
+                      row_term_exact<LT, MODE>(lds, A, (uint32_t)(lr * ROWB), TPT * 4u, l, a_l,
+                                               c2_l, mn),
+                      mn);
       }
     }
   }
@@ -233,7 +245,8 @@ __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, 
 template <int LT, int TPT, int MODE>
 __device__ __forceinline__ float lane_sum_split(const uint8_t *sInv, int ql, bool active, int rg,
                                                 int RS, const float *sT, float *sSe,
-                                                const float *__restrict__ lconst) {
+                                                const float *__restrict__ lconst,
+                                                bool mn = false) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   constexpr int CELLB = LT * ROWB;
   const char *lds = reinterpret_cast<const char *>(sT);
@@ -262,17 +275,17 @@ __device__ __forceinline__ float lane_sum_split(const uint8_t *sInv, int ql, boo
 #pragma unroll
       for (int j = 0; j < LT; ++j)
         S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
-      se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1]);
+      se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1], mn);
     } else {
-      se = se_asym(b2, I);
+      se = se_asym(b2, I, mn);
     }
     sSe[ql * LT + l] = se;
   }
   __syncthreads();
-  float acc = 0.0f;
+  float acc = obj_init(mn);
   if (rg == 0) {
 #pragma unroll
-    for (int l = 0; l < LT; ++l) acc = acc + sSe[ql * LT + l];
+    for (int l = 0; l < LT; ++l) acc = obj_add(acc, sSe[ql * LT + l], mn);
   }
   return acc;
 }
@@ -303,7 +316,8 @@ __device__ __forceinline__ void tiled_offsets(const uint8_t *ip, bool active, ui
 template <int LT, int TPT, int MODE, int TR>
 __device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip, bool active,
                                             const float *sT, const float *sOwn,
-                                            const float *__restrict__ lconst, int t, float acc) {
+                                            const float *__restrict__ lconst, int t, float acc,
+                                            bool mn = false) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   const char *lds = reinterpret_cast<const char *>(sT);
   const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
@@ -326,11 +340,11 @@ __device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip
 #pragma unroll
       for (int j = 0; j < LT; ++j)
         S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
-      se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1]);
+      se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1], mn);
     } else {
-      se = se_asym(b2, I);
+      se = se_asym(b2, I, mn);
     }
-    const float next = acc + se;
+    const float next = obj_add(acc, se, mn);
     acc = lr < rows ? next : acc;
     // the gathers of rows lr + 2, lr + 3 wait for the sum up to this row (two
     // rows in flight): without this the compiler hoists every row's loads to
@@ -349,18 +363,19 @@ template <int LT, int TPT, int MODE, int TR>
 __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, float *sT,
                                                 const float *sOwn, const float *__restrict__ T2z,
                                                 const float *__restrict__ T1,
-                                                const float *__restrict__ lconst) {
+                                                const float *__restrict__ lconst,
+                                                bool mn = false) {
   constexpr int NT = (LT + TR - 1) / TR;
   uint32_t A[LT];
   tiled_offsets<LT, TPT, MODE, TR>(ip, active, A);
-  float acc = 0.0f;
+  float acc = obj_init(mn);
 #pragma unroll 1
   for (int t = 0; t < NT; ++t) {
     __syncthreads();
     const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
     load_tile<MODE>(T2z, T1, LT, TPT, t * TR, rows, TR, sT);
     __syncthreads();
-    acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, lconst, t, acc);
+    acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, lconst, t, acc, mn);
   }
   return acc;
 }
@@ -376,7 +391,8 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
                                                   int TR, float *sT,
                                                   const float *__restrict__ T2,
                                                   const float *__restrict__ T1,
-                                                  const float *__restrict__ lconst) {
+                                                  const float *__restrict__ lconst,
+                                                  bool mn = false) {
   const int NT = (L + TR - 1) / TR;
   const int ROWB = TP * 4 * (MODE == 1 ? 2 : 1);
   const int CELLB = TR * ROWB;
@@ -389,7 +405,7 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
     const uint32_t v = (active && j < L) ? A[j] : 0u;
     A[j] = (uint32_t)(j * CELLB) + (v & (uint32_t)(TP - 1)) * 4u;
   }
-  float acc = 0.0f;
+  float acc = obj_init(mn);
   for (int t = 0; t < NT; ++t) {
     const int l0 = t * TR;
     const int rows = min(TR, L - l0);
@@ -405,8 +421,10 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
         a_l = gp(lconst)[2 * l];
         c2_l = gp(lconst)[2 * l + 1];
       }
-      acc = acc + row_term_generic<LMAX, MODE>(lds, A, (uint32_t)(lr * ROWB), (uint32_t)TP * 4u,
-                                               L, l, a_l, c2_l);
+      acc = obj_add(acc,
+                    row_term_generic<LMAX, MODE>(lds, A, (uint32_t)(lr * ROWB),
+                                                 (uint32_t)TP * 4u, L, l, a_l, c2_l, mn),
+                    mn);
     }
   }
   return acc;
@@ -415,14 +433,14 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
 // Per-chromosome pairwise tree over pilots of the lanes' sums, then * prelog:
 // fit_out[c] for c < nc.  Called by every thread; ends with a barrier.
 template <int S>
-__device__ __forceinline__ float add_from_lane_plus(float v) {
-  // v + (the value of lane + S in the same row of 16 lanes); DPP row_shl:S
+__device__ __forceinline__ float add_from_lane_plus(float v, bool mn) {
+  // v (+ or min) the value of lane + S in the same row of 16 lanes; DPP row_shl:S
   const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + S, 0xF, 0xF, false);
-  return v + __int_as_float(o);
+  return obj_add(v, __int_as_float(o), mn);
 }
 
 __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, int nc, int K,
-                                             float prelog, float *fit_out) {
+                                             float prelog, float *fit_out, bool mn = false) {
   // pairwise tree over the K pilot sums of a chromosome, one lane per pilot:
   // for s = P/2, P/4, .., 1 (P = K rounded up to a power of two) lane p < s
   // adds lane p + s when p + s < K; the result is in lane 0.
@@ -431,11 +449,11 @@ __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, 
   float v = acc;
   if (K <= 16 && (K & (K - 1)) == 0) {
     // a chromosome's lanes lie inside one DPP row: the tree in registers
-    if (K >= 16) v = add_from_lane_plus<8>(v);
-    if (K >= 8) v = add_from_lane_plus<4>(v);
-    if (K >= 4) v = add_from_lane_plus<2>(v);
-    if (K >= 2) v = add_from_lane_plus<1>(v);
-    if (active && p == 0 && c < nc) gp(fit_out)[c] = prelog * v;
+    if (K >= 16) v = add_from_lane_plus<8>(v, mn);
+    if (K >= 8) v = add_from_lane_plus<4>(v, mn);
+    if (K >= 4) v = add_from_lane_plus<2>(v, mn);
+    if (K >= 2) v = add_from_lane_plus<1>(v, mn);
+    if (active && p == 0 && c < nc) gp(fit_out)[c] = mn ? v : prelog * v;
     __syncthreads();  // the caller's next LDS writes follow every lane's reads
     return;
   }
@@ -446,11 +464,11 @@ __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, 
   for (int s = p2 >> 1; s >= 1; s >>= 1) {
     __syncthreads();
     if (active && p < s && p + s < K) {
-      v = v + sE[q + s];
+      v = obj_add(v, sE[q + s], mn);
       sE[q] = v;
     }
   }
-  if (active && p == 0 && c < nc) gp(fit_out)[c] = prelog * v;
+  if (active && p == 0 && c < nc) gp(fit_out)[c] = mn ? v : prelog * v;
   __syncthreads();
 }
 

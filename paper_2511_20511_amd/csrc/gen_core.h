@@ -292,6 +292,7 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task, 
   const int out = gen < 0 ? 0 : 1 - (gen & 1);
   float *const fit_out = fit_buf(I, out) + task.s0;
   const float prelog = I.prelog;
+  const bool mn = I.objective != 0;
   if (task.kind != kTaskElite && task.inst != loaded) {
     // every thread passed a barrier since the tables were last read
     if constexpr (NT == 1)
@@ -330,19 +331,20 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task, 
       const bool act = ql < lanes;
       const float acc = lane_sum_split<LT, TPT, MODE>(
           sInv, ql, act, rg, BLOCK / GS, sT, reinterpret_cast<float *>(smem + P::kCandOff),
-          I.lconst);
-      reduce_round(sE, acc, act && rg == 0, nc, K, prelog, fit_out);
+          I.lconst, mn);
+      reduce_round(sE, acc, act && rg == 0, nc, K, prelog, fit_out, mn);
       return;
     }
   }
   const bool active = q / K < nc;
   float acc;
   if constexpr (NT == 1)
-    acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, I.T2, I.T1, I.lconst);
+    acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, I.T2, I.T1, I.lconst,
+                                               mn);
   else
     acc = lane_sum_tiled<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z, I.T1,
-                                            I.lconst);
-  reduce_round(sE, acc, active, nc, K, prelog, fit_out);
+                                            I.lconst, mn);
+  reduce_round(sE, acc, active, nc, K, prelog, fit_out, mn);
 }
 
 // Tasks [t0, t1) of one generation for a workgroup (gens: per-instance
@@ -521,9 +523,10 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
     const int q = threadIdx.x;
     const bool active = q / K < nc;
     const float acc =
-        lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, I.T2, I.T1, I.lconst);
+        lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, I.T2, I.T1, I.lconst,
+                                     I.objective != 0);
     const int out = gen < 0 ? 0 : 1 - (gen & 1);
-    reduce_round(sE, acc, active, nc, K, I.prelog, fit_buf(I, out) + task.s0);
+    reduce_round(sE, acc, active, nc, K, I.prelog, fit_buf(I, out) + task.s0, I.objective != 0);
   }
 }
 

@@ -26,6 +26,7 @@ struct FitArgs {
   float *fit;
   int n, L, K, TP;
   float prelog;
+  int objective;  // 0: sum of the SE terms, 1: their minimum
   int tile_rows;  // generic variant: BS rows per LDS tile
   int inv_off;    // LDS byte offset of the inverse rows
   int e_off;      // LDS byte offset of the per-(c, p) sums
@@ -81,6 +82,7 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   const int CPR = BLOCK / K;
   const int q = threadIdx.x;
   const int rounds = (a.n + CPR - 1) / CPR;
+  const bool mn = a.objective != 0;
 
   if constexpr (NT > 1) {
     // Tiled table: tiles outermost.  The workgroup's rounds are taken in
@@ -117,14 +119,14 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
           const uint8_t *ip = sInv + q * LT;
           uint32_t A[LT];
           tiled_offsets<LT, TPT, MODE, TR>(ip, active, A);
-          float acc = t == 0 ? 0.0f : sAcc[g * BLOCK + q];
-          acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, a.lconst, t, acc);
+          float acc = t == 0 ? obj_init(mn) : sAcc[g * BLOCK + q];
+          acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, a.lconst, t, acc, mn);
           if (t + 1 < NT) {
             // (the barrier after the next round's staging orders this
             // round's sInv reads before that round's inverse rows)
             sAcc[g * BLOCK + q] = acc;
           } else {
-            reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0);  // ends with a barrier
+            reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn);  // ends with a barrier
           }
         }
       }
@@ -151,8 +153,8 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
     __syncthreads();
     const bool active = q / K < nc;
     const float acc =
-        lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst);
-    reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0);
+        lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst, mn);
+    reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn);
   }
 }
 
@@ -183,9 +185,10 @@ __global__ __launch_bounds__(1024) void k_fitness_generic(FitArgs a) {
     build_inverse(sStage, nc * L, L, K, sInv);
     __syncthreads();
     const bool active = q / K < nc;
+    const bool mn = a.objective != 0;
     const float acc = lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, a.T2,
-                                                   a.T1, a.lconst);
-    reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0);
+                                                   a.T1, a.lconst, mn);
+    reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn);
   }
 }
 
@@ -318,6 +321,7 @@ hipError_t launch_fitness(const DevProblem &p, const uint8_t *pop, int n, float 
   a.K = p.K;
   a.TP = p.TP;
   a.prelog = p.prelog;
+  a.objective = p.objective;
   const bool force_generic = shape.grid < 0;
   const int grid_cap = shape.grid > 0 ? shape.grid : 0;
   if (!force_generic) {

@@ -25,6 +25,7 @@ inline int pad_pilots(int K) {
 struct DevProblem {
   int L = 0, K = 0, TP = 0;  // cells, users (= pilots), padded pilot stride
   int se_mode = 0;
+  int objective = 0;         // 0: sum of the SE terms, 1: their minimum
   float prelog = 1.0f;       // 1 - tau/T, or 1
   double *beta = nullptr;    // [L][L][K] FP64 as given
   float *T2 = nullptr;       // [L(cell j)][L(BS l)][TP] normalised beta squared (FP32)
@@ -76,6 +77,7 @@ struct GenInst {
   int L, K, TP, N, E, G;
   float prelog;
   int se_mode;
+  int objective;
   DevGa ga;
 };
 

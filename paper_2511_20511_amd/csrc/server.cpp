@@ -162,6 +162,7 @@ hipError_t admit(pa_server *S, int i, Request *r) {
   p.K = pr.K;
   p.TP = pad_pilots(pr.K);
   p.se_mode = pr.se_mode;
+  p.objective = pr.objective;
   p.prelog = pr.T > 0 ? (float)(1.0 - (double)pr.K / (double)pr.T) : 1.0f;
   const size_t L = p.L, K = p.K;
   hipStream_t s = S->stream;
@@ -204,6 +205,7 @@ hipError_t admit(pa_server *S, int i, Request *r) {
   I.G = r->params.gens;
   I.prelog = p.prelog;
   I.se_mode = p.se_mode;
+  I.objective = p.objective;
   I.ga = ga_from_params(&r->params);
   return hipMemcpyAsync(S->d_insts + i, &S->h_insts[i], sizeof(GenInst), hipMemcpyHostToDevice, s);
 }

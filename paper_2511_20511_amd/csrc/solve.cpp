@@ -294,6 +294,7 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
     I.G = g.gens;
     I.prelog = p.prelog;
     I.se_mode = p.se_mode;
+    I.objective = p.objective;
     I.ga = ga_from_params(&g);
     if (I.ga.n_km > 0) which.push_back(i);
   }

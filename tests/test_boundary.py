@@ -1,6 +1,7 @@
 """The C-ABI boundary on the CPU: the library loads, exports every function
 include/pa.h declares, and rejects invalid problems and parameters through
 its host-only checks (no device needed, no compute call)."""
+import ctypes
 import os
 import re
 
@@ -122,3 +123,12 @@ def test_product_path_does_not_use_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "pa_oracle" not in text and "pao_" not in text, f
+
+
+def test_objective_is_validated():
+    import paper_2511_20511_amd as pa
+    from paper_2511_20511_amd import scenario
+    d = scenario.make_drop(7, 4, seed=1, instance_id=0)
+    for obj, want in ((0, 0), (1, 0), (2, -1), (-1, -1)):
+        h = pa._Host(d.beta, d.user_xy, d.bs_xy, 196, 1, 1.0, 0, obj)
+        assert pa.lib().pa_problem_check(ctypes.byref(h.c)) == want

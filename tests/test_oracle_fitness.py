@@ -194,3 +194,51 @@ def test_rejects_non_permutation(oracle_mod):
     bad = np.array([[[0, 0, 1], [0, 1, 2]]], dtype=np.uint8)
     with pytest.raises(ValueError):
         oracle_mod.fitness(beta, bad)
+
+
+# ---- max-min objective (objective 1: the smallest per-user SINR) -------------
+
+@pytest.mark.parametrize("name", ["L2_K1", "L2_K3_three_cycle", "L2_K3_identity"])
+def test_maxmin_hand_worked(oracle_mod, name):
+    """The fitness is the smallest of the hand-worked SIRs of the case (no pre-log)."""
+    case = {c["name"]: c for c in _hand()["cases"]}[name]
+    beta = np.array(case["beta"], dtype=np.float64)
+    chrom = np.array(case["chrom"], dtype=np.uint8)[None]
+    want = min(case["sir"])
+    assert oracle_mod.fitness(beta, chrom, objective=1)[0] == pytest.approx(want, rel=1e-12)
+    assert oracle_mod.fitness(beta, chrom, T=196, objective=1)[0] == pytest.approx(want, rel=1e-12)
+
+
+def test_maxmin_properties(oracle_mod):
+    """log2(1 + min SINR) is the smallest SE term; pilot relabelling leaves it
+    unchanged; in finite-M mode it never exceeds the asymptotic SIR of the
+    same user set (a finite array only adds noise and estimation error)."""
+    rng = np.random.default_rng(7)
+    L, K = 5, 4
+    beta = rng.lognormal(size=(L, L, K))
+    pop = _rand_pop(rng, 16, L, K)
+    mn = oracle_mod.fitness(beta, pop, objective=1)
+    for c in range(len(pop)):
+        terms = oracle_mod.se_terms(beta, pop[c])
+        assert math.log2(1.0 + mn[c]) == pytest.approx(terms.min(), rel=1e-12)
+    perm = rng.permutation(K)
+    np.testing.assert_allclose(oracle_mod.fitness(beta, perm[pop], objective=1), mn, rtol=1e-12)
+    mf = oracle_mod.fitness(beta, pop, se_mode=1, M=64, rho=10.0, objective=1)
+    assert np.all(mf <= mn * (1 + 1e-12))
+
+
+def test_maxmin_optimum_by_enumeration(oracle_mod):
+    """On L=3, K=3 the max-min SIR optimum over all 6^2 classes (enumerated here
+    with itertools) also maximises the smallest SE, and beats any random
+    assignment."""
+    import itertools
+    rng = np.random.default_rng(3)
+    beta = rng.lognormal(size=(3, 3, 3))
+    perms = list(itertools.permutations(range(3)))
+    pop = np.array([[list(range(3)), list(a), list(b)] for a in perms for b in perms],
+                   dtype=np.uint8)
+    mn = oracle_mod.fitness(beta, pop, objective=1)
+    min_se = np.array([oracle_mod.se_terms(beta, c).min() for c in pop])
+    assert int(np.argmax(mn)) == int(np.argmax(min_se))
+    rand = _rand_pop(rng, 50, 3, 3)
+    assert np.all(oracle_mod.fitness(beta, rand, objective=1) <= mn.max() * (1 + 1e-12))
