@@ -311,6 +311,31 @@ __device__ __forceinline__ void tiled_offsets(const uint8_t *ip, bool active, ui
   }
 }
 
+// SE term of BS row l (row lr of the tile in LDS) for a lane.
+template <int LT, int TPT, int MODE>
+__device__ __forceinline__ float tiled_row_se(const uint32_t (&A)[LT], const uint8_t *ip,
+                                              bool active, const char *lds, const float *sOwn,
+                                              const float *__restrict__ lconst, int l, int lr,
+                                              bool mn) {
+  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
+  const uint32_t ownr = ip[l];  // in bounds for inactive lanes too
+  const uint32_t own = active ? ownr : 0u;
+  const float b2 = sOwn[l * TPT + (int)(own & (TPT - 1))];
+  const uint32_t off = (uint32_t)(lr * ROWB);
+  float I = 0.0f;
+#pragma unroll
+  for (int j = 0; j < LT; ++j) I = I + *reinterpret_cast<const float *>(lds + A[j] + off);
+  if constexpr (MODE == 1) {
+    float S = 0.0f;
+#pragma unroll
+    for (int j = 0; j < LT; ++j)
+      S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
+    return se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1], mn);
+  } else {
+    return se_asym(b2, I, mn);
+  }
+}
+
 // Adds the SE terms of the BS rows of tile t (already in LDS) to acc, in
 // increasing l.
 template <int LT, int TPT, int MODE, int TR>
@@ -318,7 +343,6 @@ __device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip
                                             const float *sT, const float *sOwn,
                                             const float *__restrict__ lconst, int t, float acc,
                                             bool mn = false) {
-  constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   const char *lds = reinterpret_cast<const char *>(sT);
   const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
   // Branch-free over the tile's rows (a row past the last BS row of a short
@@ -327,23 +351,7 @@ __device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip
 #pragma unroll
   for (int lr = 0; lr < TR; ++lr) {
     const int l = min(t * TR + lr, LT - 1);
-    const uint32_t ownr = ip[l];  // in bounds for inactive lanes too
-    const uint32_t own = active ? ownr : 0u;
-    const float b2 = sOwn[l * TPT + (int)(own & (TPT - 1))];
-    const uint32_t off = (uint32_t)(lr * ROWB);
-    float I = 0.0f;
-#pragma unroll
-    for (int j = 0; j < LT; ++j) I = I + *reinterpret_cast<const float *>(lds + A[j] + off);
-    float se;
-    if constexpr (MODE == 1) {
-      float S = 0.0f;
-#pragma unroll
-      for (int j = 0; j < LT; ++j)
-        S = S + *reinterpret_cast<const float *>(lds + A[j] + off + TPT * 4);
-      se = se_finite(b2, I, S, gp(lconst)[2 * l], gp(lconst)[2 * l + 1], mn);
-    } else {
-      se = se_asym(b2, I, mn);
-    }
+    const float se = tiled_row_se<LT, TPT, MODE>(A, ip, active, lds, sOwn, lconst, l, lr, mn);
     const float next = obj_add(acc, se, mn);
     acc = lr < rows ? next : acc;
     // the gathers of rows lr + 2, lr + 3 wait for the sum up to this row (two
@@ -357,26 +365,80 @@ __device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip
   return acc;
 }
 
-// The whole sum for one round, (re)loading every tile.  Every thread of the
-// workgroup must call it (inactive lanes too).
+// The SE terms of the BS rows of tile T >= 1 (already in LDS) into
+// hold[l - TR], to be added after tile 0's.
+template <int LT, int TPT, int MODE, int TR, int T>
+__device__ __forceinline__ void tiled_terms(uint32_t (&A)[LT], const uint8_t *ip, bool active,
+                                            const float *sT, const float *sOwn,
+                                            const float *__restrict__ lconst,
+                                            float (&hold)[LT - TR], bool mn) {
+  static_assert(T >= 1 && T * TR < LT, "tile T holds BS rows past tile 0");
+  constexpr int rows = (T + 1) * TR <= LT ? TR : LT - T * TR;
+  const char *lds = reinterpret_cast<const char *>(sT);
+#pragma unroll
+  for (int lr = 0; lr < rows; ++lr) {
+    const int l = T * TR + lr;
+    const float se = tiled_row_se<LT, TPT, MODE>(A, ip, active, lds, sOwn, lconst, l, lr, mn);
+    hold[l - TR] = se;
+    if (lr % 2 == 1) {  // two rows in flight, as in tiled_rows
+#pragma unroll
+      for (int j = 0; j < LT; ++j) asm volatile("" : "+v"(A[j]) : "v"(se));
+    }
+  }
+}
+
+// Tile t of a round: tile 0 adds to acc, the others fill hold (t is
+// dispatched to a compile-time tile index, so hold is indexed statically).
+template <int LT, int TPT, int MODE, int TR, int T>
+__device__ __forceinline__ void tiled_visit(int t, uint32_t (&A)[LT], const uint8_t *ip,
+                                            bool active, const float *sT, const float *sOwn,
+                                            const float *__restrict__ lconst, float &acc,
+                                            float (&hold)[LT - TR], bool mn) {
+  constexpr int NT = (LT + TR - 1) / TR;
+  if (t == T) {
+    if constexpr (T == 0)
+      acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, lconst, 0, acc, mn);
+    else
+      tiled_terms<LT, TPT, MODE, TR, T>(A, ip, active, sT, sOwn, lconst, hold, mn);
+  }
+  if constexpr (T + 1 < NT)
+    tiled_visit<LT, TPT, MODE, TR, T + 1>(t, A, ip, active, sT, sOwn, lconst, acc, hold, mn);
+}
+
+// The whole sum for one round.  `held` is the tile a previous round left in
+// LDS (-1: none).  When it is the last tile the tiles are visited in
+// decreasing order, otherwise in increasing order, so that a run of rounds
+// loads NT - 1 tiles per round instead of NT; in either order tile 0's terms
+// are summed into acc and the others' held in registers and added after, in
+// increasing l: the canonical order, whatever the visiting order.  Updates
+// `held`.  Every thread of the workgroup must call it (inactive lanes too).
 template <int LT, int TPT, int MODE, int TR>
 __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, float *sT,
                                                 const float *sOwn, const float *__restrict__ T2z,
                                                 const float *__restrict__ T1,
-                                                const float *__restrict__ lconst,
+                                                const float *__restrict__ lconst, int &held,
                                                 bool mn = false) {
   constexpr int NT = (LT + TR - 1) / TR;
+  static_assert(NT >= 2, "tiled sums hold more than one tile");
   uint32_t A[LT];
   tiled_offsets<LT, TPT, MODE, TR>(ip, active, A);
   float acc = obj_init(mn);
+  float hold[LT - TR];
+  const bool down = held == NT - 1;
 #pragma unroll 1
-  for (int t = 0; t < NT; ++t) {
-    __syncthreads();
-    const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
-    load_tile<MODE>(T2z, T1, LT, TPT, t * TR, rows, TR, sT);
-    __syncthreads();
-    acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, lconst, t, acc, mn);
+  for (int v = 0; v < NT; ++v) {
+    const int t = down ? NT - 1 - v : v;
+    if (v != 0 || held != t) {
+      __syncthreads();
+      const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
+      load_tile<MODE>(T2z, T1, LT, TPT, t * TR, rows, TR, sT);
+      __syncthreads();
+    }
+    tiled_visit<LT, TPT, MODE, TR, 0>(t, A, ip, active, sT, sOwn, lconst, acc, hold, mn);
   }
+#pragma unroll
+  for (int l = TR; l < LT; ++l) acc = obj_add(acc, hold[l - TR], mn);
+  held = down ? 0 : NT - 1;
   return acc;
 }
 

@@ -170,28 +170,64 @@ __device__ __forceinline__ void copy_elites(const uint8_t *__restrict__ pin,
 // little-endian word: byte u = kp + 1 when gene i = 4b + u (cell j = i / K,
 // user k = i % K) mutates and swaps with user kp of its row, 0 otherwise (and
 // 0 past the chromosome's LK genes).  The decision of gene i is word i of the
-// MUT_DECIDE stream, its partner word i of the MUT_PARTNER stream.
-__device__ __forceinline__ uint32_t mutation_codes(int b, int LK, int K, const DevGa &ga,
-                                                   uint32_t gen, uint32_t slot) {
+// MUT_DECIDE stream, its partner word i of the MUT_PARTNER stream.  Split in
+// two: the decision mask (bit u: gene 4b + u mutates) and the partners of a
+// nonzero mask.
+__device__ __forceinline__ uint32_t mutation_mask(int b, const DevGa &ga, uint32_t gen,
+                                                  uint32_t slot) {
   const Stream dec{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutDecide};
   const Words4 w = dec.block((uint32_t)b);
-  const bool h0 = hit(w.x, ga.thr_mut), h1 = hit(w.y, ga.thr_mut);
-  const bool h2 = hit(w.z, ga.thr_mut), h3 = hit(w.w, ga.thr_mut);
-  if (!(h0 || h1 || h2 || h3)) return 0u;
+  return (hit(w.x, ga.thr_mut) ? 1u : 0u) | (hit(w.y, ga.thr_mut) ? 2u : 0u) |
+         (hit(w.z, ga.thr_mut) ? 4u : 0u) | (hit(w.w, ga.thr_mut) ? 8u : 0u);
+}
+
+__device__ __forceinline__ uint32_t mutation_partners(int b, uint32_t mask, int LK, int K,
+                                                      const DevGa &ga, uint32_t gen,
+                                                      uint32_t slot) {
   const Stream par{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutPartner};
   const Words4 pw = par.block((uint32_t)b);
   uint32_t out = 0u;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int i = 4 * b + u;
-    const bool h = u == 0 ? h0 : u == 1 ? h1 : u == 2 ? h2 : h3;
-    if (h && i < LK) {
+    if (((mask >> u) & 1u) != 0u && i < LK) {
       const int k = i % K;
       const uint32_t r = bounded(pick(pw, (uint32_t)u), (uint32_t)(K - 1));
       out |= (uint32_t)((int)r + ((int)r >= k ? 1 : 0) + 1) << (8 * u);
     }
   }
   return out;
+}
+
+__device__ __forceinline__ uint32_t mutation_codes(int b, int LK, int K, const DevGa &ga,
+                                                   uint32_t gen, uint32_t slot) {
+  const uint32_t m = mutation_mask(b, ga, gen, slot);
+  return m == 0u ? 0u : mutation_partners(b, m, LK, K, ga, gen, slot);
+}
+
+// Stores the code word of genes 4b .. 4b+3 of a child whose codes start at
+// `dst` (byte-aligned when LK is not a multiple of 4).
+__device__ __forceinline__ void store_code_word(uint8_t *codes, int LK, int b, uint32_t v) {
+  uint8_t *dst = codes + 4 * b;
+  if ((LK & 3) == 0 && ((uintptr_t)codes & 3u) == 0) {
+    *reinterpret_cast<uint32_t *>(dst) = v;
+  } else {
+    const int n = LK - 4 * b < 4 ? LK - 4 * b : 4;
+    for (int u = 0; u < n; ++u) dst[u] = (uint8_t)(v >> (8 * u));
+  }
+}
+
+// Mutation codes of the children of slots [s0, s0 + nc) into `codes` (child c
+// at byte c*LK) with the whole workgroup, one (child, Philox block) pair per
+// thread and step.  No barrier: the caller's next one publishes the codes.
+__device__ __forceinline__ void mutation_codes_block(uint8_t *codes, int nc, int LK, int K,
+                                                     const DevGa &ga, uint32_t gen, int s0,
+                                                     int block) {
+  const int nb = (LK + 3) >> 2;
+  for (int i = threadIdx.x; i < nc * nb; i += block) {
+    const int c = i / nb, b = i - c * nb;
+    store_code_word(codes + c * LK, LK, b, mutation_codes(b, LK, K, ga, gen, (uint32_t)(s0 + c)));
+  }
 }
 
 // Applies the swaps of one row (bytes row[0..K) in LDS) given its codes, in
@@ -259,19 +295,20 @@ __device__ __forceinline__ void gather_range(const ByteRange &r, uint8_t *dst, i
 // c*L*K) with the whole workgroup (nc <= block), in phases separated by
 // barriers:
 //   1. thread c < nc: its pair's six SELECT words and the four fitness loads
-//      of its tournaments; meanwhile every thread computes the mutation codes
-//      of its (child, Philox block) pairs into `codes`; then thread c
-//      resolves the tournaments, crossover decision and cut;
+//      of its tournaments; meanwhile the workgroup draws the mutation codes
+//      into `codes`; then thread c resolves the tournaments, crossover
+//      decision and cut;
 //   2. all threads over all genes: copy from the parents (aligned words,
 //      several loads in flight);
-//   3. one thread per (child, row): the swaps, in increasing k.
+//   3. (swaps) one thread per (child, row): the swaps, in increasing k.
 // `child` and `codes` are 4-byte aligned LDS buffers of nc*L*K bytes; sSel:
 // 2 ints per child.  Ends with a barrier.
 __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__ pin,
                                                      const float *__restrict__ fin, int N, int E,
                                                      int L, int K, const DevGa &ga, uint32_t gen,
                                                      int s0, int nc, uint8_t *child,
-                                                     uint8_t *codes, int32_t *sSel, int block) {
+                                                     uint8_t *codes, int32_t *sSel, int block,
+                                                     bool swaps = true) {
   const int LK = L * K;
   const int tid = threadIdx.x;
   const bool sel = tid < nc;
@@ -294,23 +331,7 @@ __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__
     fv1 = gp(fin)[v1];
   }
   const bool mutate = K >= 2 && ga.thr_mut != 0;
-  if (mutate) {
-    // one thread per (child, Philox block); child c's codes start at byte
-    // c*LK, so its words are written through a byte-aligned window when LK is
-    // not a multiple of 4
-    const int nb = (LK + 3) >> 2;
-    for (int i = tid; i < nc * nb; i += block) {
-      const int c = i / nb, b = i - c * nb;
-      const uint32_t v = mutation_codes(b, LK, K, ga, gen, (uint32_t)(s0 + c));
-      uint8_t *dst = codes + c * LK + 4 * b;
-      if ((LK & 3) == 0) {
-        *reinterpret_cast<uint32_t *>(dst) = v;
-      } else {
-        const int n = LK - 4 * b < 4 ? LK - 4 * b : 4;
-        for (int u = 0; u < n; ++u) dst[u] = (uint8_t)(v >> (8 * u));
-      }
-    }
-  }
+  if (mutate) mutation_codes_block(codes, nc, LK, K, ga, gen, s0, block);
   if (sel) {
     const bool second = ((slot - E) & 1) != 0;
     const uint32_t p1 = beats(rank_key(fv0), v0, rank_key(fu0), u0) ? v0 : u0;
@@ -343,13 +364,13 @@ __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__
     }
   }
   __syncthreads();
-  if (mutate) {
+  if (mutate && swaps) {
     for (int r = tid; r < nc * L; r += block) {
       const int off = r * K;  // (c*L + j)*K
       apply_swaps(child + off, codes + off, off, K);
     }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Elitism by a whole workgroup: wave 0 ranks, then every thread helps copy

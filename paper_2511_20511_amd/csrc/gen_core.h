@@ -23,13 +23,13 @@ struct GenArgs {
   const int32_t *gens; // non-null: a task's generation is gens[task.inst] (gen ignored)
 };
 
-// LDS plan: table tile | children (<= block*L) | inverse rows, aliased by the
-// mutation codes while children are built (<= block*L) | sums (block*4) |
-// elite indices (64 ints) | own-cell squares | parents and cut per child,
-// and with PF (persistent form) the tournament candidates of the task's pairs
-// (4 chromosomes per pair; reused for the per-row SE terms of the split lane
-// sum), their selection words (6 ints per pair), their outcome (4 ints per
-// pair) and the children's mutation codes (<= block*L).
+// LDS plan: table tile | children (<= block*L) | inverse rows (<= block*L) |
+// sums (block*4) | elite indices (64 ints) |
+// own-cell squares | parents and cut per child | with PF (persistent form) the
+// tournament candidates of the task's pairs (4 chromosomes per pair; reused
+// for the per-row SE terms of the split lane sum), their selection words (6
+// ints per pair) and their outcome (4 ints per pair) | the children's
+// mutation codes (<= block*L).
 template <int LT, int TPT, int MODE, int BLOCK, bool PF = false>
 struct GenPlan {
   static constexpr int kChildBytes = ((BLOCK * LT) + 15) / 16 * 16;
@@ -42,7 +42,7 @@ struct GenPlan {
   static constexpr int kCandBytes = PF ? (2 * BLOCK * LT + 6 * LT * TPT + 15) / 16 * 16 : 0;
   static constexpr int kPairBytes = PF ? kMaxPairs * 24 : 0;
   static constexpr int kResBytes = PF ? kMaxPairs * 16 : 0;
-  static constexpr int kCodeBytes = PF ? kChildBytes : 0;  // mutation codes (PF)
+  static constexpr int kCodeBytes = kChildBytes;  // mutation codes
   using T = TilePlan<LT, TPT, MODE,
                      kChildBytes + kInvBytes + kEBytes + kIdxBytes + kOwnBytes + kSelBytes +
                          kCandBytes + kPairBytes + kResBytes + kCodeBytes>;
@@ -67,12 +67,40 @@ __device__ __forceinline__ GenTask load_task(const GenTask *tasks, int t) {
   return GenTask{p->inst, p->kind, p->s0, p->s1};
 }
 
+// Swaps, write-out and inverse rows of the nc children built in sChild
+// (codes in sCode, apart from sInv), K % 4 == 0 so that rows are whole aligned
+// words: one thread per row (c, j) applies its swaps, stores the row to pout
+// and scatters its inverse entries.  Ends with a barrier.
+__device__ __forceinline__ void finish_rows(uint8_t *sChild, const uint8_t *sCode, int nc, int L,
+                                            int K, bool mutate, uint8_t *pout, uint8_t *sInv,
+                                            int block) {
+  for (int r = threadIdx.x; r < nc * L; r += block) {
+    if (mutate) apply_swaps(sChild + r * K, sCode + r * K, r * K, K);
+    const int c = r / L, j = r - c * L;
+    const uint32_t *rw = reinterpret_cast<const uint32_t *>(sChild + r * K);
+    gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)r * K));
+    uint8_t *dst = sInv + c * K * L + j;
+    for (int w = 0; w < (K >> 2); ++w) {
+      const uint32_t v = rw[w];
+      gw[w] = v;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int s = (int)((v >> (8 * b)) & 0xFFu);
+        if (s < K) dst[s * L] = (uint8_t)(4 * w + b);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Everything of a task but the fitness evaluation; returns the number of
 // chromosomes to evaluate (0 for an elite task or a finished instance).
-// Leaves their inverse rows in sInv and ends with a barrier.
+// Leaves their inverse rows in sInv and ends with a barrier.  sCode: the
+// mutation codes (may alias sInv; apart from it, and with K % 4 == 0, the
+// swaps, write-out and inverse rows are one pass).
 __device__ __forceinline__ int gen_prepare(const GenInst &I, const GenTask &task, int gen,
-                                           uint8_t *sChild, uint8_t *sInv, int32_t *sIdx,
-                                           int32_t *sSel, int block) {
+                                           uint8_t *sChild, uint8_t *sInv, uint8_t *sCode,
+                                           int32_t *sIdx, int32_t *sSel, int block) {
   const int L = I.L, K = I.K, LK = L * K;
   const int in = gen < 0 ? 0 : (gen & 1);
   const int out = gen < 0 ? 0 : 1 - in;
@@ -83,8 +111,14 @@ __device__ __forceinline__ int gen_prepare(const GenInst &I, const GenTask &task
   }
   const int nc = task.s1 - task.s0;
   if (task.kind == kTaskChild) {
+    const bool merged = sCode != sInv && (K & 3) == 0;
     build_children_block(pop_buf(I, in), fit_buf(I, in), I.N, I.E, L, K, I.ga, (uint32_t)gen,
-                         task.s0, nc, sChild, sInv, sSel, block);
+                         task.s0, nc, sChild, sCode, sSel, block, !merged);
+    if (merged) {
+      finish_rows(sChild, sCode, nc, L, K, K >= 2 && I.ga.thr_mut != 0,
+                  pop_buf(I, out) + (size_t)task.s0 * LK, sInv, block);
+      return nc;
+    }
     store_bytes(pop_buf(I, out) + (size_t)task.s0 * LK, sChild, nc * LK);
     build_inverse(sChild, nc * L, L, K, sInv);
   } else {
@@ -115,6 +149,9 @@ __device__ __forceinline__ PairSpan pair_span(const GenInst &I, const GenTask &t
 
 // SELECT words of the task's pairs into sPair (6 per pair: u0, v0, u1, v1,
 // crossover word, cut word) and mutation codes of its children into codes.
+// Every thread must call it; no barrier (the caller's next one publishes the
+// results: a workgroup barrier here, ahead of the grid barrier, measurably
+// lengthens every generation).
 __device__ __forceinline__ void pf_precompute(const GenInst &I, const GenTask &task, int gen,
                                               uint8_t *codes, int32_t *sPair, int block) {
   const int N = I.N, K = I.K, LK = I.L * K;
@@ -133,20 +170,8 @@ __device__ __forceinline__ void pf_precompute(const GenInst &I, const GenTask &t
     w[4] = (int32_t)b1.x;
     w[5] = (int32_t)b1.y;
   }
-  if (K >= 2 && ga.thr_mut != 0) {
-    const int nc = task.s1 - task.s0, nb = (LK + 3) >> 2;
-    for (int i = tid; i < nc * nb; i += block) {
-      const int c = i / nb, b = i - c * nb;
-      const uint32_t v = mutation_codes(b, LK, K, ga, (uint32_t)gen, (uint32_t)(task.s0 + c));
-      uint8_t *dst = codes + c * LK + 4 * b;
-      if ((LK & 3) == 0) {
-        *reinterpret_cast<uint32_t *>(dst) = v;
-      } else {
-        const int n = LK - 4 * b < 4 ? LK - 4 * b : 4;
-        for (int u = 0; u < n; ++u) dst[u] = (uint8_t)(v >> (8 * u));
-      }
-    }
-  }
+  if (K >= 2 && ga.thr_mut != 0)
+    mutation_codes_block(codes, task.s1 - task.s0, LK, K, ga, (uint32_t)gen, task.s0, block);
 }
 
 // The children of a prepared task (pf_precompute of this generation done and
@@ -234,28 +259,11 @@ __device__ __forceinline__ int pf_build(const GenInst &I, const GenTask &task, i
     }
   }
   __syncthreads();
-  // 3. one thread per row: the swaps, then (K % 4 == 0: rows are whole
-  // aligned words) the row's inverse entries and its write-out
+  // 3. the swaps; with K % 4 == 0 merged with the write-out and inverse rows
   const bool mutate = K >= 2 && I.ga.thr_mut != 0;
   uint8_t *pout = pop_buf(I, out) + (size_t)task.s0 * LK;
   if ((K & 3) == 0) {
-    for (int r = tid; r < nc * L; r += block) {
-      if (mutate) apply_swaps(sChild + r * K, sCode + r * K, r * K, K);
-      const int c = r / L, j = r - c * L;
-      const uint32_t *rw = reinterpret_cast<const uint32_t *>(sChild + r * K);
-      gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)r * K));
-      uint8_t *dst = sInv + c * K * L + j;
-      for (int w = 0; w < (K >> 2); ++w) {
-        const uint32_t v = rw[w];
-        gw[w] = v;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int s = (int)((v >> (8 * b)) & 0xFFu);
-          if (s < K) dst[s * L] = (uint8_t)(4 * w + b);
-        }
-      }
-    }
-    __syncthreads();
+    finish_rows(sChild, sCode, nc, L, K, mutate, pout, sInv, block);
     return nc;
   }
   if (mutate) {
@@ -269,15 +277,24 @@ __device__ __forceinline__ int pf_build(const GenInst &I, const GenTask &task, i
   return nc;
 }
 
+// What a workgroup's LDS holds between tasks: the instance whose table (or,
+// tiled, whose own-cell squares) it holds, and with tiled tables which tile.
+struct LdsState {
+  int inst = -1;
+  int tile = -1;
+};
+
 // One task of one generation for a workgroup of the unrolled kernel.  I is a
 // copy of the instance descriptor in registers, read before the task's first
 // global store: a descriptor field loaded after a store would make its wait
 // (the vector-memory counter is in order) wait for the store as well.
-// `loaded` is the instance whose table sits in LDS (-1: none); `prepared`:
-// the child task's draws were made ahead (persistent form).
-template <int LT, int TPT, int MODE, int BLOCK, bool PF = false>
-__device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task, int gen,
-                                         unsigned char *smem, int &loaded, bool prepared) {
+// `prepared`: the child task's draws were made ahead (persistent form).
+// KIND >= 0: the task is known to be of that kind (only its code is built).
+template <int LT, int TPT, int MODE, int BLOCK, bool PF = false, int KIND = -1>
+__device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task_in, int gen,
+                                         unsigned char *smem, LdsState &st, bool prepared) {
+  GenTask task = task_in;
+  if constexpr (KIND >= 0) task.kind = KIND;
   using P = GenPlan<LT, TPT, MODE, BLOCK, PF>;
   constexpr int NT = P::kTiles;
   constexpr int TR = P::kTileRows;
@@ -288,34 +305,36 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task, 
   int32_t *sIdx = reinterpret_cast<int32_t *>(smem + P::kIdxOff);
   float *sOwn = reinterpret_cast<float *>(smem + P::kOwnOff);
   int32_t *sSel = reinterpret_cast<int32_t *>(smem + P::kSelOff);
+  uint8_t *sCode = smem + P::kCodeOff;
   if (gen >= I.G) return;  // this instance has finished its generations
   const int out = gen < 0 ? 0 : 1 - (gen & 1);
   float *const fit_out = fit_buf(I, out) + task.s0;
   const float prelog = I.prelog;
   const bool mn = I.objective != 0;
-  if (task.kind != kTaskElite && task.inst != loaded) {
+  if (task.kind != kTaskElite && task.inst != st.inst) {
     // every thread passed a barrier since the tables were last read
     if constexpr (NT == 1)
       load_tile<MODE>(I.T2, I.T1, LT, TPT, 0, LT, TR, sT);
     else
       load_own(I.Town, LT, TPT, sOwn);
-    loaded = task.inst;
+    st.inst = task.inst;
+    st.tile = -1;
   }
   int nc;
   if constexpr (PF) {
     if (task.kind == kTaskChild) {
       int32_t *sPair = reinterpret_cast<int32_t *>(smem + P::kPairOff);
       if (!prepared) {
-        pf_precompute(I, task, gen, smem + P::kCodeOff, sPair, BLOCK);
+        pf_precompute(I, task, gen, sCode, sPair, BLOCK);
         __syncthreads();
       }
       nc = pf_build(I, task, gen, sChild, sInv, smem + P::kCandOff, sPair,
-                    reinterpret_cast<int32_t *>(smem + P::kResOff), smem + P::kCodeOff, BLOCK);
+                    reinterpret_cast<int32_t *>(smem + P::kResOff), sCode, BLOCK);
     } else {
-      nc = gen_prepare(I, task, gen, sChild, sInv, sIdx, sSel, BLOCK);
+      nc = gen_prepare(I, task, gen, sChild, sInv, sCode, sIdx, sSel, BLOCK);
     }
   } else {
-    nc = gen_prepare(I, task, gen, sChild, sInv, sIdx, sSel, BLOCK);
+    nc = gen_prepare(I, task, gen, sChild, sInv, sCode, sIdx, sSel, BLOCK);
   }
   if (nc == 0) return;
   const int K = I.K;
@@ -343,21 +362,21 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task, 
                                                mn);
   else
     acc = lane_sum_tiled<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z, I.T1,
-                                            I.lconst, mn);
+                                            I.lconst, st.tile, mn);
   reduce_round(sE, acc, active, nc, K, prelog, fit_out, mn);
 }
 
 // Tasks [t0, t1) of one generation for a workgroup (gens: per-instance
 // generations, or null for `gen`).
-template <int LT, int TPT, int MODE, int BLOCK, bool PF = false>
+template <int LT, int TPT, int MODE, int BLOCK, bool PF = false, int KIND = -1>
 __device__ __forceinline__ void gen_tasks_exact(const GenInst *insts, const GenTask *tasks,
                                                 int t0, int t1, int gen, unsigned char *smem,
-                                                int &loaded, const int32_t *gens = nullptr) {
+                                                LdsState &st, const int32_t *gens = nullptr) {
   for (int t = t0; t < t1; ++t) {
     const GenTask task = load_task(tasks, t);
     const GenInst I = insts[task.inst];
     const int g = gens ? gp(gens)[task.inst] : gen;
-    run_task<LT, TPT, MODE, BLOCK, PF>(I, task, g, smem, loaded, false);
+    run_task<LT, TPT, MODE, BLOCK, PF, KIND>(I, task, g, smem, st, false);
   }
 }
 
@@ -366,8 +385,8 @@ __global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int t0 = blockIdx.x * a.chunk;
   const int t1 = min(a.ntasks, t0 + a.chunk);
-  int loaded = -1;
-  gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, loaded, a.gens);
+  LdsState st;
+  gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, st, a.gens);
 }
 
 // ---- persistent form: generations [g0, g1) in one cooperative launch -------
@@ -454,7 +473,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_persist(PersistArgs a) {
   using P = PersistPlan<LT, TPT, MODE, BLOCK>;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   int32_t *sIdx = reinterpret_cast<int32_t *>(smem + P::kIdxOff);
-  int loaded = -1;
+  LdsState st;
   uint32_t nbar = 0;
   // with one task per workgroup (the persistent plans), the workgroup's
   // generation task and its descriptor are read once, into registers
@@ -466,12 +485,18 @@ __global__ __launch_bounds__(BLOCK) void k_gen_persist(PersistArgs a) {
   for (int gen = a.g0; gen < a.g1; ++gen) {
     if (gen < 0) {
       const int t0 = blockIdx.x * a.echunk, t1 = min(a.neval, t0 + a.echunk);
-      gen_tasks_exact<LT, TPT, MODE, BLOCK, PF>(a.insts, a.evals, t0, t1, gen, smem, loaded);
-    } else if (fixed) {
-      run_task<LT, TPT, MODE, BLOCK, PF>(mI, mt, gen, smem, loaded, prepared);
+      gen_tasks_exact<LT, TPT, MODE, BLOCK, PF, kTaskEval>(a.insts, a.evals, t0, t1, gen, smem,
+                                                           st);
     } else {
-      const int t0 = blockIdx.x * a.chunk, t1 = min(a.ntasks, t0 + a.chunk);
-      gen_tasks_exact<LT, TPT, MODE, BLOCK, PF>(a.insts, a.tasks, t0, t1, gen, smem, loaded);
+      // one inlined copy of the task code for both forms keeps the kernel's
+      // per-generation code compact
+      const int t0 = fixed ? 0 : blockIdx.x * a.chunk;
+      const int t1 = fixed ? 1 : min(a.ntasks, t0 + a.chunk);
+      for (int t = t0; t < t1; ++t) {
+        const GenTask task = fixed ? mt : load_task(a.tasks, t);
+        const GenInst I = fixed ? mI : a.insts[task.inst];
+        run_task<LT, TPT, MODE, BLOCK, PF>(I, task, gen, smem, st, prepared);
+      }
     }
     prepared = false;
     if constexpr (PF) {
@@ -517,7 +542,7 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
       load_tile<MODE>(I.T2, I.T1, L, TP, 0, L, TR, sT);
       loaded = task.inst;
     }
-    const int nc = gen_prepare(I, task, gen, sChild, sInv, sIdx, sSel, (int)blockDim.x);
+    const int nc = gen_prepare(I, task, gen, sChild, sInv, sInv, sIdx, sSel, (int)blockDim.x);
     if (nc == 0) continue;
     const int K = I.K;
     const int q = threadIdx.x;

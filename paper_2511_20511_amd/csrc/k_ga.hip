@@ -26,7 +26,7 @@ struct GaArgs {
 
 // Workgroup 0 copies the elites; workgroup b >= 1 builds the children of
 // slots E + (b-1)*cpw ... with the whole workgroup (ga_core.h) and writes them.
-// Dynamic LDS: children (cpw*L*K) | mutation flags (cpw*L*K) | 2 ints per child
+// Dynamic LDS: children (cpw*L*K) | mutation codes (cpw*L*K) | 2 ints per child
 // | 64 elite indices.
 __global__ __launch_bounds__(kGaBlock) void k_ga_step(GaArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];

@@ -183,8 +183,9 @@ hipError_t launch_persist(SolvePlan *pl, const DeviceInfo &dev, int g0, int g1, 
 
 // Autotuning of the persistent form: every candidate shape (children per
 // task = block / K / div for div = 1, 2, 4, ..., all tasks co-resident) runs
-// the start and the first generations of the plan's own instances; the
-// fastest is kept.  Shapes change the schedule, never a result bit.
+// the start and the first 8 and 40 generations of the plan's own instances;
+// the shape whose cost extrapolated to the plan's generation count is
+// smallest is kept.  Shapes change the schedule, never a result bit.
 pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
                           const std::vector<int> &members, const std::vector<GenInst> &hi,
                           int block, int cap) {
@@ -206,28 +207,34 @@ pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
   pl->persist = true;
   size_t best = 0;
   if (cands.size() > 1) {
+    // each shape's start-up and per-generation cost from a short and a long
+    // run (best of two each), extrapolated to the plan's generation count
     hipStream_t cs = ctx->stream;
-    const int g1 = std::min(pl->Gmax, 16);
+    const int gs = std::min(pl->Gmax, 8), gl = std::min(pl->Gmax, 40);
     float best_ms = 0.0f;
     for (size_t c = 0; c < cands.size(); ++c) {
       pl->classes.assign(1, cands[c]);
       pl->pgrid = cands[c].c.ntasks;
-      float ms = 0.0f;
-      for (int rep = 0; rep < 2; ++rep) {
-        PTRY(launch_start(pl, cs), "tuning");
-        PTRY(hipEventRecord(pl->ev0, cs), "hipEventRecord");
-        PTRY(launch_persist(pl, ctx->info, -1, g1, false, cs), "tuning");
-        PTRY(hipEventRecord(pl->ev1, cs), "hipEventRecord");
-        PTRY(hipEventSynchronize(pl->ev1), "hipEventSynchronize");
-        float t = 0.0f;
-        PTRY(hipEventElapsedTime(&t, pl->ev0, pl->ev1), "hipEventElapsedTime");
-        ms = rep == 0 ? t : std::min(ms, t);
+      float t[2] = {0.0f, 0.0f};
+      for (int k = 0; k < (gl > gs ? 2 : 1); ++k) {
+        for (int rep = 0; rep < 2; ++rep) {
+          PTRY(launch_start(pl, cs), "tuning");
+          PTRY(hipEventRecord(pl->ev0, cs), "hipEventRecord");
+          PTRY(launch_persist(pl, ctx->info, -1, k == 0 ? gs : gl, false, cs), "tuning");
+          PTRY(hipEventRecord(pl->ev1, cs), "hipEventRecord");
+          PTRY(hipEventSynchronize(pl->ev1), "hipEventSynchronize");
+          float ms = 0.0f;
+          PTRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1), "hipEventElapsedTime");
+          t[k] = rep == 0 ? ms : std::min(t[k], ms);
+        }
       }
+      const float est =
+          gl > gs ? t[0] + (t[1] - t[0]) * (float)(pl->Gmax - gs) / (float)(gl - gs) : t[0];
       uint32_t sync[2] = {0, 0};
       PTRY(hipMemcpy(sync, pl->d_sync, sizeof sync, hipMemcpyDeviceToHost), "tuning");
       if (sync[1] != 0) return set_error(PA_EINTERNAL, "persistent solve: a grid barrier wait timed out");
-      if (c == 0 || ms < best_ms) {
-        best_ms = ms;
+      if (c == 0 || est < best_ms) {
+        best_ms = est;
         best = c;
       }
     }
