@@ -509,8 +509,15 @@ __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, 
   const int q = threadIdx.x;
   const int c = q / K, p = q - c * K;
   float v = acc;
-  if (K <= 16 && (K & (K - 1)) == 0) {
-    // a chromosome's lanes lie inside one DPP row: the tree in registers
+  if (K <= 32 && (K & (K - 1)) == 0) {
+    // a chromosome's lanes lie inside one DPP row (K <= 16) or one aligned
+    // group of 32 lanes (K = 32): the tree in registers; the stride-16 step
+    // reads lane p ^ 16 (= p + 16 for the lanes p < 16 that keep their sum)
+    // with a bit-mask swizzle inside the 32-lane group
+    if (K >= 32) {
+      const int o = __builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x1F | (0x10 << 10));
+      v = obj_add(v, __int_as_float(o), mn);
+    }
     if (K >= 16) v = add_from_lane_plus<8>(v, mn);
     if (K >= 8) v = add_from_lane_plus<4>(v, mn);
     if (K >= 4) v = add_from_lane_plus<2>(v, mn);
