@@ -235,6 +235,97 @@ __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, 
   return acc;
 }
 
+// Quad layout of a whole table in LDS: Q[j][u][l], the BS rows l of one
+// (cell j, pilot u) contiguous and padded to LP rows, LP a multiple of 4 with
+// LP / 4 odd so that the 16-byte row groups of different pilots start in
+// different bank groups.  A lane then reads four BS rows of one cell with a
+// single ds_read_b128 (the padding rows are never used).
+template <int LT>
+constexpr int quad_rows() {
+  return ((LT + 3) / 4) % 2 == 1 ? (LT + 3) / 4 * 4 : (LT + 3) / 4 * 4 + 4;
+}
+
+// Copies the cell-major table T2[j][l][TP] into the quad layout (16-byte
+// global loads, up to 8 in flight per thread; scalar LDS stores).
+__device__ __forceinline__ void load_quad(const float *__restrict__ T2, int L, int TP, int LP,
+                                          float *dst) {
+  constexpr int kBatch = 8;
+  const int q = TP >> 2;  // float4 per table row
+  const int per_cell = L * q;
+  const int total = L * per_cell;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const gptr<const f4> s2 = gp(reinterpret_cast<const f4 *>(T2));
+  const int step = (int)blockDim.x;
+  for (int base = threadIdx.x; base < total; base += kBatch * step) {
+    f4 v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) v[u] = s2[min(base + u * step, total - 1)];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = base + u * step;
+      if (i < total) {
+        const int j = i / per_cell, rem = i - j * per_cell;
+        const int l = rem / q, c = rem - l * q;
+        float *d = dst + ((size_t)j * TP + 4 * c) * LP + l;
+        d[0] = v[u].x;
+        d[LP] = v[u].y;
+        d[2 * LP] = v[u].z;
+        d[3 * LP] = v[u].w;
+      }
+    }
+  }
+}
+
+// lane_sum_exact (asymptotic SE) on the quad layout: for each group of four
+// BS rows, one 16-byte gather per cell feeds the four rows' interference
+// sums, each over j != l in increasing j; the SE terms are added in
+// increasing l.  Same arithmetic, same order, same bits as lane_sum_exact.
+template <int LT, int TPT>
+__device__ __forceinline__ float lane_sum_quad(const uint8_t *ip, bool active, const float *sQ,
+                                               bool mn = false) {
+  constexpr int LP = quad_rows<LT>();
+  constexpr int CELLB = TPT * LP * 4;  // bytes per cell
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const char *lds = reinterpret_cast<const char *>(sQ);
+  uint32_t A[LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) A[j] = ip[j];  // in bounds for inactive lanes too
+#pragma unroll
+  for (int j = 0; j < LT; ++j) {
+    const uint32_t v = active ? A[j] : 0u;
+    A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * (uint32_t)(LP * 4);
+  }
+  float acc = obj_init(mn);
+#pragma unroll
+  for (int g = 0; g < LP / 4; ++g) {
+    if (4 * g < LT) {
+      float I[4] = {0.0f, 0.0f, 0.0f, 0.0f}, b2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int j = 0; j < LT; ++j) {
+        const f4 v = *reinterpret_cast<const f4 *>(lds + A[j] + 16 * g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = 4 * g + r;
+          if (l < LT) {
+            if (j == l)
+              b2[r] = v[r];
+            else
+              I[r] = I[r] + v[r];
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * g + r < LT) acc = obj_add(acc, se_asym(b2[r], I[r], mn), mn);
+      // the next group's gathers wait for this group's sum: without this the
+      // compiler hoists every group's loads to the top and spills
+#pragma unroll
+      for (int j = 0; j < LT; ++j) asm volatile("" : "+v"(A[j]) : "v"(acc));
+    }
+  }
+  return acc;
+}
+
 // Latency form of lane_sum_exact for a whole-table tile: the BS rows are
 // split over RS groups of GS lanes (GS >= 64, so the group index is uniform
 // per wave).  Lane ql of group rg computes the SE terms of rows l = rg,

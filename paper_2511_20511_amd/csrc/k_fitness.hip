@@ -36,7 +36,9 @@ struct FitArgs {
 // LDS plan of the population-fitness kernels: the table tile, then the
 // inverse rows (<= block*L bytes), then the per-(c, p) sums (block*4 bytes),
 // the own-cell squares, the round's chromosome bytes and, for tiled tables,
-// the partial sums of a group of kGroup rounds (kGroup*block floats).
+// the partial sums of a group of kGroup rounds (kGroup*block floats).  An
+// asymptotic-SE table that fits whole in its quad layout (fitness_core.h) is
+// staged that way (kQuad).
 template <int LT, int TPT, int MODE, int BLOCK>
 struct ExactPlan {
   static constexpr int kInvBytes = ((BLOCK * LT) + 15) / 16 * 16;
@@ -49,7 +51,9 @@ struct ExactPlan {
   using T = TilePlan<LT, TPT, MODE, kBase + kAccBytes>;
   static constexpr int kTiles = T::kTiles;
   static constexpr int kTileRows = T::kTileRows;
-  static constexpr int kInvOff = T::kTableBytes;
+  static constexpr int kQuadBytes = LT * TPT * quad_rows<LT>() * 4;
+  static constexpr bool kQuad = MODE == 0 && kTiles == 1 && kQuadBytes + kBase + 256 <= kLdsBytes;
+  static constexpr int kInvOff = kQuad ? kQuadBytes : T::kTableBytes;
   static constexpr int kEOff = kInvOff + kInvBytes;
   static constexpr int kOwnOff = kEOff + kEBytes;
   static constexpr int kStageOff = kOwnOff + kOwnBytes;
@@ -132,6 +136,9 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
       }
     }
     return;
+  } else if constexpr (P::kQuad) {
+    load_quad(a.T2, LT, TPT, quad_rows<LT>(), sT);
+    __syncthreads();
   } else {
     load_tile<MODE>(a.T2, a.T1, LT, TPT, 0, LT, TR, sT);
     __syncthreads();
@@ -152,8 +159,12 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
     build_inverse(sStage, nc * LT, LT, K, sInv);
     __syncthreads();
     const bool active = q / K < nc;
-    const float acc =
-        lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst, mn);
+    float acc;
+    if constexpr (P::kQuad)
+      acc = lane_sum_quad<LT, TPT>(sInv + q * LT, active, sT, mn);
+    else
+      acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst,
+                                                 mn);
     reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn);
   }
 }
