@@ -413,14 +413,22 @@ struct PersistArgs {
 
 constexpr uint32_t kBarrierSpins = 1u << 21;
 
-__device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t target, int32_t *err,
-                                             int32_t *sFlag) {
-  // every wave: its global writes complete and written back at agent scope
+// The grid barrier in two halves, so that a workgroup can do work that
+// needs nothing from the others (the next generation's draws) between its
+// arrival and its wait.  Arrival: every wave's global writes complete and
+// written back at agent scope, then one arrival.
+__device__ __forceinline__ void grid_arrive(uint32_t *bar) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until `target` arrivals (bounded, see above); then every wave
+// acquires, so later reads see what other workgroups wrote before arriving.
+__device__ __forceinline__ bool grid_wait(uint32_t *bar, uint32_t target, int32_t *err,
+                                          int32_t *sFlag) {
   if (threadIdx.x == 0) {
     int good = 1;
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (uint32_t spins = 0;; ++spins) {
       if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
       if (spins >= kBarrierSpins ||
@@ -435,7 +443,6 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t target, int
   }
   __syncthreads();
   const bool ok = *sFlag != 0;
-  // every wave: later reads see what other workgroups wrote before arriving
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return ok;
 }
@@ -499,8 +506,10 @@ __global__ __launch_bounds__(BLOCK) void k_gen_persist(PersistArgs a) {
       }
     }
     prepared = false;
+    grid_arrive(a.bar);
     if constexpr (PF) {
-      // prepare the next generation's child task while others finish this one
+      // prepare the next generation's child task (LDS only, nothing from the
+      // other workgroups) while they finish this one
       if (fixed && gen + 1 < a.g1 && mt.kind == kTaskChild && gen + 1 < mI.G) {
         pf_precompute(mI, mt, gen + 1, smem + P::kCodeOff,
                       reinterpret_cast<int32_t *>(smem + P::kPairOff), BLOCK);
@@ -508,7 +517,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_persist(PersistArgs a) {
       }
     }
     // sIdx[63] is free here: elite tasks use sIdx[0 .. E) with E < 64
-    if (!grid_barrier(a.bar, ++nbar * gridDim.x, a.err, sIdx + 63)) return;
+    if (!grid_wait(a.bar, ++nbar * gridDim.x, a.err, sIdx + 63)) return;
   }
   if (a.best)
     for (int i = blockIdx.x; i < a.ninst; i += gridDim.x) best_block(a.insts[i], sIdx);
