@@ -170,39 +170,27 @@ __device__ __forceinline__ void copy_elites(const uint8_t *__restrict__ pin,
 // little-endian word: byte u = kp + 1 when gene i = 4b + u (cell j = i / K,
 // user k = i % K) mutates and swaps with user kp of its row, 0 otherwise (and
 // 0 past the chromosome's LK genes).  The decision of gene i is word i of the
-// MUT_DECIDE stream, its partner word i of the MUT_PARTNER stream.  Split in
-// two: the decision mask (bit u: gene 4b + u mutates) and the partners of a
-// nonzero mask.
-__device__ __forceinline__ uint32_t mutation_mask(int b, const DevGa &ga, uint32_t gen,
-                                                  uint32_t slot) {
+// MUT_DECIDE stream, its partner word i of the MUT_PARTNER stream.  Both
+// Philox blocks are drawn unconditionally, as two independent dependence
+// chains the scheduler can overlap (a wave almost always has a lane that needs
+// the partner block anyway).
+__device__ __forceinline__ uint32_t mutation_codes(int b, int LK, int K, const DevGa &ga,
+                                                   uint32_t gen, uint32_t slot) {
   const Stream dec{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutDecide};
-  const Words4 w = dec.block((uint32_t)b);
-  return (hit(w.x, ga.thr_mut) ? 1u : 0u) | (hit(w.y, ga.thr_mut) ? 2u : 0u) |
-         (hit(w.z, ga.thr_mut) ? 4u : 0u) | (hit(w.w, ga.thr_mut) ? 8u : 0u);
-}
-
-__device__ __forceinline__ uint32_t mutation_partners(int b, uint32_t mask, int LK, int K,
-                                                      const DevGa &ga, uint32_t gen,
-                                                      uint32_t slot) {
   const Stream par{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutPartner};
+  const Words4 w = dec.block((uint32_t)b);
   const Words4 pw = par.block((uint32_t)b);
   uint32_t out = 0u;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int i = 4 * b + u;
-    if (((mask >> u) & 1u) != 0u && i < LK) {
+    if (hit(pick(w, (uint32_t)u), ga.thr_mut) && i < LK) {
       const int k = i % K;
       const uint32_t r = bounded(pick(pw, (uint32_t)u), (uint32_t)(K - 1));
       out |= (uint32_t)((int)r + ((int)r >= k ? 1 : 0) + 1) << (8 * u);
     }
   }
   return out;
-}
-
-__device__ __forceinline__ uint32_t mutation_codes(int b, int LK, int K, const DevGa &ga,
-                                                   uint32_t gen, uint32_t slot) {
-  const uint32_t m = mutation_mask(b, ga, gen, slot);
-  return m == 0u ? 0u : mutation_partners(b, m, LK, K, ga, gen, slot);
 }
 
 // Stores the code word of genes 4b .. 4b+3 of a child whose codes start at
@@ -218,15 +206,24 @@ __device__ __forceinline__ void store_code_word(uint8_t *codes, int LK, int b, u
 }
 
 // Mutation codes of the children of slots [s0, s0 + nc) into `codes` (child c
-// at byte c*LK) with the whole workgroup, one (child, Philox block) pair per
-// thread and step.  No barrier: the caller's next one publishes the codes.
+// at byte c*LK) with the whole workgroup, two (child, Philox block) pairs per
+// thread and step, their four Philox blocks drawn together.  No barrier: the
+// caller's next one publishes the codes.
 __device__ __forceinline__ void mutation_codes_block(uint8_t *codes, int nc, int LK, int K,
                                                      const DevGa &ga, uint32_t gen, int s0,
                                                      int block) {
   const int nb = (LK + 3) >> 2;
-  for (int i = threadIdx.x; i < nc * nb; i += block) {
+  const int total = nc * nb;
+  for (int i = threadIdx.x; i < total; i += 2 * block) {
+    const int i2 = i + block;
+    const bool two = i2 < total;
+    const int j2 = two ? i2 : i;  // a valid pair to draw for (not stored)
     const int c = i / nb, b = i - c * nb;
-    store_code_word(codes + c * LK, LK, b, mutation_codes(b, LK, K, ga, gen, (uint32_t)(s0 + c)));
+    const int c2 = j2 / nb, b2 = j2 - c2 * nb;
+    const uint32_t v = mutation_codes(b, LK, K, ga, gen, (uint32_t)(s0 + c));
+    const uint32_t v2 = mutation_codes(b2, LK, K, ga, gen, (uint32_t)(s0 + c2));
+    store_code_word(codes + c * LK, LK, b, v);
+    if (two) store_code_word(codes + c2 * LK, LK, b2, v2);
   }
 }
 

@@ -181,27 +181,31 @@ hipError_t launch_start(SolvePlan *pl, hipStream_t s);
 hipError_t launch_persist(SolvePlan *pl, const DeviceInfo &dev, int g0, int g1, bool best,
                           hipStream_t s);
 
-// Autotuning of the persistent form: every candidate shape (children per
-// task = block / K / div for div = 1, 2, 4, ..., all tasks co-resident) runs
+// Autotuning of the persistent form: every candidate shape (block size from
+// `blocks`, each with its co-residency cap; children per task = block / K /
+// div for div = 1, 2, 4, ..., all tasks co-resident) runs
 // the start and the first 8 and 40 generations of the plan's own instances;
 // the shape whose cost extrapolated to the plan's generation count is
 // smallest is kept.  Shapes change the schedule, never a result bit.
 pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
                           const std::vector<int> &members, const std::vector<GenInst> &hi,
-                          int block, int cap) {
+                          const std::vector<std::pair<int, int>> &blocks) {
   int maxK = 0;
   for (int i : members) maxK = std::max(maxK, hi[i].K);
   std::vector<PlanClass> cands;
-  int last_tasks = -1;
-  for (int div = 1; div <= std::max(1, block / maxK); div *= 2) {
-    const int nt = count_tasks(members, pl->insts, pl->params, block, div);
-    if (nt > cap) break;
-    if (nt == last_tasks) continue;
-    last_tasks = nt;
-    PlanClass pc;
-    pa_status st = make_class(pl, key, members, hi, Shape{block, div}, ctx->info.cus, &pc);
-    if (st != PA_OK) return st;
-    cands.push_back(pc);
+  for (const auto &bc : blocks) {
+    const int block = bc.first, cap = bc.second;
+    int last_tasks = -1;
+    for (int div = 1; div <= std::max(1, block / maxK); div *= 2) {
+      const int nt = count_tasks(members, pl->insts, pl->params, block, div);
+      if (nt > cap) break;
+      if (nt == last_tasks) continue;
+      last_tasks = nt;
+      PlanClass pc;
+      pa_status st = make_class(pl, key, members, hi, Shape{block, div}, ctx->info.cus, &pc);
+      if (st != PA_OK) return st;
+      cands.push_back(pc);
+    }
   }
   if (cands.empty()) return set_error(PA_EINTERNAL, "no persistent shape");
   pl->persist = true;
@@ -325,31 +329,32 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
   }
   const int cus = ctx->info.cus;
   // persistent form: one class with an unrolled variant whose full tasks
-  // (block / K children each) all fit on the device at once
-  Shape pshape{0, 1};
-  int pcap = 0;
+  // (block / K children each) all fit on the device at once, for 256- and
+  // 512-thread workgroups (512 only for tiled tables)
+  std::vector<std::pair<int, int>> pblocks;
   if (groups.size() == 1 && exact_variant(groups[0].first.L, groups[0].first.TP)) {
     const ClassKey &key = groups[0].first;
-    GenClass q;
-    q.L = key.L;
-    q.TP = key.TP;
-    q.mode = key.mode;
-    q.block = tiled(key.L, key.TP, key.mode, 256) ? 512 : 256;
-    int cap = 0;
-    PersistLaunch ql{};
-    ql.grid = 1;
-    PTRY(launch_gen_persist(pl->d_insts, q, ql, ctx->info, &cap, nullptr), "occupancy query");
-    if (cap > 0 && count_tasks(groups[0].second, pl->insts, pl->params, q.block) <= cap) {
-      pshape = Shape{q.block, 1};
-      pcap = cap;
+    for (int block : {256, 512}) {
+      if (block == 256 && tiled(key.L, key.TP, key.mode, 256)) continue;
+      GenClass q;
+      q.L = key.L;
+      q.TP = key.TP;
+      q.mode = key.mode;
+      q.block = block;
+      int cap = 0;
+      PersistLaunch ql{};
+      ql.grid = 1;
+      PTRY(launch_gen_persist(pl->d_insts, q, ql, ctx->info, &cap, nullptr), "occupancy query");
+      if (cap > 0 && count_tasks(groups[0].second, pl->insts, pl->params, block) <= cap)
+        pblocks.push_back({block, cap});
     }
   }
   PTRY(alloc(pl, &pl->d_sync, 2), "hipMalloc(plan)");
   PTRY(hipMemset(pl->d_sync, 0, 2 * sizeof(uint32_t)), "hipMemset");
   PTRY(hipEventCreate(&pl->ev0), "hipEventCreate");
   PTRY(hipEventCreate(&pl->ev1), "hipEventCreate");
-  if (pshape.block) {
-    pa_status st = tune_persistent(pl, ctx, groups[0].first, groups[0].second, hi, pshape.block, pcap);
+  if (!pblocks.empty()) {
+    pa_status st = tune_persistent(pl, ctx, groups[0].first, groups[0].second, hi, pblocks);
     if (st != PA_OK) return st;
   } else {
     for (auto &grp : groups) {
