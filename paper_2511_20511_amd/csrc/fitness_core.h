@@ -381,6 +381,56 @@ __device__ __forceinline__ float lane_sum_split(const uint8_t *sInv, int ql, boo
   return acc;
 }
 
+// lane_sum_split on the quad layout (asymptotic SE): group rg takes the
+// four-row groups rg, rg + RS, ...; per group one 16-byte gather per cell
+// feeds four interference sums (over j != l in increasing j), the SE terms go
+// to sSe[ql][l] and after a barrier lane ql of group 0 adds its L terms in
+// increasing l.  Same bits as lane_sum_split.  Every thread of the workgroup
+// must call it.
+template <int LT, int TPT>
+__device__ __forceinline__ float lane_sum_split_quad(const uint8_t *sInv, int ql, bool active,
+                                                     int rg, int RS, const float *sQ, float *sSe,
+                                                     bool mn = false) {
+  constexpr int LP = quad_rows<LT>();
+  constexpr int CELLB = TPT * LP * 4;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const char *lds = reinterpret_cast<const char *>(sQ);
+  const uint8_t *ip = sInv + ql * LT;  // inside the inverse region for every lane
+  uint32_t A[LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) A[j] = ip[j];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) {
+    const uint32_t v = active ? A[j] : 0u;
+    A[j] = (uint32_t)(j * CELLB) + (v & (TPT - 1)) * (uint32_t)(LP * 4);
+  }
+  for (int g = rg; 4 * g < LT; g += RS) {
+    float I[4] = {0.0f, 0.0f, 0.0f, 0.0f}, b2[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int j = 0; j < LT; ++j) {
+      const f4 v = *reinterpret_cast<const f4 *>(lds + A[j] + 16 * g);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const bool own = j == 4 * g + r;
+        b2[r] = own ? v[r] : b2[r];
+        I[r] = own ? I[r] : I[r] + v[r];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int l = 4 * g + r;
+      if (l < LT) sSe[ql * LT + l] = se_asym(b2[r], I[r], mn);
+    }
+  }
+  __syncthreads();
+  float acc = obj_init(mn);
+  if (rg == 0) {
+#pragma unroll
+    for (int l = 0; l < LT; ++l) acc = obj_add(acc, sSe[ql * LT + l], mn);
+  }
+  return acc;
+}
+
 // Tiled tables (more BS rows than LDS holds).  The tiles hold the table with
 // its own-cell entries zeroed (T2z[j][l][.] = 0 for j == l) and the own-cell
 // squares come from a small LDS table sOwn[l][p], so the tile loop need not

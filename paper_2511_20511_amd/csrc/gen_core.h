@@ -48,7 +48,11 @@ struct GenPlan {
                          kCandBytes + kPairBytes + kResBytes + kCodeBytes>;
   static constexpr int kTiles = T::kTiles;
   static constexpr int kTileRows = T::kTileRows;
-  static constexpr int kChildOff = T::kTableBytes;
+  // an asymptotic-SE table that fits whole in its quad layout is staged that
+  // way (four BS rows per 16-byte gather)
+  static constexpr int kQuadBytes = LT * TPT * quad_rows<LT>() * 4;
+  static constexpr bool kQuad = MODE == 0 && kTiles == 1 && kQuadBytes <= T::kBudget;
+  static constexpr int kChildOff = kQuad ? kQuadBytes : T::kTableBytes;
   static constexpr int kInvOff = kChildOff + kChildBytes;
   static constexpr int kEOff = kInvOff + kInvBytes;
   static constexpr int kIdxOff = kEOff + kEBytes;
@@ -313,7 +317,9 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task_i
   const bool mn = I.objective != 0;
   if (task.kind != kTaskElite && task.inst != st.inst) {
     // every thread passed a barrier since the tables were last read
-    if constexpr (NT == 1)
+    if constexpr (P::kQuad)
+      load_quad(I.T2, LT, TPT, quad_rows<LT>(), sT);
+    else if constexpr (NT == 1)
       load_tile<MODE>(I.T2, I.T1, LT, TPT, 0, LT, TR, sT);
     else
       load_own(I.Town, LT, TPT, sOwn);
@@ -348,16 +354,23 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task_i
       const int rg = __builtin_amdgcn_readfirstlane(q / GS);
       const int ql = q - rg * GS;
       const bool act = ql < lanes;
-      const float acc = lane_sum_split<LT, TPT, MODE>(
-          sInv, ql, act, rg, BLOCK / GS, sT, reinterpret_cast<float *>(smem + P::kCandOff),
-          I.lconst, mn);
+      float acc;
+      if constexpr (P::kQuad)
+        acc = lane_sum_split_quad<LT, TPT>(sInv, ql, act, rg, BLOCK / GS, sT,
+                                           reinterpret_cast<float *>(smem + P::kCandOff), mn);
+      else
+        acc = lane_sum_split<LT, TPT, MODE>(
+            sInv, ql, act, rg, BLOCK / GS, sT, reinterpret_cast<float *>(smem + P::kCandOff),
+            I.lconst, mn);
       reduce_round(sE, acc, act && rg == 0, nc, K, prelog, fit_out, mn);
       return;
     }
   }
   const bool active = q / K < nc;
   float acc;
-  if constexpr (NT == 1)
+  if constexpr (P::kQuad)
+    acc = lane_sum_quad<LT, TPT>(sInv + q * LT, active, sT, mn);
+  else if constexpr (NT == 1)
     acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, I.T2, I.T1, I.lconst,
                                                mn);
   else
