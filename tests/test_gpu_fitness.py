@@ -51,7 +51,11 @@ def test_fitness_matches_oracle(oracle_mod, L, K, n, se_mode):
     assert err.max() <= TOL
 
 
-@pytest.mark.parametrize("L,K", [(7, 4), (19, 16), (37, 32), (7, 5), (19, 17), (5, 6)])
+# the unrolled kernels stage a whole table in the quad layout (L = 7, 19 and
+# L = 37 up to K = 16, asymptotic SE) or the row layout (finite-M, tiled L = 37,
+# K = 32); the runtime-L kernel always uses the row layout
+@pytest.mark.parametrize("L,K", [(7, 4), (19, 16), (37, 32), (7, 5), (19, 17), (5, 6), (37, 16),
+                                 (37, 4)])
 def test_every_launch_shape_gives_same_bits(L, K):
     torch = need_gpu()
     import paper_2511_20511_amd as pa
