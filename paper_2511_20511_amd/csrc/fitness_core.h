@@ -245,32 +245,47 @@ constexpr int quad_rows() {
   return ((LT + 3) / 4) % 2 == 1 ? (LT + 3) / 4 * 4 : (LT + 3) / 4 * 4 + 4;
 }
 
-// Copies the cell-major table T2[j][l][TP] into the quad layout (16-byte
-// global loads, up to 8 in flight per thread; scalar LDS stores).
-__device__ __forceinline__ void load_quad(const float *__restrict__ T2, int L, int TP, int LP,
-                                          float *dst) {
-  constexpr int kBatch = 8;
-  const int q = TP >> 2;  // float4 per table row
-  const int per_cell = L * q;
-  const int total = L * per_cell;
+// Copies BS rows [r0, r0 + rows) of the cell-major table T2[j][l][TP] into
+// the quad layout Q[j][u][lr] with LP rows per (cell, pilot) (r0 and LP
+// multiples of 4, rows <= LP).  A thread takes 4 rows x 4 pilots of one cell:
+// four 16-byte global loads (a row past the table's last is clamped: its
+// values land in padding rows that are never read), a 4x4 transpose in
+// registers and four 16-byte LDS stores.
+__device__ __forceinline__ void load_quad(const float *__restrict__ T2, int L, int TP, int r0,
+                                          int rows, int LP, float *dst) {
+  constexpr int kBatch = 4;
   typedef float f4 __attribute__((ext_vector_type(4)));
+  const int q = TP >> 2;             // float4 per table row
+  const int ng = (rows + 3) >> 2;    // row groups
+  const int per_cell = ng * q;
+  const int total = L * per_cell;
   const gptr<const f4> s2 = gp(reinterpret_cast<const f4 *>(T2));
+  f4 *d = reinterpret_cast<f4 *>(dst);
   const int step = (int)blockDim.x;
   for (int base = threadIdx.x; base < total; base += kBatch * step) {
-    f4 v[kBatch];
+    f4 v[kBatch][4];
 #pragma unroll
-    for (int u = 0; u < kBatch; ++u) v[u] = s2[min(base + u * step, total - 1)];
+    for (int u = 0; u < kBatch; ++u) {
+      const int i = min(base + u * step, total - 1);  // clamped: every load is in bounds
+      const int j = i / per_cell, rem = i - j * per_cell;
+      const int g = rem / q, c = rem - g * q;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int l = min(r0 + 4 * g + r, L - 1);
+        v[u][r] = s2[((size_t)j * L + l) * q + c];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kBatch; ++u) {
       const int i = base + u * step;
       if (i < total) {
         const int j = i / per_cell, rem = i - j * per_cell;
-        const int l = rem / q, c = rem - l * q;
-        float *d = dst + ((size_t)j * TP + 4 * c) * LP + l;
-        d[0] = v[u].x;
-        d[LP] = v[u].y;
-        d[2 * LP] = v[u].z;
-        d[3 * LP] = v[u].w;
+        const int g = rem / q, c = rem - g * q;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const f4 o = {v[u][0][k], v[u][1][k], v[u][2][k], v[u][3][k]};
+          d[(((size_t)j * TP + 4 * c + k) * LP + 4 * g) >> 2] = o;
+        }
       }
     }
   }

@@ -318,7 +318,7 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task_i
   if (task.kind != kTaskElite && task.inst != st.inst) {
     // every thread passed a barrier since the tables were last read
     if constexpr (P::kQuad)
-      load_quad(I.T2, LT, TPT, quad_rows<LT>(), sT);
+      load_quad(I.T2, LT, TPT, 0, LT, quad_rows<LT>(), sT);
     else if constexpr (NT == 1)
       load_tile<MODE>(I.T2, I.T1, LT, TPT, 0, LT, TR, sT);
     else

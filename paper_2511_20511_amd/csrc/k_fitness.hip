@@ -137,7 +137,7 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
     }
     return;
   } else if constexpr (P::kQuad) {
-    load_quad(a.T2, LT, TPT, quad_rows<LT>(), sT);
+    load_quad(a.T2, LT, TPT, 0, LT, quad_rows<LT>(), sT);
     __syncthreads();
   } else {
     load_tile<MODE>(a.T2, a.T1, LT, TPT, 0, LT, TR, sT);
