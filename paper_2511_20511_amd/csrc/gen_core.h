@@ -428,16 +428,23 @@ constexpr uint32_t kBarrierSpins = 1u << 21;
 
 // The grid barrier in two halves, so that a workgroup can do work that
 // needs nothing from the others (the next generation's draws) between its
-// arrival and its wait.  Arrival: every wave's global writes complete and
-// written back at agent scope, then one arrival.
+// arrival and its wait.  Arrival: every wave waits until its global writes
+// have completed (reached the L2 the workgroup's CU shares), the workgroup
+// barrier orders them before thread 0, whose agent-scope release (a write-back
+// of that L2, which holds every wave's writes) precedes the arrival.
 __device__ __forceinline__ void grid_arrive(uint32_t *bar) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0); expcnt and lgkmcnt not waited on
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// Wait until `target` arrivals (bounded, see above); then every wave
-// acquires, so later reads see what other workgroups wrote before arriving.
+// Wait until `target` arrivals (bounded, see above); thread 0 acquires at
+// agent scope (invalidating the caches of the workgroup's CU) before the
+// workgroup barrier, so every wave's later reads see what other workgroups
+// wrote before arriving.
 __device__ __forceinline__ bool grid_wait(uint32_t *bar, uint32_t target, int32_t *err,
                                           int32_t *sFlag) {
   if (threadIdx.x == 0) {
@@ -452,12 +459,11 @@ __device__ __forceinline__ bool grid_wait(uint32_t *bar, uint32_t target, int32_
       }
       __builtin_amdgcn_s_sleep(2);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *sFlag = good;
   }
   __syncthreads();
-  const bool ok = *sFlag != 0;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  return ok;
+  return *sFlag != 0;
 }
 
 // Best chromosome of an instance's population after its last generation
