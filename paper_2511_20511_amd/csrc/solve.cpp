@@ -186,7 +186,8 @@ hipError_t launch_persist(SolvePlan *pl, const DeviceInfo &dev, int g0, int g1, 
 // div for div = 1, 2, 4, ..., all tasks co-resident) runs
 // the start and the first 8 and 40 generations of the plan's own instances;
 // the shape whose cost extrapolated to the plan's generation count is
-// smallest is kept.  Shapes change the schedule, never a result bit.
+// smallest is kept (within 3%, the larger workgroup).  Shapes change the
+// schedule, never a result bit.
 pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
                           const std::vector<int> &members, const std::vector<GenInst> &hi,
                           const std::vector<std::pair<int, int>> &blocks) {
@@ -215,7 +216,7 @@ pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
     // run (best of two each), extrapolated to the plan's generation count
     hipStream_t cs = ctx->stream;
     const int gs = std::min(pl->Gmax, 8), gl = std::min(pl->Gmax, 40);
-    float best_ms = 0.0f;
+    std::vector<float> ests(cands.size(), 0.0f);
     for (size_t c = 0; c < cands.size(); ++c) {
       pl->classes.assign(1, cands[c]);
       pl->pgrid = cands[c].c.ntasks;
@@ -237,10 +238,16 @@ pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
       uint32_t sync[2] = {0, 0};
       PTRY(hipMemcpy(sync, pl->d_sync, sizeof sync, hipMemcpyDeviceToHost), "tuning");
       if (sync[1] != 0) return set_error(PA_EINTERNAL, "persistent solve: a grid barrier wait timed out");
-      if (c == 0 || est < best_ms) {
-        best_ms = est;
+      ests[c] = est;
+    }
+    // estimates within 3% of the best count as equal (run-to-run noise is of
+    // that order); among them the larger workgroup, then the cheaper, wins
+    const float lo = *std::min_element(ests.begin(), ests.end());
+    for (size_t c = 0; c < cands.size(); ++c) {
+      if (ests[c] > lo * 1.03f) continue;
+      if (ests[best] > lo * 1.03f || cands[c].c.block > cands[best].c.block ||
+          (cands[c].c.block == cands[best].c.block && ests[c] < ests[best]))
         best = c;
-      }
     }
   }
   pl->classes.assign(1, cands[best]);
