@@ -227,7 +227,8 @@ pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
                          const pa_ga_params *params, pa_result *results, void *stream);
 
 /* Stepwise solve, for callers that decide themselves when to stop (Alg. 1
- * loops "while termination not met"); same kernels and bits as pa_solve.
+ * loops until an unspecified termination condition holds); same kernels and
+ * bits as pa_solve.
  *   pa_solve_begin  seeding, initial population and its fitness.  Async.
  *   pa_solve_next   ngens more generations (one cooperative launch for the
  *                   persistent form, else one fused launch each); at most
