@@ -226,6 +226,40 @@ __device__ __forceinline__ int pf_build(const GenInst &I, const GenTask &task, i
     sRes[4 * tid + 2] = cut * K;
   }
   __syncthreads();
+  const bool mutate = K >= 2 && I.ga.thr_mut != 0;
+  uint8_t *pout = pop_buf(I, out) + (size_t)task.s0 * LK;
+  if ((K & 3) == 0) {
+    // 2+3. one thread per row (c, j), rows whole aligned words: the crossover
+    // cuts between rows, so the row is copied whole from its parent (rows
+    // before the cut from the first, the others from the second), then its
+    // swaps, its write-out and its inverse entries
+    for (int r = tid; r < nc * L; r += block) {
+      const int c = r / L, j = r - c * L;
+      const int slot = task.s0 + c;
+      const int lp = ((slot - E) >> 1) - ps.pa0;
+      const bool second = ((slot - E) & 1) != 0;
+      const int32_t *res = sRes + 4 * lp;
+      const int fs = second ? res[1] : res[0], rs = second ? res[0] : res[1];
+      const int src = j * K < res[2] ? fs : rs;
+      const uint32_t *from = reinterpret_cast<const uint32_t *>(sCand + (4 * lp + src) * LK + j * K);
+      uint32_t *row = reinterpret_cast<uint32_t *>(sChild + r * K);
+      for (int w = 0; w < (K >> 2); ++w) row[w] = from[w];
+      if (mutate) apply_swaps(sChild + r * K, sCode + r * K, r * K, K);
+      gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)r * K));
+      uint8_t *dst = sInv + c * K * L + j;
+      for (int w = 0; w < (K >> 2); ++w) {
+        const uint32_t v = row[w];
+        gw[w] = v;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int t = (int)((v >> (8 * b)) & 0xFFu);
+          if (t < K) dst[t * L] = (uint8_t)(4 * w + b);
+        }
+      }
+    }
+    __syncthreads();
+    return nc;
+  }
   // 2. child c = first parent's genes [0, cut) + second's [cut, LK), one
   // power-of-two team of threads per child, 32-bit words when LK % 4 == 0
   {
@@ -263,13 +297,7 @@ __device__ __forceinline__ int pf_build(const GenInst &I, const GenTask &task, i
     }
   }
   __syncthreads();
-  // 3. the swaps; with K % 4 == 0 merged with the write-out and inverse rows
-  const bool mutate = K >= 2 && I.ga.thr_mut != 0;
-  uint8_t *pout = pop_buf(I, out) + (size_t)task.s0 * LK;
-  if ((K & 3) == 0) {
-    finish_rows(sChild, sCode, nc, L, K, mutate, pout, sInv, block);
-    return nc;
-  }
+  // 3. the swaps (K % 4 != 0)
   if (mutate) {
     for (int r = tid; r < nc * L; r += block) apply_swaps(sChild + r * K, sCode + r * K, r * K, K);
   }
