@@ -211,8 +211,11 @@ pa_status pa_ga_step(pa_instance *inst, const pa_ga_params *params, int32_t gen,
  * grid barriers, with the tasks' size autotuned on the instance itself;
  * otherwise the whole solve (one launch per generation) is captured into a
  * hipGraph.  Later calls with the same parameters replay the plan.  The
- * form and the shape never change a result bit.  PA_EINTERNAL if a grid
- * barrier wait times out (the results are then invalid).  Blocking. */
+ * form and the shape never change a result bit.  The environment variable
+ * PA_PERSIST_BLOCK=256 or 512, read when a plan is built, restricts the
+ * autotuner to that workgroup size (for reproducible profiles; unset, both
+ * are tried).  PA_EINTERNAL if a grid barrier wait times out (the results
+ * are then invalid).  Blocking. */
 pa_status pa_solve(pa_instance *inst, const pa_ga_params *params, pa_result *out, void *stream);
 
 /* Many independent solves in one: n instances of the same context, each with

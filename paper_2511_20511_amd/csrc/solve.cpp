@@ -11,6 +11,7 @@
 //    per-generation launch is paid.
 // Either way a solve ends with one copy of the results.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "pa_host.h"
@@ -337,11 +338,15 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
   const int cus = ctx->info.cus;
   // persistent form: one class with an unrolled variant whose full tasks
   // (block / K children each) all fit on the device at once, for 256- and
-  // 512-thread workgroups (512 only for tiled tables)
+  // 512-thread workgroups (512 only for tiled tables; PA_PERSIST_BLOCK=256 or
+  // 512 in the environment keeps only that size, for reproducible profiles)
   std::vector<std::pair<int, int>> pblocks;
+  const char *only_env = std::getenv("PA_PERSIST_BLOCK");
+  const int only = only_env ? std::atoi(only_env) : 0;
   if (groups.size() == 1 && exact_variant(groups[0].first.L, groups[0].first.TP)) {
     const ClassKey &key = groups[0].first;
     for (int block : {256, 512}) {
+      if (only != 0 && block != only) continue;
       if (block == 256 && tiled(key.L, key.TP, key.mode, 256)) continue;
       GenClass q;
       q.L = key.L;

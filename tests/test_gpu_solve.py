@@ -115,3 +115,39 @@ def test_stepwise_matches_solve():
         assert np.array_equal(a.trace.view(np.uint32), b.trace.view(np.uint32))
     with pytest.raises(pa.PaError):
         pa.pa_solve_next(inst, 1)
+
+
+def test_persistent_block_override_keeps_bits():
+    """PA_PERSIST_BLOCK restricts the persistent autotuner to one workgroup
+    size; the shape follows it and the results do not change."""
+    need_gpu()
+    import os
+    import paper_2511_20511_amd as pa
+    flush("persistent block override")
+    d = scenario.make_drop(19, 16, seed=4, instance_id=2)
+    prob = dict(beta=d.beta, user_xy=d.user_xy, bs_xy=d.bs_xy, T=196, M=256,
+                rho=scenario.snr_to_rho(10.0))
+    params = pa.GaParams(pop=256, gens=30, elite=8, seed=4, instance_id=2)
+    results, shapes = [], []
+    saved = os.environ.get("PA_PERSIST_BLOCK")
+    try:
+        for only in ("256", "512", None):
+            if only is None:
+                os.environ.pop("PA_PERSIST_BLOCK", None)
+            else:
+                os.environ["PA_PERSIST_BLOCK"] = only
+            inst = pa.pa_instance_create(ctx(), **prob)  # a new plan per setting
+            results.append(pa.pa_solve(inst, params))
+            shapes.append(pa.pa_solve_shape(ctx(), inst))
+            inst.close()
+    finally:
+        if saved is None:
+            os.environ.pop("PA_PERSIST_BLOCK", None)
+        else:
+            os.environ["PA_PERSIST_BLOCK"] = saved
+    assert all(s["persistent"] == 1 for s in shapes)
+    assert shapes[0]["block"] == 256 and shapes[1]["block"] == 512
+    for r in results[1:]:
+        assert np.array_equal(r.best, results[0].best)
+        assert np.array_equal(r.trace.view(np.uint32), results[0].trace.view(np.uint32))
+        assert np.float32(r.best_fit).view(np.uint32) == np.float32(results[0].best_fit).view(np.uint32)
