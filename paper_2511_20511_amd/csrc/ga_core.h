@@ -288,6 +288,8 @@ __device__ __forceinline__ void gather_range(const ByteRange &r, uint8_t *dst, i
   }
 }
 
+enum : int { kBuildSelect = 0, kBuildGather = 1, kBuildAll = 2 };
+
 // Builds the children of slots [s0, s0 + nc) in LDS (child c at child +
 // c*L*K) with the whole workgroup (nc <= block), in phases separated by
 // barriers:
@@ -297,7 +299,9 @@ __device__ __forceinline__ void gather_range(const ByteRange &r, uint8_t *dst, i
 //      decision and cut;
 //   2. all threads over all genes: copy from the parents (aligned words,
 //      several loads in flight);
-//   3. (swaps) one thread per (child, row): the swaps, in increasing k.
+//   3. one thread per (child, row): the swaps, in increasing k.
+// `upto` stops after phase 1 (kBuildSelect: parents and cut in sSel) or
+// phase 2 (kBuildGather: children without their swaps).
 // `child` and `codes` are 4-byte aligned LDS buffers of nc*L*K bytes; sSel:
 // 2 ints per child.  Ends with a barrier.
 __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__ pin,
@@ -305,7 +309,7 @@ __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__
                                                      int L, int K, const DevGa &ga, uint32_t gen,
                                                      int s0, int nc, uint8_t *child,
                                                      uint8_t *codes, int32_t *sSel, int block,
-                                                     bool swaps = true) {
+                                                     int upto = kBuildAll) {
   const int LK = L * K;
   const int tid = threadIdx.x;
   const bool sel = tid < nc;
@@ -340,6 +344,7 @@ __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__
     sSel[2 * tid + 1] = cut * K;
   }
   __syncthreads();
+  if (upto == kBuildSelect) return;
   // child c = first parent's genes [0, cut) + second's [cut, LK): two byte
   // ranges per child; a power-of-two team of threads per range moves it as
   // aligned words, several loads in flight per thread
@@ -361,7 +366,7 @@ __device__ __forceinline__ void build_children_block(const uint8_t *__restrict__
     }
   }
   __syncthreads();
-  if (mutate && swaps) {
+  if (mutate && upto == kBuildAll) {
     for (int r = tid; r < nc * L; r += block) {
       const int off = r * K;  // (c*L + j)*K
       apply_swaps(child + off, codes + off, off, K);

@@ -71,26 +71,52 @@ __device__ __forceinline__ GenTask load_task(const GenTask *tasks, int t) {
   return GenTask{p->inst, p->kind, p->s0, p->s1};
 }
 
-// Swaps, write-out and inverse rows of the nc children built in sChild
-// (codes in sCode, apart from sInv), K % 4 == 0 so that rows are whole aligned
-// words: one thread per row (c, j) applies its swaps, stores the row to pout
-// and scatters its inverse entries.  Ends with a barrier.
-__device__ __forceinline__ void finish_rows(uint8_t *sChild, const uint8_t *sCode, int nc, int L,
-                                            int K, bool mutate, uint8_t *pout, uint8_t *sInv,
-                                            int block) {
-  for (int r = threadIdx.x; r < nc * L; r += block) {
-    if (mutate) apply_swaps(sChild + r * K, sCode + r * K, r * K, K);
-    const int c = r / L, j = r - c * L;
-    const uint32_t *rw = reinterpret_cast<const uint32_t *>(sChild + r * K);
-    gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)r * K));
-    uint8_t *dst = sInv + c * K * L + j;
-    for (int w = 0; w < (K >> 2); ++w) {
-      const uint32_t v = rw[w];
-      gw[w] = v;
+// The children's rows straight from their parents (K % 4 == 0, K <= 32;
+// parents and cut in sSel as build_children_block leaves them), one thread
+// per row (c, j), the loads of two rows in flight per thread: the crossover
+// cuts between rows, so row j comes whole from the first parent when j < cut
+// and from the second otherwise; then the row's swaps, its write-out and its
+// inverse entries.  Ends with a barrier.
+__device__ __forceinline__ void rows_from_parents(const uint8_t *__restrict__ pin,
+                                                  const int32_t *sSel, const uint8_t *sCode,
+                                                  int nc, int L, int K, bool mutate,
+                                                  uint8_t *sChild, uint8_t *pout, uint8_t *sInv,
+                                                  int block) {
+  const int LK = L * K, nw = K >> 2, rows = nc * L;
+  for (int r = threadIdx.x; r < rows; r += 2 * block) {
+    uint32_t v[2][8];  // K <= 32
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int s = (int)((v >> (8 * b)) & 0xFFu);
-        if (s < K) dst[s * L] = (uint8_t)(4 * w + b);
+    for (int h = 0; h < 2; ++h) {
+      const int q = min(r + h * block, rows - 1);  // clamped: every load is in bounds
+      const int c = q / L, j = q - c * L;
+      const uint32_t pr = (uint32_t)sSel[2 * c];
+      const uint32_t par = j * K < sSel[2 * c + 1] ? (pr & 0xFFFFu) : (pr >> 16);
+      const gptr<const uint32_t> src =
+          gp(reinterpret_cast<const uint32_t *>(pin + (size_t)par * LK + j * K));
+#pragma unroll
+      for (int w = 0; w < 8; ++w) v[h][w] = w < nw ? src[w] : 0u;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = r + h * block;
+      if (q < rows) {
+        const int c = q / L, j = q - c * L;
+        uint32_t *row = reinterpret_cast<uint32_t *>(sChild + q * K);
+#pragma unroll
+        for (int w = 0; w < 8; ++w)
+          if (w < nw) row[w] = v[h][w];
+        if (mutate) apply_swaps(sChild + q * K, sCode + q * K, q * K, K);
+        gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)q * K));
+        uint8_t *dst = sInv + c * K * L + j;
+        for (int w = 0; w < nw; ++w) {
+          const uint32_t x = row[w];
+          gw[w] = x;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int t = (int)((x >> (8 * b)) & 0xFFu);
+            if (t < K) dst[t * L] = (uint8_t)(4 * w + b);
+          }
+        }
       }
     }
   }
@@ -101,7 +127,8 @@ __device__ __forceinline__ void finish_rows(uint8_t *sChild, const uint8_t *sCod
 // chromosomes to evaluate (0 for an elite task or a finished instance).
 // Leaves their inverse rows in sInv and ends with a barrier.  sCode: the
 // mutation codes (may alias sInv; apart from it, and with K % 4 == 0, the
-// swaps, write-out and inverse rows are one pass).
+// rows are taken from the parents, swapped, written out and inverted in one
+// pass).
 __device__ __forceinline__ int gen_prepare(const GenInst &I, const GenTask &task, int gen,
                                            uint8_t *sChild, uint8_t *sInv, uint8_t *sCode,
                                            int32_t *sIdx, int32_t *sSel, int block) {
@@ -115,12 +142,13 @@ __device__ __forceinline__ int gen_prepare(const GenInst &I, const GenTask &task
   }
   const int nc = task.s1 - task.s0;
   if (task.kind == kTaskChild) {
-    const bool merged = sCode != sInv && (K & 3) == 0;
+    const bool merged = sCode != sInv && (K & 3) == 0 && K <= 32;
     build_children_block(pop_buf(I, in), fit_buf(I, in), I.N, I.E, L, K, I.ga, (uint32_t)gen,
-                         task.s0, nc, sChild, sCode, sSel, block, !merged);
+                         task.s0, nc, sChild, sCode, sSel, block,
+                         merged ? kBuildSelect : kBuildAll);
     if (merged) {
-      finish_rows(sChild, sCode, nc, L, K, K >= 2 && I.ga.thr_mut != 0,
-                  pop_buf(I, out) + (size_t)task.s0 * LK, sInv, block);
+      rows_from_parents(pop_buf(I, in), sSel, sCode, nc, L, K, K >= 2 && I.ga.thr_mut != 0,
+                        sChild, pop_buf(I, out) + (size_t)task.s0 * LK, sInv, block);
       return nc;
     }
     store_bytes(pop_buf(I, out) + (size_t)task.s0 * LK, sChild, nc * LK);
