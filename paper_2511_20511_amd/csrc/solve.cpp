@@ -385,19 +385,61 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
     *out = guard.release();
     return PA_OK;
   }
-  // capture the whole solve
+  // capture the whole solve.  Size classes share no buffers, so with more
+  // than one class each class's chain of launches is captured on a stream
+  // of its own, forked after the seeding and joined before the best: the
+  // chains are independent branches of the graph and may run concurrently
+  // (the streams serve the capture only)
   hipStream_t cs = ctx->stream;
-  PTRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  hipError_t e = launch_kmeans_batch(pl->d_insts, pl->d_which, pl->nwhich, cs);
+  const size_t ncls = pl->classes.size();
+  std::vector<hipStream_t> side(ncls > 1 ? ncls : 0, nullptr);
+  std::vector<hipEvent_t> join(side.size(), nullptr);
+  hipEvent_t fork = nullptr;
+  auto release_side = [&]() {
+    for (hipStream_t st : side)
+      if (st) (void)hipStreamDestroy(st);
+    for (hipEvent_t ev : join)
+      if (ev) (void)hipEventDestroy(ev);
+    if (fork) (void)hipEventDestroy(fork);
+  };
+  hipError_t e = hipSuccess;
+  if (!side.empty()) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  for (size_t c = 0; c < side.size() && e == hipSuccess; ++c) {
+    e = hipStreamCreateWithFlags(&side[c], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&join[c], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    release_side();
+    return hip_error(e, "capture streams");
+  }
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    release_side();
+    return hip_error(e, "hipStreamBeginCapture");
+  }
+  e = launch_kmeans_batch(pl->d_insts, pl->d_which, pl->nwhich, cs);
   if (e == hipSuccess) e = launch_init_batch(pl->d_insts, n, pl->maxN, cs);
-  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess; ++c)
-    e = launch_gen(pl->d_insts, pl->classes[c].c, -1, ctx->info, cs);
-  for (int g = 0; g < pl->Gmax && e == hipSuccess; ++g)
-    for (size_t c = 0; c < pl->classes.size() && e == hipSuccess; ++c)
-      e = launch_gen(pl->d_insts, pl->classes[c].c, g, ctx->info, cs);
+  if (side.empty()) {
+    for (size_t c = 0; c < ncls && e == hipSuccess; ++c)
+      e = launch_gen(pl->d_insts, pl->classes[c].c, -1, ctx->info, cs);
+    for (int g = 0; g < pl->Gmax && e == hipSuccess; ++g)
+      for (size_t c = 0; c < ncls && e == hipSuccess; ++c)
+        e = launch_gen(pl->d_insts, pl->classes[c].c, g, ctx->info, cs);
+  } else {
+    if (e == hipSuccess) e = hipEventRecord(fork, cs);
+    for (size_t c = 0; c < ncls && e == hipSuccess; ++c) {
+      e = hipStreamWaitEvent(side[c], fork, 0);
+      if (e == hipSuccess) e = launch_gen(pl->d_insts, pl->classes[c].c, -1, ctx->info, side[c]);
+      for (int g = 0; g < pl->Gmax && e == hipSuccess; ++g)
+        e = launch_gen(pl->d_insts, pl->classes[c].c, g, ctx->info, side[c]);
+      if (e == hipSuccess) e = hipEventRecord(join[c], side[c]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(cs, join[c], 0);
+    }
+  }
   if (e == hipSuccess) e = launch_best_batch(pl->d_insts, n, -1, cs);
   hipGraph_t graph = nullptr;
   hipError_t e2 = hipStreamEndCapture(cs, &graph);
+  release_side();
   if (e != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     return hip_error(e, "capturing the solve");
