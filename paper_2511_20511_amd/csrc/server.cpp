@@ -31,6 +31,10 @@
 namespace pa {
 namespace {
 
+// side streams of a server: a tick's size classes run on them concurrently
+// (as many as the hardware queues a process gets by default)
+constexpr int kServerSideStreams = 4;
+
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -72,6 +76,10 @@ struct pa_server {
   pa_context *ctx = nullptr;
   pa_server_cfg cfg{};
   hipStream_t stream = nullptr;
+  // a tick's size classes run on these (forked from and joined to `stream`)
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr;
   std::vector<pa::Slot> slots;
   void *arena = nullptr;          // device memory of every slot
   void *pinned = nullptr;         // pinned staging (results, descriptors, tasks)
@@ -295,11 +303,21 @@ hipError_t tick(pa_server *S, std::vector<int> &finished) {
     e = hipMemcpyAsync(S->d_tasks, S->h_tasks, sizeof(GenTask) * nt, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(S->d_gens, S->h_gens, sizeof(int32_t) * ns, hipMemcpyHostToDevice, s);
-    for (auto &L : launches) {
+    // several size classes: each on a side stream, so that they overlap
+    const size_t nside = launches.size() > 1 ? std::min(launches.size(), S->side.size()) : 0;
+    if (nside > 0 && e == hipSuccess) e = hipEventRecord(S->fork, s);
+    for (size_t j = 0; j < nside && e == hipSuccess; ++j)
+      e = hipStreamWaitEvent(S->side[j], S->fork, 0);
+    for (size_t k = 0; k < launches.size(); ++k) {
       if (e != hipSuccess) break;
+      Launch &L = launches[k];
       L.c.tasks = S->d_tasks + L.off;
       L.c.gens = S->d_gens;
-      e = launch_gen(S->d_insts, L.c, 0, S->ctx->info, s);
+      e = launch_gen(S->d_insts, L.c, 0, S->ctx->info, nside > 0 ? S->side[k % nside] : s);
+    }
+    for (size_t j = 0; j < nside && e == hipSuccess; ++j) {
+      e = hipEventRecord(S->join[j], S->side[j]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s, S->join[j], 0);
     }
   }
   // advance; requests past their last generation finish
@@ -383,6 +401,14 @@ void free_server(pa_server *S) {
   if (S->d_which) (void)hipFree(S->d_which);
   if (S->d_tasks) (void)hipFree(S->d_tasks);
   if (S->pinned) (void)hipHostFree(S->pinned);
+  for (hipStream_t st : S->side)
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  for (hipEvent_t ev : S->join)
+    if (ev) (void)hipEventDestroy(ev);
+  if (S->fork) (void)hipEventDestroy(S->fork);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   for (auto &kv : S->reqs) delete kv.second;
   delete S;
@@ -443,6 +469,13 @@ pa_status pa_server_create(pa_context *ctx, const pa_server_cfg *cfg, pa_server 
                            up256(sizeof(int32_t) * 4 * ns) + sizeof(GenTask) * S->task_cap;
   if (e == hipSuccess) e = hipHostMalloc(&S->pinned, pin_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->fork, hipEventDisableTiming);
+  for (int j = 0; j < kServerSideStreams && e == hipSuccess; ++j) {
+    S->side.push_back(nullptr);
+    S->join.push_back(nullptr);
+    e = hipStreamCreateWithFlags(&S->side.back(), hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->join.back(), hipEventDisableTiming);
+  }
   if (e != hipSuccess) return hip_error(e, "server allocation");
   uint8_t *pin = static_cast<uint8_t *>(S->pinned);
   uint8_t *h_results = pin;
