@@ -1,12 +1,20 @@
 """Benchmark of the K-means-seeded elitist GA for pilot assignment on one MI355X.
 
-A step is one whole solve of the workload (K-means seeding, initial fitness,
-G generations of elitism / selection / crossover / mutation / fitness, best
-chromosome back on the host).  The default workload is a single instance with
-L = 19 hexagonal cells, K = tau = 16 users, M = 256, T = 196, a population of
-256, 500 generations and 8 elites.  `value` is chromosome fitness
-evaluations per second: (N + (N - E) * G) per solve over the timed solves,
-inputs resident in HBM.
+Headline workload: 64 independent instances of L = 37 hexagonal cells,
+K = tau = 32 users, M = 256, T = 196, each with its own user drop, a
+population of 1024, 200 generations and 8 elites, solved together by
+pa_solve_batch (one generation launch per generation, captured in a
+hipGraph).  A step is one whole batch (K-means seeding, initial fitness,
+200 generations of elitism / selection / crossover / mutation / fitness, the
+best chromosome of every instance back on the host); `value` is chromosome
+fitness evaluations per second, sum over instances of N + (N - E) * G per
+batch, over the timed batches, inputs resident in HBM.
+
+Also measured (extra keys): the peak LDS and VALU rates of the device
+(probe kernels), pa_fitness alone, the single L=19 / K=16 and L=7 / K=4
+solves, the 512-instance uneven batch with each instance's FP32-vs-FP64
+error, the Poisson-arrival server run and the plain one-launch-per-step path
+on the same arrivals, and the oracle on the host cores.
 
 Prints ONE JSON line on stdout (progress goes to stderr).
 """
@@ -15,6 +23,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -22,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-LDS_PEAK_GBS = 256 * 2.4e9 * 128 / 1e9  # 256 CUs x 2.4 GHz x 128 B/clk (ds_read_b32, 32 banks)
+LDS_NOMINAL_B_PER_CLK = 128  # 32 banks x 4 bytes per clock and CU (ds_read_b32)
 
 
 def log(msg):
@@ -42,246 +51,251 @@ def source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload, gens_per_launch):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter passes, or None
     when they were taken for another kernel, workload or source version."""
-    path = os.path.join(ROOT, "profiles", f"k_gen_persist_{workload}_traffic.json")
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f)
-    if (rec.get("kernel") != kernel or rec.get("generations_per_launch") != gens_per_launch
-            or rec.get("source_sha256") != source_sha256()):
-        return None
-    return float(rec["bytes_per_launch"])
+        recs = json.load(f)
+    for rec in recs:
+        if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                and rec.get("source_sha256") == source_sha256()):
+            return float(rec["bytes_per_launch"])
+    return None
 
 
 def evals_per_solve(N, E, G):
     return N + (N - E) * G
 
 
-def cpu_baseline(drop, w, best=None, best_fit=None, budget_s=12.0):
-    """The FP64 oracle, single-threaded, on whole solves of the same workload;
-    also the FP64 fitness of the GPU's best chromosome (its FP32 error)."""
-    import numpy as np
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+# ---- the oracle on the host (never touches the GPU) --------------------------
+
+def oracle_sample(L, K, N, G, E, seed, inst, T):
+    """Child-process mode: one oracle solve of instance `inst` of a workload with
+    G generations; prints {"evals": .., "seconds": ..}."""
+    import oracle
+    from paper_2511_20511_amd import scenario
+    oracle.build(force=False)
+    d = scenario.make_drop(L, K, seed=seed, instance_id=inst)
+    t0 = time.perf_counter()
+    oracle.solve(d.beta, d.user_xy, d.bs_xy, N, G, E, 0.8, 0.05, 0.5, 0.1, seed, inst, T=T)
+    el = time.perf_counter() - t0
+    print(json.dumps({"evals": evals_per_solve(N, E, G), "seconds": el}), flush=True)
+
+
+def cpu_baseline(w, sample_gens, procs):
+    """The FP64 oracle (single-threaded C, as written) on a bounded sample of
+    the headline workload: instance 0 with `sample_gens` generations on one
+    core, then `procs` independent processes, one instance each, at once.
+    Run before the GPU is touched; children are fresh interpreters."""
     import oracle
     oracle.build(force=False)
-    err = None
-    if best is not None:
-        f64 = float(oracle.fitness(drop.beta, best[None].astype(np.uint8), T=w["T"])[0])
-        err = abs(best_fit - f64) / abs(f64)
+    args = lambda i: [sys.executable, os.path.abspath(__file__), "--oracle-sample",
+                      ",".join(str(x) for x in (w["L"], w["K"], w["N"], sample_gens, w["E"],
+                                                w["seed"], i, w["T"]))]
+    one = json.loads(subprocess.run(args(0), capture_output=True, text=True, check=True).stdout)
+    single = one["evals"] / one["seconds"]
     t0 = time.perf_counter()
-    solves = 0
-    while True:
-        oracle.solve(drop.beta, drop.user_xy, drop.bs_xy, w["N"], w["gens"], w["E"], w["p_cross"],
-                     w["p_mut"], w["kmeans_frac"], w["p_init"], w["seed"], 0, T=w["T"])
-        solves += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or solves >= 3:
-            break
-    ev = solves * evals_per_solve(w["N"], w["E"], w["gens"])
-    return {"value": ev / el, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{solves} full oracle solve(s) of the same workload ({el:.1f} s, FP64, 1 thread)",
-            "best_fp32_rel_err_vs_fp64": err}
+    ps = [subprocess.Popen(args(i), stdout=subprocess.PIPE, text=True) for i in range(procs)]
+    outs = [json.loads(p.communicate()[0]) for p in ps]
+    wall = time.perf_counter() - t0
+    multi = sum(o["evals"] for o in outs) / wall
+    return {"value": single, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": (f"instance 0 of {w['instances']} x (L={w['L']} K={w['K']} N={w['N']} "
+                       f"E={w['E']}), K-means init + {sample_gens} generations, FP64, one "
+                       f"thread: {one['evals']} evaluations in {one['seconds']:.1f} s (the "
+                       f"workload's rate per evaluation; its full batch is "
+                       f"{w['instances'] * evals_per_solve(w['N'], w['E'], w['gens'])} "
+                       f"evaluations)"),
+            "cpu_model": cpu_model(), "nproc": usable_cores(),
+            "multicore": {"value": multi, "unit": "evals/s", "cores": procs,
+                          "sample": f"{procs} oracle processes at once, instances 0..{procs - 1}, "
+                                    f"same sample each, {wall:.1f} s wall"}}
 
 
-def workload_sizes(scenario, w, n):
-    """(L, K, N) of the n instances of a workload (uniform, or the uneven size mix)."""
-    if w.get("mix"):
-        return scenario.size_mix(n, w["seed"])
-    return [(w["L"], w["K"], w["N"])] * n
+# ---- GPU measurements ---------------------------------------------------------
 
-
-def run_batch(pa, scenario, torch, name):
-    """Many independent instances in one graph-captured batch: evals/s and solves/s."""
-    import numpy as np
-    w = dict(scenario.WORKLOADS[name])
-    G, E, n = w["gens"], w["E"], w["instances"]
-    sizes = workload_sizes(scenario, w, n)
-    ctx = pa.pa_context_create(0)
-    insts, params = [], []
+def make_batch(pa, scenario, ctx, w, sizes):
+    insts, params, drops = [], [], []
     for i, (L, K, N) in enumerate(sizes):
         d = scenario.make_drop(L, K, seed=w["seed"], instance_id=i)
         insts.append(pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=w["T"], M=w["M"],
                                            rho=scenario.snr_to_rho(w["snr_db"])))
-        params.append(pa.GaParams(pop=N, gens=G, elite=E, p_cross=w["p_cross"], p_mut=w["p_mut"],
-                                  kmeans_frac=w["kmeans_frac"], p_init=w["p_init"],
-                                  seed=w["seed"], instance_id=i))
-    t0 = time.perf_counter()
-    pa.pa_solve_batch(ctx, insts, params)  # builds and captures the plan
-    plan_s = time.perf_counter() - t0
-    reps = 3
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dev = []
-    for _ in range(reps):
-        res = pa.pa_solve_batch(ctx, insts, params)
-        dev.append(res[0].device_ms)
-    wall = (time.perf_counter() - t0) / reps
-    ev = sum(evals_per_solve(N, E, G) for (_, _, N) in sizes)
-    gathers = sum((N + (N - E) * G) * L * L * K for (L, K, N) in sizes)
-    out = {"workload": name, "instances": n, "gens": G,
-           "sizes": "size_mix: L {7,19,37}, K [4,32], N [128,1024]" if w.get("mix") else
-           f"L={sizes[0][0]} K={sizes[0][1]} N={sizes[0][2]}",
-           "ms_per_batch": wall * 1e3, "device_ms": float(np.median(dev)),
-           "plan_build_s": plan_s,
-           "evals_per_s": ev / wall, "solves_per_s": n / wall,
-           "lds_gbs": gathers * 4 / wall / 1e9,
-           "lds_frac_of_peak": gathers * 4 / wall / 1e9 / LDS_PEAK_GBS,
-           "solve_plan": pa.pa_solve_shape(ctx, None)}
-    log(f"batch {name}: {wall * 1e3:.1f} ms, {ev / wall:.3e} evals/s, {n / wall:.1f} solves/s, "
-        f"LDS {out['lds_gbs']:.0f} GB/s ({100 * out['lds_frac_of_peak']:.1f}%)")
-    for inst in insts:
-        inst.close()
-    return out
+        params.append(pa.GaParams(pop=N, gens=w["gens"], elite=w["E"], p_cross=w["p_cross"],
+                                  p_mut=w["p_mut"], kmeans_frac=w["kmeans_frac"],
+                                  p_init=w["p_init"], seed=w["seed"], instance_id=i))
+        drops.append(d)
+    return insts, params, drops
 
 
-def run_serve(pa, scenario, torch, name, seconds, plain_sample):
-    """Poisson arrivals of uneven solves through the continuous-batching server:
-    solves/s and p50/p99 latency (scheduled arrival -> result on the host),
-    beside a FIFO one-instance-at-a-time plain path on the same arrival trace."""
+def workload_sizes(scenario, w):
+    if w.get("mix"):
+        return scenario.size_mix(w["instances"], w["seed"])
+    return [(w["L"], w["K"], w["N"])] * w["instances"]
+
+
+def lds_peak(peaks, kind):
+    """Measured peak LDS bytes/s of the device for ds_read_b32 or ds_read_b128."""
+    return peaks[kind] * peaks["cus"] * peaks["clock_mhz"] * 1e6
+
+
+def kernel_roofline(pa, torch, ctx, insts, params, w, peaks, launches, workload):
+    """The batch's generation kernel alone: stepwise batch, HIP events around
+    `launches` generation launches on the stream they run on."""
+    stream = torch.cuda.current_stream()
+    pa.pa_solve_batch_begin(ctx, insts, params)
+    pa.pa_solve_batch_next(ctx, 5)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pa.pa_solve_batch_next(ctx, launches)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / launches
+    shape = pa.pa_solve_shape(ctx, None)
+    L, K = w["L"], w["K"]
+    TP = max(4, 1 << (K - 1).bit_length())
+    kname = f"k_gen_exact<{L},{TP},0,{shape['block']}>"
+    per_child = 4 * L * L * K  # algorithmic LDS bytes: one table word per (BS, cell, pilot)
+    children = w["instances"] * (w["N"] - w["E"])
+    bytes_launch = per_child * children
+    achieved = bytes_launch / (us * 1e-6) / 1e9
+    peak = lds_peak(peaks, "lds_b32") / 1e9
+    nominal = LDS_NOMINAL_B_PER_CLK * peaks["cus"] * peaks["clock_mhz"] * 1e6 / 1e9
+    return {"bound": "lds", "kernel": kname, "instruction": "ds_read_b32",
+            "achieved": achieved, "peak": peak, "unit": "GB/s", "frac": achieved / peak,
+            "traffic": measured_traffic(kname, workload),
+            "peak_source": "measured conflict-free ds_read_b32 rate (pa_device_peaks)",
+            "peak_nominal": nominal, "frac_of_nominal": achieved / nominal,
+            "avg_launch_us": us, "launches_timed": launches,
+            "algorithmic_bytes_per_launch": bytes_launch,
+            "per_unit": f"{per_child} B of LDS reads per child (4 L^2 K), "
+                        f"{children} children per launch"}
+
+
+def run_batch_extra(pa, scenario, torch, oracle_mod, name, reps=3):
+    """A batched workload timed end to end; with oracle_mod, the FP64 error of
+    every instance's best FP32 fitness."""
     import numpy as np
     w = dict(scenario.WORKLOADS[name])
-    G, E, P = w["gens"], w["E"], w["pool"]
-    sizes = scenario.size_mix(P, w["seed"])
-    drops = [scenario.make_drop(L, K, seed=w["seed"], instance_id=i)
-             for i, (L, K, N) in enumerate(sizes)]
-    rho = scenario.snr_to_rho(w["snr_db"])
-    arrivals = scenario.poisson_arrivals(w["rate"], seconds, w["seed"])
-    n = len(arrivals)
-
-    def params(i):
-        return pa.GaParams(pop=sizes[i % P][2], gens=G, elite=E, p_cross=w["p_cross"],
-                           p_mut=w["p_mut"], kmeans_frac=w["kmeans_frac"], p_init=w["p_init"],
-                           seed=w["seed"] + i, instance_id=i)
-
+    sizes = workload_sizes(scenario, w)
     ctx = pa.pa_context_create(0)
-    srv = pa.pa_server_create(ctx, max_L=37, max_K=32, max_pop=1024, max_gens=G)
-    # warm-up: one request of each size class
-    for i in range(min(P, 16)):
-        d = drops[i]
-        t = pa.pa_server_submit(srv, d.beta, d.user_xy, d.bs_xy, params(i), T=w["T"], M=w["M"],
-                                rho=rho)
-        pa.pa_server_poll(srv, t)
-    tickets = []
-    t_submit = np.zeros(n)
+    insts, params, drops = make_batch(pa, scenario, ctx, w, sizes)
     t0 = time.perf_counter()
-    for i in range(n):
-        while time.perf_counter() - t0 < arrivals[i]:
-            pass
-        d = drops[i % P]
-        t_submit[i] = time.perf_counter() - t0
-        tickets.append(pa.pa_server_submit(srv, d.beta, d.user_xy, d.bs_xy, params(i), T=w["T"],
-                                           M=w["M"], rho=rho))
-    lat = np.zeros(n)
-    for i, t in enumerate(tickets):
-        r = pa.pa_server_poll(srv, t)
-        lat[i] = (t_submit[i] - arrivals[i]) + r.device_ms * 1e-3
-    t_end = time.perf_counter() - t0
-    stats = pa.pa_server_stats(srv)
-    srv.close()
-    done = arrivals + lat
-    solves_per_s = n / (done.max() - arrivals[0])
-    # plain comparator: measured pa_solve_plain service time of each pool entry,
-    # FIFO over the same arrival trace
-    svc = np.zeros(P)
-    m = min(P, plain_sample)
-    for i in range(m):
-        d = drops[i]
-        inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=w["T"], M=w["M"], rho=rho)
-        pa.pa_solve_plain(inst, params(i))
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pa.pa_solve_plain(inst, params(i))
-        svc[i] = time.perf_counter() - t1
+    res = pa.pa_solve_batch(ctx, insts, params)
+    plan_s = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = pa.pa_solve_batch(ctx, insts, params)
+    wall = (time.perf_counter() - t0) / reps
+    G, E = w["gens"], w["E"]
+    ev = sum(evals_per_solve(N, E, G) for (_, _, N) in sizes)
+    out = {"workload": name, "instances": len(sizes), "gens": G,
+           "sizes": "size_mix: L {7,19,37}, K [4,32], N [128,1024]" if w.get("mix") else
+           f"L={sizes[0][0]} K={sizes[0][1]} N={sizes[0][2]}",
+           "ms_per_batch": wall * 1e3, "device_ms": res[0].device_ms, "plan_build_s": plan_s,
+           "evals_per_s": ev / wall, "solves_per_s": len(sizes) / wall,
+           "solve_plan": pa.pa_solve_shape(ctx, None)}
+    if oracle_mod is not None:
+        errs = []
+        for i, r in enumerate(res):
+            want = float(oracle_mod.fitness(drops[i].beta, r.best[None], T=w["T"])[0])
+            errs.append(abs(r.best_fit - want) / abs(want))
+        errs = np.array(errs)
+        out["best_fp32_vs_fp64_rel_err"] = {"max": float(errs.max()),
+                                            "p99": float(np.percentile(errs, 99)),
+                                            "median": float(np.median(errs)),
+                                            "instances": len(errs), "tolerance": 1e-5}
+    log(f"batch {name}: {wall * 1e3:.1f} ms, {ev / wall:.3e} evals/s, "
+        f"{len(sizes) / wall:.1f} solves/s")
+    for inst in insts:
         inst.close()
-    if m < P:
-        svc[m:] = np.resize(svc[:m], P - m)
-    fin = 0.0
-    plat = np.zeros(n)
-    for i in range(n):
-        fin = max(arrivals[i], fin) + svc[i % P]
-        plat[i] = fin - arrivals[i]
-    out = {"workload": name, "rate_per_s": w["rate"], "seconds": seconds, "requests": n,
-           "gens": G, "sizes": "size_mix: L {7,19,37}, K [4,32], N [128,1024]",
-           "solves_per_s": solves_per_s,
-           "p50_ms": float(np.percentile(lat, 50) * 1e3),
-           "p99_ms": float(np.percentile(lat, 99) * 1e3),
-           "slots": stats["slots"], "ticks": stats["ticks"],
-           "plain": {"kind": "FIFO pa_solve_plain, one instance at a time, same arrival trace "
-                             "(measured service time per pool entry)",
-                     "mean_service_ms": float(svc.mean() * 1e3),
-                     "solves_per_s": n / (fin - arrivals[0]) if n else 0.0,
-                     "p50_ms": float(np.percentile(plat, 50) * 1e3),
-                     "p99_ms": float(np.percentile(plat, 99) * 1e3)}}
-    log(f"serve {name}: {n} requests in {t_end:.1f} s, {solves_per_s:.0f} solves/s, "
-        f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms; plain FIFO: "
-        f"{out['plain']['solves_per_s']:.0f} solves/s, p99 {out['plain']['p99_ms']:.0f} ms")
+    ctx.close()
     return out
 
 
-def run_convergence(pa, scenario, torch, drops, gens):
-    """K-means-seeded (kmeans_frac = 0.5) vs randomly initialised (0) GA on the
-    same drops (L=19, K=16, N=256, E=8): best sum SE at the end, generations
-    until the trace reaches 99% of its final value, and the distribution of
-    the final best next to a random pilot assignment (one random chromosome)
-    and the K-means seed alone."""
+def run_single(pa, scenario, torch, name, steps, peaks):
+    """A single-instance solve (pa_solve): latency, and for the persistent form
+    its one launch timed with events (all generations)."""
     import numpy as np
-    L, K, N, E = 19, 16, 256, 8
+    w = dict(scenario.WORKLOADS[name])
+    L, K, N, G, E = w["L"], w["K"], w["N"], w["gens"], w["E"]
     ctx = pa.pa_context_create(0)
-    rho = scenario.snr_to_rho(10.0)
-    insts, params, rpa, seed_fit = [], [], [], []
-    pop = torch.empty((N, L, K), dtype=torch.uint8, device="cuda")
-    fit = torch.empty(N, dtype=torch.float32, device="cuda")
-    for i in range(drops):
-        d = scenario.make_drop(L, K, seed=7, instance_id=i)
-        inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=196, M=256, rho=rho)
-        for km in (0.5, 0.0):
-            insts.append(inst)
-            params.append(pa.GaParams(pop=N, gens=gens, elite=E, p_cross=0.8, p_mut=0.05,
-                                      kmeans_frac=km, p_init=0.1, seed=100 + i, instance_id=i))
-        # slot 0 of a random population: one random assignment; of a K-means
-        # population: the seed itself
-        for km, dst in ((0.0, rpa), (0.5, seed_fit)):
-            pa.pa_kmeans_init(inst, pa.GaParams(pop=N, kmeans_frac=km, seed=100 + i,
-                                                instance_id=i), pop)
-            pa.pa_fitness(inst, pop, 1, fit)
-            torch.cuda.synchronize()
-            dst.append(float(fit[0].item()))
-    # a batch may hold an instance once: run the two initialisations apart
-    res_km = pa.pa_solve_batch(ctx, insts[0::2], params[0::2])
-    res_rd = pa.pa_solve_batch(ctx, insts[1::2], params[1::2])
-
-    def to99(tr):
-        target = 0.99 * tr[-1]
-        return int(np.argmax(tr >= target))
-
-    out = {"workload": f"{drops} drops, L={L} K={K} N={N} G={gens} E={E}, M=256, T=196, SNR 10 dB"}
-    for name, res in (("kmeans_init", res_km), ("random_init", res_rd)):
-        best = np.array([r.best_fit for r in res])
-        g99 = np.array([to99(r.trace) for r in res])
-        out[name] = {"best_mean": float(best.mean()),
-                     "best_p10_p50_p90": [float(x) for x in np.percentile(best, [10, 50, 90])],
-                     "gens_to_99pct_mean": float(g99.mean()),
-                     "gens_to_99pct_median": float(np.median(g99)),
-                     "initial_best_mean": float(np.mean([r.trace[0] for r in res]))}
-    for name, vals in (("random_assignment", rpa), ("kmeans_seed_only", seed_fit)):
-        v = np.array(vals)
-        out[name] = {"mean": float(v.mean()),
-                     "p10_p50_p90": [float(x) for x in np.percentile(v, [10, 50, 90])]}
-    g_km = np.array([to99(r.trace) for r in res_km])
-    g_rd = np.array([to99(r.trace) for r in res_rd])
-    out["kmeans_reaches_99pct_first_frac"] = float(np.mean(g_km < g_rd))
-    out["reduction_of_mean_gens_to_99pct"] = float(1.0 - g_km.mean() / max(g_rd.mean(), 1e-9))
-    out["kmeans_final_better_frac"] = float(np.mean(
-        np.array([r.best_fit for r in res_km]) > np.array([r.best_fit for r in res_rd])))
+    d = scenario.make_drop(L, K, seed=w["seed"], instance_id=0)
+    inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=w["T"], M=w["M"],
+                                 rho=scenario.snr_to_rho(w["snr_db"]))
+    p = pa.GaParams(pop=N, gens=G, elite=E, p_cross=w["p_cross"], p_mut=w["p_mut"],
+                    kmeans_frac=w["kmeans_frac"], p_init=w["p_init"], seed=w["seed"],
+                    instance_id=0)
+    for _ in range(2):
+        pa.pa_solve(inst, p)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        r = pa.pa_solve(inst, p)
+        lat.append(time.perf_counter() - t0)
+    dev = r.device_ms
+    pa.pa_solve_plain(inst, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, steps // 2)):
+        pa.pa_solve_plain(inst, p)
+    plain_ms = (time.perf_counter() - t0) * 1e3 / max(1, steps // 2)
+    shape = pa.pa_solve_shape(None, inst)
+    out = {"workload": name, "L": L, "K": K, "pop": N, "gens": G, "elite": E,
+           "solve_ms_median": float(np.median(lat) * 1e3), "solve_ms_min": float(min(lat) * 1e3),
+           "solve_device_ms": dev, "evals_per_s": evals_per_solve(N, E, G) / np.median(lat),
+           "plain_solve_ms": plain_ms, "solve_plan": shape}
+    if shape["persistent"]:
+        stream = torch.cuda.current_stream()
+        TP = max(4, 1 << (K - 1).bit_length())
+        kname = f"k_gen_persist<{L},{TP},0,{shape['block']}>"
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        pa.pa_solve_begin(inst, p)
+        e0.record(stream)
+        pa.pa_solve_next(inst, G)
+        e1.record(stream)
+        e1.synchronize()
+        us = e0.elapsed_time(e1) * 1e3
+        b = (N - E) * G * 4 * L * L * K
+        out["generation_kernel"] = {"kernel": kname, "avg_launch_us": us,
+                                    "generations_per_launch": G,
+                                    "lds_gbs": b / (us * 1e-6) / 1e9,
+                                    "frac_of_measured_b32": b / (us * 1e-6) / lds_peak(peaks, "lds_b32")}
+    log(f"single {name}: {out['solve_ms_median']:.3f} ms per solve (device {dev:.3f} ms), "
+        f"plain {plain_ms:.3f} ms, plan {shape}")
+    inst.close()
+    ctx.close()
     return out
 
 
-def run_fitness(pa, scenario, torch, stream):
-    """pa_fitness alone on a resident population: evals/s and LDS roofline."""
+def run_fitness(pa, scenario, torch, peaks):
+    """pa_fitness alone on a resident population: evals/s and LDS roofline
+    against the measured peak of the instruction each layout issues."""
     out = []
-    for (L, K, n) in ((37, 32, 16384), (19, 16, 65536)):
+    stream = torch.cuda.current_stream()
+    for (L, K, n, instr) in ((37, 32, 16384, "lds_b32"), (19, 16, 65536, "lds_b128")):
         d = scenario.make_drop(L, K, seed=1, instance_id=0)
         ctx = pa.pa_context_create(0)
         inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=196)
@@ -299,13 +313,187 @@ def run_fitness(pa, scenario, torch, stream):
         e1.synchronize()
         ms = e0.elapsed_time(e1) / iters
         gbs = n * L * L * K * 4 / (ms * 1e-3) / 1e9
+        peak = lds_peak(peaks, instr) / 1e9
         TP = max(4, 1 << (K - 1).bit_length())
         out.append({"kernel": f"k_fitness_exact<{L},{TP},0,*>", "L": L, "K": K, "n": n,
+                    "instruction": "ds_read_b32" if instr == "lds_b32" else "ds_read_b128",
                     "avg_launch_us": ms * 1e3, "evals_per_s": n / (ms * 1e-3),
-                    "achieved_gbs": gbs, "frac": gbs / LDS_PEAK_GBS})
+                    "achieved_gbs": gbs, "peak_gbs": peak, "frac": gbs / peak})
         log(f"pa_fitness L={L} K={K} n={n}: {ms * 1e3:.1f} us, {n / (ms * 1e-3):.3e} evals/s, "
-            f"{gbs:.0f} GB/s LDS ({100 * gbs / LDS_PEAK_GBS:.1f}%)")
+            f"{gbs:.0f} GB/s LDS ({100 * gbs / peak:.1f}% of the measured {instr} peak)")
         inst.close()
+        ctx.close()
+    return out
+
+
+def run_serve(pa, scenario, torch, name, warm_s, seconds, plain_s):
+    """Poisson arrivals of uneven solves through the continuous-batching server
+    (warm-up, then the measured window): solves/s and p50/p99 latency
+    (scheduled arrival -> result on the host); then the plain path
+    (pa_solve_plain, one request at a time, FIFO) run on the first `plain_s`
+    seconds of the same arrival trace."""
+    import threading
+
+    import numpy as np
+    w = dict(scenario.WORKLOADS[name])
+    G, E, P = w["gens"], w["E"], w["pool"]
+    sizes = scenario.size_mix(P, w["seed"])
+    drops = [scenario.make_drop(L, K, seed=w["seed"], instance_id=i)
+             for i, (L, K, N) in enumerate(sizes)]
+    rho = scenario.snr_to_rho(w["snr_db"])
+    arrivals = scenario.poisson_arrivals(w["rate"], warm_s + seconds, w["seed"])
+    n = len(arrivals)
+
+    def params(i):
+        return pa.GaParams(pop=sizes[i % P][2], gens=G, elite=E, p_cross=w["p_cross"],
+                           p_mut=w["p_mut"], kmeans_frac=w["kmeans_frac"], p_init=w["p_init"],
+                           seed=w["seed"] + i, instance_id=i)
+
+    ctx = pa.pa_context_create(0)
+    srv = pa.pa_server_create(ctx, max_L=37, max_K=32, max_pop=1024, max_gens=G)
+    tickets = [None] * n
+    t_submit = np.zeros(n)
+    lat = np.zeros(n)
+    done_at = np.zeros(n)
+    t0 = time.perf_counter()
+
+    def poller():
+        for i in range(n):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            r = pa.pa_server_poll(srv, tickets[i])
+            lat[i] = (t_submit[i] - arrivals[i]) + r.device_ms * 1e-3
+            done_at[i] = arrivals[i] + lat[i]
+
+    th = threading.Thread(target=poller)
+    th.start()
+    for i in range(n):
+        while time.perf_counter() - t0 < arrivals[i]:
+            pass
+        d = drops[i % P]
+        t_submit[i] = time.perf_counter() - t0
+        tickets[i] = pa.pa_server_submit(srv, d.beta, d.user_xy, d.bs_xy, params(i), T=w["T"],
+                                         M=w["M"], rho=rho)
+    th.join()
+    stats = pa.pa_server_stats(srv)
+    srv.close()
+    m = arrivals >= warm_s
+    lm = lat[m]
+    span = done_at[m].max() - arrivals[m][0]
+    out = {"workload": name, "rate_per_s": w["rate"], "warmup_s": warm_s, "seconds": seconds,
+           "requests_measured": int(m.sum()), "gens": G,
+           "sizes": "size_mix: L {7,19,37}, K [4,32], N [128,1024]",
+           "solves_per_s": float(m.sum() / span),
+           "p50_ms": float(np.percentile(lm, 50) * 1e3),
+           "p99_ms": float(np.percentile(lm, 99) * 1e3),
+           "slots": stats["slots"], "ticks": stats["ticks"]}
+    log(f"serve {name}: {int(m.sum())} requests measured, {out['solves_per_s']:.0f} solves/s, "
+        f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms")
+    # plain path on the same trace (prefix), measured: one request at a time;
+    # each pool entry's instance is created (uploaded) once, before the run
+    insts = {i: pa.pa_instance_create(ctx, drops[i].beta, drops[i].user_xy, drops[i].bs_xy,
+                                      T=w["T"], M=w["M"], rho=rho) for i in range(P)}
+    np_ = int(np.searchsorted(arrivals, plain_s))
+    plat = np.zeros(np_)
+    pdone = np.zeros(np_)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(np_):
+        now = time.perf_counter() - t0
+        if now < arrivals[i]:
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+        pa.pa_solve_plain(insts[i % P], params(i))
+        pdone[i] = time.perf_counter() - t0
+        plat[i] = pdone[i] - arrivals[i]
+    for inst in insts.values():
+        inst.close()
+    ctx.close()
+    out["plain"] = {"kind": "pa_solve_plain one request at a time (FIFO, one stream, no graph, "
+                            "no batching), run on the first "
+                            f"{plain_s:.0f} s of the same arrival trace",
+                    "requests": np_,
+                    "solves_per_s": float(np_ / (pdone[-1] - arrivals[0])) if np_ else 0.0,
+                    "p50_ms": float(np.percentile(plat, 50) * 1e3) if np_ else 0.0,
+                    "p99_ms": float(np.percentile(plat, 99) * 1e3) if np_ else 0.0}
+    log(f"plain on the first {plain_s:.0f} s: {np_} requests, "
+        f"{out['plain']['solves_per_s']:.0f} solves/s, p99 {out['plain']['p99_ms']:.0f} ms")
+    return out
+
+
+def run_convergence(pa, scenario, torch, drops, gens, keep=None):
+    """K-means-seeded (kmeans_frac = 0.5) vs randomly initialised (0) GA on the
+    same drops (L=19, K=16, N=256, E=8): best sum SE at the end, generations
+    and wall time until the trace reaches 99% of its final value, the whole
+    distribution of the final best, and a random pilot assignment (one random
+    chromosome) and the K-means seed alone."""
+    import numpy as np
+    L, K, N, E = 19, 16, 256, 8
+    ctx = pa.pa_context_create(0)
+    rho = scenario.snr_to_rho(10.0)
+    insts, params, rpa, seed_fit = [], [], [], []
+    pop = torch.empty((N, L, K), dtype=torch.uint8, device="cuda")
+    fit = torch.empty(N, dtype=torch.float32, device="cuda")
+    for i in range(drops):
+        d = scenario.make_drop(L, K, seed=7, instance_id=i)
+        inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=196, M=256, rho=rho)
+        for km in (0.5, 0.0):
+            insts.append(inst)
+            params.append(pa.GaParams(pop=N, gens=gens, elite=E, p_cross=0.8, p_mut=0.05,
+                                      kmeans_frac=km, p_init=0.1, seed=100 + i, instance_id=i))
+        for km, dst in ((0.0, rpa), (0.5, seed_fit)):
+            pa.pa_kmeans_init(inst, pa.GaParams(pop=N, kmeans_frac=km, seed=100 + i,
+                                                instance_id=i), pop)
+            pa.pa_fitness(inst, pop, 1, fit)
+            torch.cuda.synchronize()
+            dst.append(float(fit[0].item()))
+    # wall time per generation of one solve (the single-instance persistent
+    # form, stepwise): time to 99% = init + generations x per-generation time
+    one = insts[0]
+    pa.pa_solve(one, params[0])
+    stream = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record(stream)
+    pa.pa_solve_begin(one, params[0])
+    e1.record(stream)
+    pa.pa_solve_next(one, gens)
+    e2.record(stream)
+    e2.synchronize()
+    init_ms = e0.elapsed_time(e1)
+    gen_ms = e1.elapsed_time(e2) / gens
+    res_km = pa.pa_solve_batch(ctx, insts[0::2], params[0::2])
+    res_rd = pa.pa_solve_batch(ctx, insts[1::2], params[1::2])
+
+    def to99(tr):
+        return int(np.argmax(tr >= 0.99 * tr[-1]))
+
+    out = {"workload": f"{drops} drops, L={L} K={K} N={N} G={gens} E={E}, M=256, T=196, SNR 10 dB",
+           "solve_init_ms": init_ms, "solve_ms_per_generation": gen_ms}
+    for name, res in (("kmeans_init", res_km), ("random_init", res_rd)):
+        best = np.array([r.best_fit for r in res])
+        g99 = np.array([to99(r.trace) for r in res])
+        out[name] = {"best_mean": float(best.mean()),
+                     "best_quantiles_0_5_10_25_50_75_90_95_100": [
+                         float(x) for x in np.percentile(best, [0, 5, 10, 25, 50, 75, 90, 95, 100])],
+                     "gens_to_99pct_mean": float(g99.mean()),
+                     "gens_to_99pct_median": float(np.median(g99)),
+                     "ms_to_99pct_mean": float(init_ms + g99.mean() * gen_ms),
+                     "initial_best_mean": float(np.mean([r.trace[0] for r in res])),
+                     "best": [float(x) for x in best]}
+    for name, vals in (("random_assignment", rpa), ("kmeans_seed_only", seed_fit)):
+        v = np.array(vals)
+        out[name] = {"mean": float(v.mean()),
+                     "quantiles_0_5_10_25_50_75_90_95_100": [
+                         float(x) for x in np.percentile(v, [0, 5, 10, 25, 50, 75, 90, 95, 100])],
+                     "values": [float(x) for x in v]}
+    g_km = np.array([to99(r.trace) for r in res_km])
+    g_rd = np.array([to99(r.trace) for r in res_rd])
+    out["kmeans_reaches_99pct_first_frac"] = float(np.mean(g_km < g_rd))
+    out["reduction_of_mean_gens_to_99pct"] = float(1.0 - g_km.mean() / max(g_rd.mean(), 1e-9))
+    out["kmeans_final_better_frac"] = float(np.mean(
+        np.array([r.best_fit for r in res_km]) > np.array([r.best_fit for r in res_rd])))
+    if keep is not None:  # the solves themselves, for checks against the oracle
+        keep.update(kmeans_init=res_km, random_init=res_rd, params=params)
     return out
 
 
@@ -314,29 +502,48 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="single_L19_K16")
+    ap.add_argument("--workload", default="batch64_L37_K32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-iters", type=int, default=200)
-    ap.add_argument("--batch", default="batch64_L37_K32,batch512_mix",
+    ap.add_argument("--cpu-sample-gens", type=int, default=100)
+    ap.add_argument("--kernel-launches", type=int, default=100)
+    ap.add_argument("--batch", default="batch512_mix",
                     help="also time these batched workloads (comma-separated, '' to skip)")
+    ap.add_argument("--single", default="single_L19_K16,single_L7_K4",
+                    help="also time these single-instance solves ('' to skip)")
     ap.add_argument("--serve", default="serve_mix_2000rps",
                     help="also run this served workload ('' to skip)")
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
-    ap.add_argument("--plain-sample", type=int, default=64,
-                    help="pool entries whose plain service time is measured for the comparator")
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--plain-seconds", type=float, default=3.0,
+                    help="the plain path runs on this prefix of the arrival trace")
     ap.add_argument("--no-fitness", action="store_true", help="skip the pa_fitness roofline lines")
     ap.add_argument("--experiment", default="", choices=["", "convergence"],
                     help="only run this experiment and print its JSON line")
     ap.add_argument("--drops", type=int, default=256)
     ap.add_argument("--exp-gens", type=int, default=200)
+    ap.add_argument("--oracle-sample", default="", help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (5 times) and exit: the "
                          "reference kernel that scales HBM byte counters")
     args = ap.parse_args()
+    if args.oracle_sample:
+        v = [int(x) for x in args.oracle_sample.split(",")]
+        oracle_sample(*v)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(each instance runs on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    from paper_2511_20511_amd import scenario
+    w = dict(scenario.WORKLOADS[args.workload])
+    cpu = None
+    if not args.no_cpu_baseline:
+        procs = min(usable_cores(), 16)
+        log(f"cpu baseline: oracle sample on 1 core, then {procs} processes ...")
+        cpu = cpu_baseline(w, args.cpu_sample_gens, procs)
+        log(f"oracle: {cpu['value']:.0f} evals/s on one core, "
+            f"{cpu['multicore']['value']:.0f} evals/s on {procs}")
 
     import numpy as np
     import torch
@@ -352,7 +559,6 @@ def main():
         return
 
     import paper_2511_20511_amd as pa
-    from paper_2511_20511_amd import scenario
 
     if args.experiment == "convergence":
         print(json.dumps({"experiment": "convergence",
@@ -360,106 +566,76 @@ def main():
               flush=True)
         return
 
-    w = dict(scenario.WORKLOADS[args.workload])
-    L, K, N, G, E = w["L"], w["K"], w["N"], w["gens"], w["E"]
-    rho = scenario.snr_to_rho(w["snr_db"])
-    drop = scenario.make_drop(L, K, seed=w["seed"], instance_id=0)
     ctx = pa.pa_context_create(0)
-    inst = pa.pa_instance_create(ctx, drop.beta, drop.user_xy, drop.bs_xy, T=w["T"], M=w["M"],
-                                 rho=rho)
-    params = pa.GaParams(pop=N, gens=G, elite=E, p_cross=w["p_cross"], p_mut=w["p_mut"],
-                         kmeans_frac=w["kmeans_frac"], p_init=w["p_init"], seed=w["seed"],
-                         instance_id=0)
-    stream = torch.cuda.current_stream()
-
-    log(f"workload {args.workload}: L={L} K={K} N={N} G={G} E={E}")
+    peaks = pa.pa_device_peaks(ctx)
+    log(f"device peaks: {peaks}")
+    sizes = workload_sizes(scenario, w)
+    insts, params, drops = make_batch(pa, scenario, ctx, w, sizes)
+    log(f"workload {args.workload}: {len(sizes)} instances, sizes {sizes[0]}, G={w['gens']}")
+    t0 = time.perf_counter()
+    pa.pa_solve_batch(ctx, insts, params)  # builds and captures the plan
+    plan_s = time.perf_counter() - t0
     for _ in range(args.warmup):
-        pa.pa_solve(inst, params)
+        pa.pa_solve_batch(ctx, insts, params)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     dev_ms = []
     res = None
     for _ in range(args.steps):
-        res = pa.pa_solve(inst, params)
-        dev_ms.append(res.device_ms)
+        res = pa.pa_solve_batch(ctx, insts, params)
+        dev_ms.append(res[0].device_ms)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = wall * 1e3 / args.steps
-    ev = evals_per_solve(N, E, G)
+    ev = sum(evals_per_solve(N, w["E"], w["gens"]) for (_, _, N) in sizes)
     value = ev * args.steps / wall
-    log(f"solve: {ms_per_step:.3f} ms/solve wall, device {np.median(dev_ms):.3f} ms, "
-        f"best {res.best_fit:.4f}")
+    shape = pa.pa_solve_shape(ctx, None)
+    log(f"batch: {ms_per_step:.2f} ms per batch, device {np.median(dev_ms):.2f} ms, "
+        f"{value:.3e} evals/s, plan {shape}")
+    roofline = kernel_roofline(pa, torch, ctx, insts, params, w, peaks, args.kernel_launches,
+                               args.workload)
+    log(f"generation kernel {roofline['kernel']}: {roofline['avg_launch_us']:.1f} us/launch, "
+        f"{roofline['achieved']:.0f} GB/s LDS = {100 * roofline['frac']:.1f}% of the measured "
+        f"ds_read_b32 peak ({100 * roofline['frac_of_nominal']:.1f}% of nominal)")
+    # the FP32 best of every instance against the FP64 definition
+    import oracle
+    oracle.build(force=False)
+    want = [float(oracle.fitness(d.beta, r.best[None], T=w["T"])[0]) for r, d in zip(res, drops)]
+    errs = [abs(r.best_fit - f) / abs(f) for r, f in zip(res, want)]
+    for inst in insts:
+        inst.close()
 
-    # plain comparator: one launch per step, no fusion, no graph
-    pa.pa_solve_plain(inst, params)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plain_steps = max(1, args.steps // 2)
-    for _ in range(plain_steps):
-        pa.pa_solve_plain(inst, params)
-    torch.cuda.synchronize()
-    plain_ms = (time.perf_counter() - t1) * 1e3 / plain_steps
-    log(f"plain solve (one launch per step): {plain_ms:.3f} ms/solve")
-
-    # dominant kernel: the generation kernel, timed with events on the stream
-    # it is launched on.  Persistent form: one launch runs all G generations
-    # (pa_solve_next(G)); graph form: one launch per generation.
-    shape = pa.pa_solve_shape(None, inst)
-    log(f"solve plan: {shape}")
-    TP = max(4, 1 << (K - 1).bit_length())
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    pa.pa_solve_begin(inst, params)
-    if shape["persistent"]:
-        gens_per_launch, launches = G, 1
-        kname = f"k_gen_persist<{L},{TP},0,{shape['block']}>"
-    else:
-        pa.pa_solve_next(inst, 10)
-        gens_per_launch, launches = 1, min(args.kernel_iters, G - 10)
-        kname = f"k_gen_exact<{L},{TP},0,{shape['block']}>"
-    e0.record(stream)
-    pa.pa_solve_next(inst, gens_per_launch * launches)
-    e1.record(stream)
-    e1.synchronize()
-    k_ms = e0.elapsed_time(e1) / launches
-    # algorithmic LDS bytes of one launch: every child reads one 4-byte table
-    # word per (BS, cell, pilot)
-    lds_bytes = (N - E) * gens_per_launch * L * L * K * 4
-    achieved = lds_bytes / (k_ms * 1e-3) / 1e9
-    roofline = {"bound": "lds", "kernel": kname,
-                "achieved": achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / LDS_PEAK_GBS,
-                "traffic": measured_traffic(kname, args.workload, gens_per_launch),
-                "avg_launch_us": k_ms * 1e3, "bytes_per_launch": lds_bytes,
-                "generations_per_launch": gens_per_launch}
-    log(f"generation kernel {kname}: {k_ms * 1e3:.2f} us/launch ({gens_per_launch} generation(s)), "
-        f"{achieved:.0f} GB/s LDS ({100 * achieved / LDS_PEAK_GBS:.1f}% of {LDS_PEAK_GBS:.0f})")
-
-    extra = {}
-    if not args.no_fitness:
-        extra["fitness"] = run_fitness(pa, scenario, torch, stream)
-    if args.batch:
-        extra["batch"] = [run_batch(pa, scenario, torch, b) for b in args.batch.split(",") if b]
-    if args.serve:
-        extra["serve"] = run_serve(pa, scenario, torch, args.serve, args.serve_seconds,
-                                   args.plain_sample)
     line = {
         "metric": "chromosome fitness evals/s", "value": value, "unit": "evals/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "L": L, "K": K, "tau": K, "M": w["M"], "T": w["T"],
-                   "pop": N, "gens": G, "elite": E, "instances": 1},
-        "solves_per_s": args.steps / wall,
-        "solve_device_ms": float(np.median(dev_ms)),
-        "plain_solve_ms": plain_ms,
+        "config": {"workload": args.workload, "instances": len(sizes), "L": w.get("L"),
+                   "K": w.get("K"), "tau": w.get("K"), "M": w["M"], "T": w["T"],
+                   "pop": w.get("N"), "gens": w["gens"], "elite": w["E"],
+                   "evals_per_step": ev},
+        "solves_per_s": len(sizes) * args.steps / wall,
+        "batch_device_ms": float(np.median(dev_ms)),
+        "plan_build_s": plan_s,
         "solve_plan": shape,
+        "best_fp32_vs_fp64_rel_err_max": float(max(errs)),
         "roofline": roofline,
+        "device_peaks": peaks,
     }
-    line.update(extra)
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        line["cpu_baseline"] = cpu_baseline(drop, w, res.best, res.best_fit)
-        log(f"oracle: {line['cpu_baseline']['value']:.0f} evals/s")
+    if args.single:
+        line["single"] = [run_single(pa, scenario, torch, s, args.steps, peaks)
+                          for s in args.single.split(",") if s]
+    if not args.no_fitness:
+        line["fitness"] = run_fitness(pa, scenario, torch, peaks)
+    if args.batch:
+        line["batch"] = [run_batch_extra(pa, scenario, torch, oracle, b)
+                         for b in args.batch.split(",") if b]
+    if args.serve:
+        line["serve"] = run_serve(pa, scenario, torch, args.serve, args.serve_warmup,
+                                  args.serve_seconds, args.plain_seconds)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+    ctx.close()
     print(json.dumps(line), flush=True)
 
 

@@ -243,6 +243,31 @@ pa_status pa_solve_begin(pa_instance *inst, const pa_ga_params *params, void *st
 pa_status pa_solve_next(pa_instance *inst, int32_t ngens, void *stream);
 pa_status pa_solve_state(pa_instance *inst, pa_result *out, int32_t *gens_done, void *stream);
 
+/* Stepwise form of pa_solve_batch (same plan, kernels and bits): begin
+ * seeds every instance and evaluates its initial population, next runs
+ * ngens more generations of every instance (one fused launch per class and
+ * generation, or one persistent launch), state copies the best chromosome,
+ * fitness and trace of each instance's current population into results[i]
+ * (results[i].best and .trace as in pa_solve_batch) and *gens_done.  An
+ * instance whose own gens is below the generations run stays at its last
+ * generation.  begin and next: async; state: blocking. */
+pa_status pa_solve_batch_begin(pa_context *ctx, int32_t n, pa_instance *const *insts,
+                               const pa_ga_params *params, void *stream);
+pa_status pa_solve_batch_next(pa_context *ctx, int32_t ngens, void *stream);
+pa_status pa_solve_batch_state(pa_context *ctx, pa_result *results, int32_t *gens_done,
+                               void *stream);
+
+/* The current population of one instance of a solve plan (Alg. 1's
+ * population P after the generations run so far): inst != NULL selects the
+ * plan of pa_solve / pa_solve_begin on inst (index 0), inst == NULL the
+ * context's batch plan (index = the instance's position in the batch call).
+ * pop: HOST [N][L][K] bytes, fit: HOST [N] FP32 (either may be NULL); *gen
+ * (may be NULL) = the generation that population belongs to.  PA_EINVAL
+ * when there is no plan or it has not run, or index is out of range.
+ * Blocking (orders after the work enqueued on `stream`). */
+pa_status pa_solve_population(pa_context *ctx, pa_instance *inst, int32_t index, uint8_t *pop,
+                              float *fit, int32_t *gen, void *stream);
+
 /* The same solve as one launch per step (seeding, fitness, then per
  * generation a pa_ga_step launch and a pa_fitness launch), no fusion and no
  * graph: the plain comparator.  Bit-identical results to pa_solve. */
@@ -306,10 +331,14 @@ typedef struct pa_server_cfg {
   double hbm_budget;
 } pa_server_cfg;
 
+/* Server counters: slots, resident and queued requests, requests submitted
+ * and completed, ticks run, bytes of one slot, and the most generation tasks
+ * one workgroup ran in a single launch so far. */
 typedef struct pa_server_counters {
   int32_t slots, resident, queued;
   uint64_t submitted, completed, ticks;
   double slot_bytes;
+  int32_t max_tasks_per_workgroup;
 } pa_server_counters;
 
 /* Creates a server on the context's device (cfg may be NULL for defaults).
@@ -341,6 +370,21 @@ void pa_server_destroy(pa_server *srv);
  * labels [L*K], iterations.  Blocking. */
 pa_status pa_instance_kmeans_state(pa_instance *inst, uint8_t *seed, int32_t *centroids,
                                    int32_t *labels, int32_t *iters);
+
+/* Peak rates of the context's device, measured by probe kernels (the
+ * denominators of the LDS-gather rooflines; not part of the method):
+ *   lds_b32    bytes per clock per CU of conflict-free ds_read_b32 gathers
+ *              (each half-wave reads 32 words in 32 distinct banks)
+ *   lds_b128   bytes per clock per CU of ds_read_b128 (consecutive words)
+ *   valu_f32   wave64 v_add_f32 instructions per clock per CU
+ *   clock_mhz  the shader clock during the probes (cycles over event time)
+ *   cus        compute units.
+ * Blocking; allocates and frees a few KiB of device memory. */
+typedef struct pa_peak_rates {
+  double lds_b32, lds_b128, valu_f32, clock_mhz;
+  int32_t cus;
+} pa_peak_rates;
+pa_status pa_device_peaks(pa_context *ctx, pa_peak_rates *out);
 
 const char *pa_status_string(pa_status s);
 const char *pa_last_error(void);

@@ -12,8 +12,10 @@ valid inside the library.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -23,7 +25,8 @@ __all__ = [
     "pa_context_create", "pa_context_destroy", "pa_instance_create", "pa_instance_destroy",
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
-    "pa_solve_shape", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
+    "pa_solve_shape", "pa_solve_batch_begin", "pa_solve_batch_next", "pa_solve_batch_state",
+    "pa_solve_population", "pa_device_peaks", "release_all", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
     "pa_server_destroy", "Server", "pa_exhaustive",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
@@ -91,11 +94,17 @@ class _ServerCfg(ctypes.Structure):
                 ("hbm_budget", ctypes.c_double)]
 
 
+class _PeakRates(ctypes.Structure):
+    _fields_ = [("lds_b32", ctypes.c_double), ("lds_b128", ctypes.c_double),
+                ("valu_f32", ctypes.c_double), ("clock_mhz", ctypes.c_double),
+                ("cus", ctypes.c_int32)]
+
+
 class _ServerCounters(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("resident", ctypes.c_int32),
                 ("queued", ctypes.c_int32), ("submitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("ticks", ctypes.c_uint64),
-                ("slot_bytes", ctypes.c_double)]
+                ("slot_bytes", ctypes.c_double), ("max_tasks_per_workgroup", ctypes.c_int32)]
 
 
 @dataclass
@@ -108,6 +117,22 @@ class Result:
 
 
 _lib = None
+# every live handle, so that release_all() can free them in order at exit
+_live = {"servers": weakref.WeakSet(), "instances": weakref.WeakSet(),
+         "contexts": weakref.WeakSet()}
+
+
+def release_all():
+    """Destroys every live server, instance and context (in that order), so no
+    plan, graph, stream, event or device buffer of the library outlives the
+    interpreter's orderly shutdown.  Registered with atexit when the library
+    is loaded; callable at any time (the handles become closed)."""
+    for kind in ("servers", "instances", "contexts"):
+        for obj in list(_live[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
 
 
 def lib():
@@ -139,6 +164,10 @@ def lib():
         "pa_solve_state": (st, [vp, ctypes.POINTER(_Result), ctypes.POINTER(i32), vp]),
         "pa_solve_shape": (st, [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                 ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "pa_solve_batch_begin": (st, [vp, i32, ctypes.POINTER(vp), ctypes.POINTER(_Params), vp]),
+        "pa_solve_batch_next": (st, [vp, i32, vp]),
+        "pa_solve_batch_state": (st, [vp, ctypes.POINTER(_Result), ctypes.POINTER(i32), vp]),
+        "pa_solve_population": (st, [vp, vp, i32, vp, vp, ctypes.POINTER(i32), vp]),
         "pa_server_create": (st, [vp, ctypes.POINTER(_ServerCfg), ctypes.POINTER(vp)]),
         "pa_server_submit": (st, [vp, ctypes.POINTER(_Problem), ctypes.POINTER(_Params),
                                   ctypes.POINTER(ctypes.c_uint64)]),
@@ -147,6 +176,7 @@ def lib():
         "pa_server_destroy": (None, [vp]),
         "pa_exhaustive": (st, [vp, ctypes.c_int64, ctypes.POINTER(_Result),
                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp]),
+        "pa_device_peaks": (st, [vp, ctypes.POINTER(_PeakRates)]),
         "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
         "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
         "pa_status_string": (ctypes.c_char_p, [st]),
@@ -158,6 +188,7 @@ def lib():
         f.restype = res
         f.argtypes = args
     _lib = L
+    atexit.register(release_all)
     return L
 
 
@@ -231,6 +262,7 @@ class Context:
     def __init__(self, device: int = 0):
         self.h = ctypes.c_void_p()
         _check(lib().pa_context_create(device, ctypes.byref(self.h)))
+        _live["contexts"].add(self)
 
     def close(self):
         if self.h:
@@ -252,6 +284,7 @@ class Instance:
         self.L, self.K = host.L, host.K
         self.h = ctypes.c_void_p()
         _check(lib().pa_instance_create(ctx.h, ctypes.byref(host.c), ctypes.byref(self.h)))
+        _live["instances"].add(self)
 
     def close(self):
         if self.h:
@@ -344,6 +377,52 @@ def pa_solve_batch(ctx: Context, insts, params, stream=None) -> list:
                    float(cr[i].device_ms)) for i in range(n)]
 
 
+def pa_solve_batch_begin(ctx: Context, insts, params, stream=None):
+    """Stepwise batch: seeding and initial fitness of every instance."""
+    n = len(insts)
+    if len(params) != n:
+        raise ValueError("one GaParams per instance")
+    handles = (ctypes.c_void_p * max(n, 1))(*[i.h for i in insts])
+    cp = (_Params * max(n, 1))(*[p.to_c() for p in params])
+    _check(lib().pa_solve_batch_begin(ctx.h, n, handles, cp, _stream(stream)))
+    ctx._batch = ([(i.L, i.K) for i in insts], [p.gens for p in params],
+                  [p.pop for p in params])
+
+
+def pa_solve_batch_next(ctx: Context, ngens: int = 1, stream=None):
+    _check(lib().pa_solve_batch_next(ctx.h, int(ngens), _stream(stream)))
+
+
+def pa_solve_batch_state(ctx: Context, stream=None):
+    """(list of Result, generations done) of a stepwise batch."""
+    shapes, gens, _ = ctx._batch
+    n = len(shapes)
+    bests = [np.zeros(s, dtype=np.uint8) for s in shapes]
+    traces = [np.zeros(g + 1, dtype=np.float32) for g in gens]
+    cr = (_Result * max(n, 1))(*[_Result(b.ctypes.data, 0.0, 0, t.ctypes.data, 0.0)
+                                 for b, t in zip(bests, traces)])
+    done = ctypes.c_int32(0)
+    _check(lib().pa_solve_batch_state(ctx.h, cr, ctypes.byref(done), _stream(stream)))
+    d = int(done.value)
+    return [Result(bests[i], float(cr[i].best_fit), int(cr[i].best_index),
+                   traces[i][:min(d, gens[i]) + 1], float(cr[i].device_ms))
+            for i in range(n)], d
+
+
+def pa_solve_population(ctx: Context | None, inst: Instance | None, index: int, L: int, K: int,
+                        N: int, stream=None):
+    """(population [N][L][K] uint8, fitness [N] float32, generation) of one
+    instance of a plan (inst's pa_solve plan, or the context's batch plan)."""
+    pop = np.zeros((N, L, K), dtype=np.uint8)
+    fit = np.zeros(N, dtype=np.float32)
+    gen = ctypes.c_int32(0)
+    _check(lib().pa_solve_population(ctx.h if ctx is not None else None,
+                                     inst.h if inst is not None else None, int(index),
+                                     pop.ctypes.data, fit.ctypes.data, ctypes.byref(gen),
+                                     _stream(stream)))
+    return pop, fit, int(gen.value)
+
+
 def pa_solve_begin(inst: Instance, params: GaParams, stream=None):
     inst._gens = params.gens
     p = params.to_c()
@@ -398,6 +477,14 @@ def pa_exhaustive(inst: Instance, max_count: int = 0, stream=None):
                    float(r.device_ms)), int(rank.value), int(cnt.value))
 
 
+def pa_device_peaks(ctx: Context) -> dict:
+    """Measured peak rates of the device (LDS gathers per clock and CU with
+    ds_read_b32 and ds_read_b128, FP32 VALU issue, shader clock)."""
+    r = _PeakRates()
+    _check(lib().pa_device_peaks(ctx.h, ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in r._fields_}
+
+
 # ---- continuous-batching server ---------------------------------------------
 
 PA_EAGAIN = -4
@@ -413,6 +500,7 @@ class Server:
                          int(max_gens), float(hbm_budget))
         self.h = ctypes.c_void_p()
         _check(lib().pa_server_create(ctx.h, ctypes.byref(cfg), ctypes.byref(self.h)))
+        _live["servers"].add(self)
         self.ctx = ctx
         self._shape = {}
 

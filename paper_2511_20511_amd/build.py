@@ -20,9 +20,16 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpa_amd.so")
 
-SOURCES = ["api.cpp", "k_prep.hip", "k_fitness.hip", "k_ga.hip", "k_kmeans.hip", "k_gen.hip",
-           "k_gen_L7.hip", "k_gen_L19.hip", "k_gen_L37.hip", "solve.cpp", "server.cpp",
-           "k_exhaustive.hip"]
+# (source, object name, extra defines)
+SOURCES = [(f, f, []) for f in ("api.cpp", "k_prep.hip", "k_fitness.hip", "k_ga.hip",
+                                "k_kmeans.hip", "k_gen.hip", "solve.cpp", "server.cpp",
+                                "k_exhaustive.hip", "k_peak.hip")]
+# the unrolled generation kernels: one object per (cells, SE mode, form), so
+# that they compile in parallel
+SOURCES += [("k_gen_unrolled.hip", f"k_gen_L{L}_m{m}_{form}.hip",
+             [f"-DPA_GEN_L={L}", f"-DPA_GEN_MODE={m}", f"-DPA_GEN_FORM={form}",
+              f"-DPA_GEN_PERSIST={int(form == 'p')}"])
+            for L in (37, 19, 7) for m in (0, 1) for form in ("x", "p")]
 ARCH = "gfx950"
 
 
@@ -39,9 +46,10 @@ def flags() -> list[str]:
             "-I", os.path.join(ROOT, "include"), "-Wall", "-Wno-unused-function"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [_hipcc()] + flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit) -> str:
+    src, name, defines = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [_hipcc()] + flags() + defines + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")

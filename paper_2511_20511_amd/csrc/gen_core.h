@@ -644,11 +644,6 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
 // ---------------------------------------------------------------- host side
 namespace pa {
 
-inline void gen_allow_lds(const void *kern, int bytes) {
-  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
-    (void)hipGetLastError();
-}
-
 inline GenArgs gen_args(const GenInst *insts, const GenClass &c, int gen, int grid) {
   GenArgs a;
   a.insts = insts;
@@ -664,16 +659,13 @@ template <int LT, int TPT, int MODE, int BLOCK>
 hipError_t gen_launch_exact(const GenInst *insts, const GenClass &c, int gen, hipStream_t s) {
   using P = GenPlan<LT, TPT, MODE, BLOCK>;
   auto kern = k_gen_exact<LT, TPT, MODE, BLOCK>;
-  static bool attr = false;
-  if (!attr) {
-    gen_allow_lds(reinterpret_cast<const void *>(kern), P::kTotal);
-    attr = true;
-  }
+  static LdsAttr attr;
+  const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(kern), P::kTotal);
   const int n = gen < 0 ? c.neval : c.ntasks;
   if (n <= 0) return hipSuccess;
   const int grid = c.grid < 1 ? 1 : (c.grid > n ? n : c.grid);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), P::kTotal, s, gen_args(insts, c, gen, grid));
-  return hipGetLastError();
+  return launch_status(ae);
 }
 
 // A persistent launch of a class (PersistArgs with the grid), or, when
@@ -686,78 +678,77 @@ struct PersistCall {
   int *capacity;
 };
 
+// The persistent kernel is an ordinary launch whose grid is at most the
+// number of its workgroups the device holds at once (the occupancy query
+// below; plans never ask for more).  On a device that runs nothing else all
+// of them are then resident together; if other streams keep CUs busy, the
+// late workgroups start as those kernels end, and a grid-barrier wait that
+// exceeds its bound makes the solve report PA_EINTERNAL instead of hanging.
+// (The cooperative-launch API is not used: the runtime serves it from an
+// internal device queue that lives until the process tears the runtime
+// down.)
 template <int LT, int TPT, int MODE, int BLOCK>
 hipError_t gen_persist_exact(const PersistCall &pc, hipStream_t s) {
   using P = PersistPlan<LT, TPT, MODE, BLOCK>;
   auto kern = k_gen_persist<LT, TPT, MODE, BLOCK>;
-  static bool attr = false;
-  if (!attr) {
-    gen_allow_lds(reinterpret_cast<const void *>(kern), P::kTotal);
-    attr = true;
-  }
+  static LdsAttr attr;
+  const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(kern), P::kTotal);
+  int nb = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &nb, reinterpret_cast<const void *>(kern), BLOCK, P::kTotal);
+  if (e != hipSuccess) return e;
   if (pc.capacity) {
-    int nb = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, reinterpret_cast<const void *>(kern), BLOCK, P::kTotal);
-    *pc.capacity = e == hipSuccess ? nb * pc.cus : 0;
-    return e;
+    *pc.capacity = nb * pc.cus;
+    return hipSuccess;
   }
-  PersistArgs a = pc.args;
-  void *args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(kern), dim3(pc.grid),
-                                    dim3(BLOCK), args, P::kTotal, s);
+  if (pc.grid < 1 || pc.grid > nb * pc.cus) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(kern, dim3(pc.grid), dim3(BLOCK), P::kTotal, s, pc.args);
+  return launch_status(ae);
 }
 
-template <int LT, int TPT, int MODE>
+template <int LT, int TPT, int MODE, bool PERSIST>
 hipError_t gen_dispatch_block(const GenInst *insts, const GenClass &c, int gen, hipStream_t s,
                               bool *handled, const PersistCall *pc) {
   *handled = true;
   switch (c.block) {
-    case 64:
-      return pc ? gen_persist_exact<LT, TPT, MODE, 64>(*pc, s)
-                : gen_launch_exact<LT, TPT, MODE, 64>(insts, c, gen, s);
     case 256:
-      return pc ? gen_persist_exact<LT, TPT, MODE, 256>(*pc, s)
-                : gen_launch_exact<LT, TPT, MODE, 256>(insts, c, gen, s);
+      if constexpr (PERSIST) return gen_persist_exact<LT, TPT, MODE, 256>(*pc, s);
+      else return gen_launch_exact<LT, TPT, MODE, 256>(insts, c, gen, s);
     case 512:
-      return pc ? gen_persist_exact<LT, TPT, MODE, 512>(*pc, s)
-                : gen_launch_exact<LT, TPT, MODE, 512>(insts, c, gen, s);
+      if constexpr (PERSIST) return gen_persist_exact<LT, TPT, MODE, 512>(*pc, s);
+      else return gen_launch_exact<LT, TPT, MODE, 512>(insts, c, gen, s);
     default: *handled = false; return hipSuccess;
   }
 }
 
-// Launches the unrolled generation kernel of cell count LT (its persistent
-// form when pc is set); *handled = false when no unrolled variant serves
-// (TP, mode, block).
-template <int LT>
-hipError_t gen_dispatch_L(const GenInst *insts, const GenClass &c, int gen, hipStream_t s,
-                          bool *handled, const PersistCall *pc) {
+// Launches the unrolled generation kernel of cell count LT and SE mode MODE
+// (its persistent form when PERSIST, with pc set); *handled = false when no
+// unrolled variant serves (L, mode, TP, block).
+template <int LT, int MODE, bool PERSIST>
+hipError_t gen_dispatch_unrolled(const GenInst *insts, const GenClass &c, int gen, hipStream_t s,
+                                 bool *handled, const PersistCall *pc) {
   *handled = false;
-  if (c.L != LT) return hipSuccess;
-  if (c.mode == 0) {
-    switch (c.TP) {
-      case 4: return gen_dispatch_block<LT, 4, 0>(insts, c, gen, s, handled, pc);
-      case 8: return gen_dispatch_block<LT, 8, 0>(insts, c, gen, s, handled, pc);
-      case 16: return gen_dispatch_block<LT, 16, 0>(insts, c, gen, s, handled, pc);
-      case 32: return gen_dispatch_block<LT, 32, 0>(insts, c, gen, s, handled, pc);
-      default: return hipSuccess;
-    }
-  }
+  if (c.L != LT || c.mode != MODE || (pc != nullptr) != PERSIST) return hipSuccess;
   switch (c.TP) {
-    case 4: return gen_dispatch_block<LT, 4, 1>(insts, c, gen, s, handled, pc);
-    case 8: return gen_dispatch_block<LT, 8, 1>(insts, c, gen, s, handled, pc);
-    case 16: return gen_dispatch_block<LT, 16, 1>(insts, c, gen, s, handled, pc);
-    case 32: return gen_dispatch_block<LT, 32, 1>(insts, c, gen, s, handled, pc);
+    case 4: return gen_dispatch_block<LT, 4, MODE, PERSIST>(insts, c, gen, s, handled, pc);
+    case 8: return gen_dispatch_block<LT, 8, MODE, PERSIST>(insts, c, gen, s, handled, pc);
+    case 16: return gen_dispatch_block<LT, 16, MODE, PERSIST>(insts, c, gen, s, handled, pc);
+    case 32: return gen_dispatch_block<LT, 32, MODE, PERSIST>(insts, c, gen, s, handled, pc);
     default: return hipSuccess;
   }
 }
 
-hipError_t gen_dispatch_L7(const GenInst *, const GenClass &, int, hipStream_t, bool *,
-                           const PersistCall *);
-hipError_t gen_dispatch_L19(const GenInst *, const GenClass &, int, hipStream_t, bool *,
-                            const PersistCall *);
-hipError_t gen_dispatch_L37(const GenInst *, const GenClass &, int, hipStream_t, bool *,
-                            const PersistCall *);
+// One dispatch function per (L, SE mode, form), each defined by its own
+// compile unit of k_gen_unrolled.hip (x: per-generation, p: persistent).
+using GenDispatchFn = hipError_t (*)(const GenInst *, const GenClass &, int, hipStream_t, bool *,
+                                     const PersistCall *);
+#define PA_GEN_DECL(LV, MV, FV)                                                                \
+  hipError_t gen_dispatch_L##LV##_m##MV##_##FV(const GenInst *, const GenClass &, int,         \
+                                               hipStream_t, bool *, const PersistCall *);
+PA_GEN_DECL(7, 0, x) PA_GEN_DECL(7, 0, p) PA_GEN_DECL(7, 1, x) PA_GEN_DECL(7, 1, p)
+PA_GEN_DECL(19, 0, x) PA_GEN_DECL(19, 0, p) PA_GEN_DECL(19, 1, x) PA_GEN_DECL(19, 1, p)
+PA_GEN_DECL(37, 0, x) PA_GEN_DECL(37, 0, p) PA_GEN_DECL(37, 1, x) PA_GEN_DECL(37, 1, p)
+#undef PA_GEN_DECL
 hipError_t gen_dispatch_generic(const GenInst *, const GenClass &, int, hipStream_t);
 
 }  // namespace pa

@@ -207,13 +207,6 @@ __global__ __launch_bounds__(1024) void k_fitness_generic(FitArgs a) {
 
 namespace {
 
-// Raises a kernel's dynamic-LDS limit; a runtime that does not need (or know)
-// the attribute leaves the default, so its error is cleared, not returned.
-void allow_lds(const void *kern, int bytes) {
-  if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess)
-    (void)hipGetLastError();
-}
-
 template <int LT, int TPT, int MODE>
 constexpr int exact_block() {
   // Small tables: 256 threads so several workgroups share a CU; large ones:
@@ -237,13 +230,10 @@ hipError_t run_exact(const FitArgs &a0, const DeviceInfo &dev, int grid_cap, hip
   if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
   if (grid > rounds) grid = rounds;
   auto kern = k_fitness_exact<LT, TPT, MODE, B>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    allow_lds(reinterpret_cast<const void *>(kern), P::kTotal);
-    attr_set = true;
-  }
+  static LdsAttr attr;
+  const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(kern), P::kTotal);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(B), P::kTotal, s, a);
-  return hipGetLastError();
+  return launch_status(ae);
 }
 
 template <int LT, int MODE>
@@ -294,13 +284,10 @@ hipError_t run_generic(const FitArgs &a0, int block, const DeviceInfo &dev, int 
   if (grid_cap > 0 && grid > grid_cap) grid = grid_cap;
   if (grid > rounds) grid = rounds;
   auto kern = k_fitness_generic<LMAX, MODE>;
-  static bool attr_set = false;
-  if (!attr_set) {
-    allow_lds(reinterpret_cast<const void *>(kern), kLdsBytes);
-    attr_set = true;
-  }
+  static LdsAttr attr;
+  const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(kern), kLdsBytes);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(block), total, s, a);
-  return hipGetLastError();
+  return launch_status(ae);
 }
 
 template <int MODE>

@@ -28,14 +28,11 @@ hipError_t gen_launch_generic(const GenInst *insts, const GenClass &c, int gen, 
   pl.sel_off = pl.idx_off + idxb;
   const int total = pl.sel_off + selb;
   auto kern = k_gen_generic<LMAX, MODE>;
-  static bool attr = false;
-  if (!attr) {
-    gen_allow_lds(reinterpret_cast<const void *>(kern), kLdsBytes);
-    attr = true;
-  }
+  static LdsAttr attr;
+  const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(kern), kLdsBytes);
   const int grid = c.grid < 1 ? 1 : (c.grid > n ? n : c.grid);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(block), total, s, gen_args(insts, c, gen, grid), pl);
-  return hipGetLastError();
+  return launch_status(ae);
 }
 
 template <int MODE>
@@ -66,14 +63,26 @@ int gen_children_per_task(int L, int K, int TP, int mode, int block) {
   return block / K;
 }
 
+// The unrolled variant of (L, SE mode, form), or null when there is none.
+GenDispatchFn unrolled_fn(int L, int mode, bool persist) {
+  static const GenDispatchFn table[3][2][2] = {
+      {{gen_dispatch_L7_m0_x, gen_dispatch_L7_m0_p}, {gen_dispatch_L7_m1_x, gen_dispatch_L7_m1_p}},
+      {{gen_dispatch_L19_m0_x, gen_dispatch_L19_m0_p},
+       {gen_dispatch_L19_m1_x, gen_dispatch_L19_m1_p}},
+      {{gen_dispatch_L37_m0_x, gen_dispatch_L37_m0_p},
+       {gen_dispatch_L37_m1_x, gen_dispatch_L37_m1_p}}};
+  const int li = L == 7 ? 0 : L == 19 ? 1 : L == 37 ? 2 : -1;
+  if (li < 0 || mode < 0 || mode > 1) return nullptr;
+  return table[li][mode][persist ? 1 : 0];
+}
+
 hipError_t launch_gen(const GenInst *insts, const GenClass &c, int gen, const DeviceInfo &dev,
                       hipStream_t s) {
   (void)dev;
   bool handled = false;
   hipError_t e = hipSuccess;
-  if (c.L == 7) e = gen_dispatch_L7(insts, c, gen, s, &handled, nullptr);
-  else if (c.L == 19) e = gen_dispatch_L19(insts, c, gen, s, &handled, nullptr);
-  else if (c.L == 37) e = gen_dispatch_L37(insts, c, gen, s, &handled, nullptr);
+  if (const GenDispatchFn fn = unrolled_fn(c.L, c.mode, false))
+    e = fn(insts, c, gen, s, &handled, nullptr);
   if (handled) return e;
   return gen_dispatch_generic(insts, c, gen, s);
 }
@@ -100,9 +109,8 @@ hipError_t launch_gen_persist(const GenInst *insts, const GenClass &c, const Per
   if (capacity) *capacity = 0;
   bool handled = false;
   hipError_t e = hipSuccess;
-  if (c.L == 7) e = gen_dispatch_L7(insts, c, 0, s, &handled, &pc);
-  else if (c.L == 19) e = gen_dispatch_L19(insts, c, 0, s, &handled, &pc);
-  else if (c.L == 37) e = gen_dispatch_L37(insts, c, 0, s, &handled, &pc);
+  if (const GenDispatchFn fn = unrolled_fn(c.L, c.mode, true))
+    e = fn(insts, c, 0, s, &handled, &pc);
   if (!handled) return capacity ? hipSuccess : hipErrorNotSupported;
   return e;
 }

@@ -4,9 +4,34 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "pa_dev.h"
 
 namespace pa {
+
+// A kernel's dynamic-LDS limit is raised once per kernel, by whichever
+// thread launches it first (std::call_once: the server's worker and caller
+// threads may race to the first launch); later launches reuse the outcome.
+struct LdsAttr {
+  std::once_flag once;
+  hipError_t err = hipSuccess;
+};
+inline hipError_t allow_lds_once(LdsAttr &a, const void *kern, int bytes) {
+  std::call_once(a.once, [&] {
+    a.err = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (a.err != hipSuccess) (void)hipGetLastError();  // not sticky: reported with the launch
+  });
+  return a.err;
+}
+// Status of a launch made after allow_lds_once returned attr_err: the launch's
+// own error, or, when the launch failed and raising the limit had failed
+// too, that earlier failure (the likely cause).
+inline hipError_t launch_status(hipError_t attr_err) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess && attr_err != hipSuccess) return attr_err;
+  return e;
+}
 
 constexpr int kMaxL = 64;
 constexpr int kMaxK = 64;

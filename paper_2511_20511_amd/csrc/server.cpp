@@ -100,6 +100,7 @@ struct pa_server {
   pa_status failed = PA_OK;
   std::string fail_msg;
   uint64_t submitted = 0, completed = 0, ticks = 0;
+  int max_chunk = 0;  // most tasks one workgroup ran in a launch (worker thread)
   std::thread worker;
 };
 
@@ -298,6 +299,7 @@ hipError_t tick(pa_server *S, std::vector<int> &finished) {
     c.ntasks = (int)(nt - off);
     c.grid = gen_class_grid(c.L, c.TP, c.mode, c.block, c.ntasks, S->ctx->info.cus);
     launches.push_back(Launch{c, off});
+    S->max_chunk = std::max(S->max_chunk, (c.ntasks + c.grid - 1) / std::max(1, c.grid));
   }
   if (e == hipSuccess && nt > 0) {
     e = hipMemcpyAsync(S->d_tasks, S->h_tasks, sizeof(GenTask) * nt, hipMemcpyHostToDevice, s);
@@ -592,6 +594,7 @@ pa_status pa_server_stats(pa_server *S, pa_server_counters *out) {
   out->completed = S->completed;
   out->ticks = S->ticks;
   out->slot_bytes = (double)S->slot_bytes;
+  out->max_tasks_per_workgroup = S->max_chunk;
   return PA_OK;
 }
 

@@ -46,6 +46,8 @@ struct SolvePlan {
   uint32_t *d_sync = nullptr;    // [0]: grid-barrier counter, [1]: barrier time-out flag
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int cur_gen = -1;  // stepwise solve: generations done (-1: not started)
+  int done_gen = -1; // generations the populations have reached (-1: never run)
+  std::vector<GenInst> h_inst;  // host copy of the descriptors
   std::vector<int32_t> h_idx;
   std::vector<float> h_fit, h_trace;
   std::vector<uint8_t> h_best;
@@ -317,6 +319,7 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
     I.ga = ga_from_params(&g);
     if (I.ga.n_km > 0) which.push_back(i);
   }
+  pl->h_inst = hi;
   PTRY(alloc(pl, &pl->d_insts, (size_t)n), "hipMalloc(plan)");
   PTRY(hipMemcpy(pl->d_insts, hi.data(), sizeof(GenInst) * n, hipMemcpyHostToDevice), "upload");
   pl->nwhich = (int)which.size();
@@ -489,6 +492,8 @@ pa_status run_plan(SolvePlan *pl, const DeviceInfo &dev, hipStream_t s, pa_resul
     PTRY(hipGraphLaunch(pl->exec, s), "hipGraphLaunch");
   }
   PTRY(hipEventRecord(pl->ev1, s), "hipEventRecord");
+  pl->cur_gen = -1;
+  pl->done_gen = pl->Gmax;
   return copy_results(pl, s, results, -1);
 }
 
@@ -540,6 +545,67 @@ bool plan_matches(const SolvePlan *pl, int n, pa_instance *const *insts, const p
 
 }  // namespace
 
+pa_status check_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
+                      const pa_ga_params *params) {
+  if (!ctx || !insts || !params) return set_error(PA_EINVAL, "NULL argument");
+  if (n < 1) return set_error(PA_EINVAL, "n=%d must be >= 1", n);
+  for (int i = 0; i < n; ++i) {
+    if (!insts[i]) return set_error(PA_EINVAL, "instance %d is NULL", i);
+    if (insts[i]->ctx != ctx) return set_error(PA_EINVAL, "instance %d belongs to another context", i);
+    for (int k = 0; k < i; ++k)
+      if (insts[k] == insts[i]) return set_error(PA_EINVAL, "instance %d appears twice", i);
+    pa_status st = validate_ga(insts[i], &params[i]);
+    if (st != PA_OK) return set_error(st, "instance %d: %s", i, pa_last_error());
+  }
+  return PA_OK;
+}
+
+// Stepwise solve of a plan: seeding and initial fitness (begin), ngens more
+// generations (next), best of the current populations (state).
+pa_status plan_begin(SolvePlan *pl, const DeviceInfo &dev, hipStream_t s) {
+  hipError_t e = launch_start(pl, s);
+  if (e == hipSuccess && pl->persist) e = launch_persist(pl, dev, -1, 0, false, s);
+  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess && !pl->persist; ++c)
+    e = launch_gen(pl->d_insts, pl->classes[c].c, -1, dev, s);
+  if (e != hipSuccess) return hip_error(e, "solve begin");
+  pl->cur_gen = 0;
+  pl->done_gen = 0;
+  return PA_OK;
+}
+
+pa_status plan_next(SolvePlan *pl, const DeviceInfo &dev, int ngens, hipStream_t s) {
+  if (!pl || pl->cur_gen < 0) return set_error(PA_EINVAL, "the stepwise solve was not begun");
+  if (ngens < 0 || pl->cur_gen + ngens > pl->Gmax)
+    return set_error(PA_EINVAL, "%d more generations exceed gens=%d (done %d)", ngens, pl->Gmax,
+                     pl->cur_gen);
+  if (pl->persist) {
+    if (ngens == 0) return PA_OK;
+    hipError_t e = launch_persist(pl, dev, pl->cur_gen, pl->cur_gen + ngens, false, s);
+    if (e != hipSuccess) return hip_error(e, "solve next");
+    pl->cur_gen += ngens;
+    pl->done_gen = pl->cur_gen;
+    return PA_OK;
+  }
+  for (int k = 0; k < ngens; ++k) {
+    for (size_t c = 0; c < pl->classes.size(); ++c) {
+      hipError_t e = launch_gen(pl->d_insts, pl->classes[c].c, pl->cur_gen, dev, s);
+      if (e != hipSuccess) return hip_error(e, "solve next");
+    }
+    ++pl->cur_gen;
+    pl->done_gen = pl->cur_gen;
+  }
+  return PA_OK;
+}
+
+pa_status plan_state(SolvePlan *pl, pa_result *out, int32_t *gens_done, hipStream_t s) {
+  if (!pl || pl->cur_gen < 0) return set_error(PA_EINVAL, "the stepwise solve was not begun");
+  PTRY(hipEventRecord(pl->ev0, s), "hipEventRecord");
+  PTRY(launch_best_batch(pl->d_insts, (int)pl->insts.size(), pl->cur_gen, s), "launch best");
+  PTRY(hipEventRecord(pl->ev1, s), "hipEventRecord");
+  if (gens_done) *gens_done = pl->cur_gen;
+  return copy_results(pl, s, out, pl->cur_gen);
+}
+
 int gen_class_block(int L, int TP, int mode, int maxK) {
   if (!exact_variant(L, TP)) return std::max(256, (maxK + 63) / 64 * 64);
   return tiled(L, TP, mode, 256) ? 512 : 256;
@@ -576,17 +642,10 @@ pa_status pa_solve(pa_instance *in, const pa_ga_params *g, pa_result *out, void 
 
 pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
                          const pa_ga_params *params, pa_result *results, void *stream) {
-  if (!ctx || !insts || !params || !results) return set_error(PA_EINVAL, "NULL argument");
-  if (n < 1) return set_error(PA_EINVAL, "n=%d must be >= 1", n);
-  for (int i = 0; i < n; ++i) {
-    if (!insts[i]) return set_error(PA_EINVAL, "instance %d is NULL", i);
-    if (insts[i]->ctx != ctx) return set_error(PA_EINVAL, "instance %d belongs to another context", i);
-    for (int k = 0; k < i; ++k)
-      if (insts[k] == insts[i]) return set_error(PA_EINVAL, "instance %d appears twice", i);
-    pa_status st = validate_ga(insts[i], &params[i]);
-    if (st != PA_OK) return set_error(st, "instance %d: %s", i, pa_last_error());
-  }
-  pa_status st = use_device(ctx);
+  if (!results) return set_error(PA_EINVAL, "NULL argument");
+  pa_status st = check_batch(ctx, n, insts, params);
+  if (st != PA_OK) return st;
+  st = use_device(ctx);
   if (st != PA_OK) return st;
   if (!plan_matches(ctx->batch_plan, n, insts, params)) {
     free_plan(ctx->batch_plan);
@@ -606,56 +665,73 @@ pa_status pa_solve_begin(pa_instance *in, const pa_ga_params *g, void *stream) {
     in->plan = nullptr;
     if ((st = build_plan(in->ctx, 1, &in, g, &in->plan)) != PA_OK) return st;
   }
-  SolvePlan *pl = in->plan;
-  hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_start(pl, s);
-  if (e == hipSuccess && pl->persist) e = launch_persist(pl, in->ctx->info, -1, 0, false, s);
-  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess && !pl->persist; ++c)
-    e = launch_gen(pl->d_insts, pl->classes[c].c, -1, in->ctx->info, s);
-  if (e != hipSuccess) return hip_error(e, "pa_solve_begin");
-  pl->cur_gen = 0;
-  return PA_OK;
+  return plan_begin(in->plan, in->ctx->info, (hipStream_t)stream);
 }
 
 pa_status pa_solve_next(pa_instance *in, int32_t ngens, void *stream) {
   if (!in) return set_error(PA_EINVAL, "instance is NULL");
-  SolvePlan *pl = in->plan;
-  if (!pl || pl->cur_gen < 0) return set_error(PA_EINVAL, "pa_solve_begin was not called");
-  if (ngens < 0 || pl->cur_gen + ngens > pl->Gmax)
-    return set_error(PA_EINVAL, "%d more generations exceed gens=%d (done %d)", ngens, pl->Gmax,
-                     pl->cur_gen);
   pa_status st = use_device(in->ctx);
   if (st != PA_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  if (pl->persist) {
-    if (ngens == 0) return PA_OK;
-    hipError_t e = launch_persist(pl, in->ctx->info, pl->cur_gen, pl->cur_gen + ngens, false, s);
-    if (e != hipSuccess) return hip_error(e, "pa_solve_next");
-    pl->cur_gen += ngens;
-    return PA_OK;
-  }
-  for (int k = 0; k < ngens; ++k) {
-    for (size_t c = 0; c < pl->classes.size(); ++c) {
-      hipError_t e = launch_gen(pl->d_insts, pl->classes[c].c, pl->cur_gen, in->ctx->info, s);
-      if (e != hipSuccess) return hip_error(e, "pa_solve_next");
-    }
-    ++pl->cur_gen;
-  }
-  return PA_OK;
+  return plan_next(in->plan, in->ctx->info, ngens, (hipStream_t)stream);
 }
 
 pa_status pa_solve_state(pa_instance *in, pa_result *out, int32_t *gens_done, void *stream) {
   if (!in || !out) return set_error(PA_EINVAL, "instance or result is NULL");
-  SolvePlan *pl = in->plan;
-  if (!pl || pl->cur_gen < 0) return set_error(PA_EINVAL, "pa_solve_begin was not called");
   pa_status st = use_device(in->ctx);
   if (st != PA_OK) return st;
+  return plan_state(in->plan, out, gens_done, (hipStream_t)stream);
+}
+
+pa_status pa_solve_batch_begin(pa_context *ctx, int32_t n, pa_instance *const *insts,
+                               const pa_ga_params *params, void *stream) {
+  pa_status st = check_batch(ctx, n, insts, params);
+  if (st != PA_OK) return st;
+  if ((st = use_device(ctx)) != PA_OK) return st;
+  if (!plan_matches(ctx->batch_plan, n, insts, params)) {
+    free_plan(ctx->batch_plan);
+    ctx->batch_plan = nullptr;
+    if ((st = build_plan(ctx, n, insts, params, &ctx->batch_plan)) != PA_OK) return st;
+  }
+  return plan_begin(ctx->batch_plan, ctx->info, (hipStream_t)stream);
+}
+
+pa_status pa_solve_batch_next(pa_context *ctx, int32_t ngens, void *stream) {
+  if (!ctx) return set_error(PA_EINVAL, "context is NULL");
+  pa_status st = use_device(ctx);
+  if (st != PA_OK) return st;
+  return plan_next(ctx->batch_plan, ctx->info, ngens, (hipStream_t)stream);
+}
+
+pa_status pa_solve_batch_state(pa_context *ctx, pa_result *results, int32_t *gens_done,
+                               void *stream) {
+  if (!ctx || !results) return set_error(PA_EINVAL, "context or results is NULL");
+  pa_status st = use_device(ctx);
+  if (st != PA_OK) return st;
+  return plan_state(ctx->batch_plan, results, gens_done, (hipStream_t)stream);
+}
+
+pa_status pa_solve_population(pa_context *ctx, pa_instance *in, int32_t index, uint8_t *pop,
+                              float *fit, int32_t *gen, void *stream) {
+  SolvePlan *pl = in ? in->plan : (ctx ? ctx->batch_plan : nullptr);
+  if (!pl) return set_error(PA_EINVAL, "no solve plan (solve first)");
+  if (pl->done_gen < 0) return set_error(PA_EINVAL, "the plan has not run");
+  if (index < 0 || index >= (int)pl->insts.size())
+    return set_error(PA_EINVAL, "index %d outside [0, %d)", index, (int)pl->insts.size());
+  pa_status st = use_device(in ? in->ctx : ctx);
+  if (st != PA_OK) return st;
+  const pa_ga_params &g = pl->params[index];
+  const DevProblem &p = pl->insts[index]->p;
+  const int G = std::min(pl->done_gen, g.gens);
+  const GenInst &I = pl->h_inst[index];
+  const size_t LK = (size_t)p.L * p.K;
   hipStream_t s = (hipStream_t)stream;
-  PTRY(hipEventRecord(pl->ev0, s), "hipEventRecord");
-  PTRY(launch_best_batch(pl->d_insts, 1, pl->cur_gen, s), "launch best");
-  PTRY(hipEventRecord(pl->ev1, s), "hipEventRecord");
-  if (gens_done) *gens_done = pl->cur_gen;
-  return copy_results(pl, s, out, pl->cur_gen);
+  if (pop) PTRY(hipMemcpyAsync(pop, I.pop[G & 1], LK * g.pop, hipMemcpyDeviceToHost, s), "copy population");
+  if (fit)
+    PTRY(hipMemcpyAsync(fit, I.fit[G & 1], sizeof(float) * g.pop, hipMemcpyDeviceToHost, s),
+         "copy fitness");
+  PTRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (gen) *gen = G;
+  return PA_OK;
 }
 
 pa_status pa_solve_shape(pa_context *ctx, pa_instance *in, int32_t *persistent, int32_t *block,
