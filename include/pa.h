@@ -274,6 +274,29 @@ pa_status pa_solve_population(pa_context *ctx, pa_instance *inst, int32_t index,
 pa_status pa_solve_plain(pa_instance *inst, const pa_ga_params *params, pa_result *out,
                          void *stream);
 
+/* pa_solve for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve and the same result bits as pa_solve, but no allocation of
+ * any kind.  The descriptor, task lists and double-buffered populations and
+ * fitness live in a fixed scratch array of the library, one per device, of
+ * PA_NOALLOC_SCRATCH_BYTES (8 MiB; the solve needs about 2 N L K + 8 N
+ * bytes plus 16 bytes per task of block / K chromosomes).  Outputs go to
+ * caller-owned DEVICE memory:
+ *   d_best      DEVICE L*K bytes: best chromosome of the last population
+ *   d_best_fit  DEVICE 1 float: its fitness
+ *   d_trace     DEVICE gens+1 floats (best fitness per generation), or NULL
+ * It also leaves the instance's K-means state as pa_kmeans_init does.
+ * Async on `stream`: outputs are valid once the stream has been
+ * synchronised.  PA_EINVAL for invalid parameters or a solve larger than the
+ * scratch; PA_EDEVICE when the scratch could not be located on the device.
+ * Every call on a device uses that device's one scratch array: calls that
+ * overlap on one device (other streams or threads) race, and a call must
+ * not start before the previous one on its device has finished unless both
+ * are on the same stream. */
+#define PA_NOALLOC_SCRATCH_BYTES (8u << 20)
+pa_status pa_solve_noalloc(pa_instance *inst, const pa_ga_params *params, uint8_t *d_best,
+                           float *d_best_fit, float *d_trace, void *stream);
+
 /* pa_fitness with an explicit launch shape, for tuning and tests:
  *   block     threads per workgroup (64..1024, multiple of 64, >= K; 0 = default)
  *   grid_cap  maximum workgroups (0 = enough to fill the GPU)

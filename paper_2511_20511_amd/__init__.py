@@ -26,7 +26,7 @@ __all__ = [
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
     "pa_solve_shape", "pa_solve_batch_begin", "pa_solve_batch_next", "pa_solve_batch_state",
-    "pa_solve_population", "pa_device_peaks", "release_all", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
+    "pa_solve_population", "pa_device_peaks", "pa_solve_noalloc", "release_all", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
     "pa_server_destroy", "Server", "pa_exhaustive",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
@@ -177,6 +177,7 @@ def lib():
         "pa_exhaustive": (st, [vp, ctypes.c_int64, ctypes.POINTER(_Result),
                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp]),
         "pa_device_peaks": (st, [vp, ctypes.POINTER(_PeakRates)]),
+        "pa_solve_noalloc": (st, [vp, ctypes.POINTER(_Params), vp, vp, vp, vp]),
         "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
         "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
         "pa_status_string": (ctypes.c_char_p, [st]),
@@ -421,6 +422,19 @@ def pa_solve_population(ctx: Context | None, inst: Instance | None, index: int, 
                                      pop.ctypes.data, fit.ctypes.data, ctypes.byref(gen),
                                      _stream(stream)))
     return pop, fit, int(gen.value)
+
+
+def pa_solve_noalloc(inst: Instance, params: GaParams, d_best, d_best_fit, d_trace=None,
+                     stream=None):
+    """pa_solve without any device allocation (async): best chromosome, its
+    fitness and (optionally) the trace into the caller's device tensors
+    (uint8 [L][K], float32 [1], float32 [gens+1])."""
+    import torch
+    p = params.to_c()
+    _check(lib().pa_solve_noalloc(inst.h, ctypes.byref(p), _dev(d_best, torch.uint8),
+                                  _dev(d_best_fit, torch.float32),
+                                  None if d_trace is None else _dev(d_trace, torch.float32),
+                                  _stream(stream)))
 
 
 def pa_solve_begin(inst: Instance, params: GaParams, stream=None):

@@ -283,6 +283,9 @@ pa_status pa_context_create(int32_t device, pa_context **out) {
     delete c;
     return hip_fail(e, "hipStreamCreate");
   }
+  // the no-allocation entry point's scratch: a failed lookup only disables
+  // that entry point (it then reports PA_EDEVICE)
+  if (noalloc_scratch(device, &c->scratch) != hipSuccess) c->scratch = nullptr;
   *out = c;
   return PA_OK;
 }

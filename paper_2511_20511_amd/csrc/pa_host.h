@@ -21,6 +21,7 @@ struct pa_context {
   pa::DeviceInfo info;
   hipStream_t stream = nullptr;          // library-internal work and graph capture
   pa::SolvePlan *batch_plan = nullptr;   // last pa_solve_batch plan (replayed when unchanged)
+  void *scratch = nullptr;               // device address of the device's no-allocation scratch
 };
 
 struct pa_instance {
@@ -55,4 +56,7 @@ pa_status use_device(pa_context *ctx);
 // ntasks tasks (0 when the table does not fit LDS).
 int gen_class_block(int L, int TP, int mode, int maxK);
 int gen_class_grid(int L, int TP, int mode, int block, int ntasks, int cus);
+// Device address of the no-allocation scratch array of `device` (looked up
+// once per device, with that device current); its lookup error otherwise.
+hipError_t noalloc_scratch(int device, void **ptr);
 }  // namespace pa
