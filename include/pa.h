@@ -333,21 +333,30 @@ pa_status pa_exhaustive(pa_instance *inst, int64_t max_count, pa_result *out, in
 /* ---- continuous-batching server -------------------------------------- */
 
 /* Many independent solves arriving over time (not in the paper; the serving
- * form of the batched solve).  A server owns a worker thread, a HIP stream and
- * `slots` device arenas, each sized for the largest request it accepts
- * (max_L, max_K, max_pop, max_gens); the number of slots is the smaller of
- * max_slots and hbm_budget / (bytes of one slot).  Each tick the worker
- * admits queued requests into free slots, runs ONE generation of every
- * resident request (each at its own generation; one launch per class of
- * (L, padded K, SE mode)), and returns the requests that reached their last
- * generation.  A request's result is bit-identical to pa_solve of the same
- * problem and parameters.
+ * form of the batched solve).  A server owns a worker thread, a HIP stream, a
+ * table of max_slots slots for resident requests and one device arena of the
+ * HBM budget.  Each tick the worker retires requests cancelled while
+ * resident, admits queued requests in arrival order while a slot is free and
+ * the arena holds the head request's own bytes (its tables, double-buffered
+ * populations and result, about 12 L^2 K + 2 N L K + 8 N bytes: a request
+ * takes what its sizes need, not what the largest would), runs ONE
+ * generation of every resident request (each at its own generation; one
+ * launch per class of (L, padded K, SE mode)), and returns the requests that
+ * reached their last generation.  A request's result is bit-identical to
+ * pa_solve of the same problem and parameters.  If a tick fails on the
+ * device, the requests resident at that moment fail with PA_EDEVICE and the
+ * worker goes on with the queue while the device still answers (otherwise
+ * every request fails and submit returns PA_EDEVICE).
  *   max_slots   resident requests at most (0 = 512)
  *   max_queue   waiting requests at most; beyond, submit returns PA_EAGAIN
  *               (0 = 1048576)
  *   max_L, max_K, max_pop, max_gens   largest accepted request
  *               (0 = 37, 32, 1024, 1000)
- *   hbm_budget  bytes of device memory for the slots (0 = 80% of free) */
+ *   hbm_budget  bytes of device memory for the arena (0 = 80% of free); the
+ *               arena is the smaller of this and max_slots largest requests
+ * Test hook: the environment variable PA_SERVER_FAULT_TICK=n, read at
+ * creation, makes the n-th tick report a device error after its work has
+ * completed (the recovery path runs, the device is not disturbed). */
 typedef struct pa_server_cfg {
   int32_t max_slots, max_queue;
   int32_t max_L, max_K, max_pop, max_gens;
@@ -355,22 +364,28 @@ typedef struct pa_server_cfg {
 } pa_server_cfg;
 
 /* Server counters: slots, resident and queued requests, requests submitted
- * and completed, ticks run, bytes of one slot, and the most generation tasks
- * one workgroup ran in a single launch so far. */
+ * and completed, ticks run, arena bytes of the largest accepted request, the
+ * most generation tasks one workgroup ran in a single launch, the most
+ * requests resident at once, requests cancelled and failed, the arena's size
+ * and its peak use in bytes. */
 typedef struct pa_server_counters {
   int32_t slots, resident, queued;
   uint64_t submitted, completed, ticks;
   double slot_bytes;
   int32_t max_tasks_per_workgroup;
+  int32_t max_resident;
+  uint64_t cancelled, failed;
+  double arena_bytes, arena_peak_bytes;
 } pa_server_counters;
 
 /* Creates a server on the context's device (cfg may be NULL for defaults).
- * PA_ENOMEM when the budget holds no slot.  Blocking. */
+ * PA_ENOMEM when the budget holds no request.  Blocking. */
 pa_status pa_server_create(pa_context *ctx, const pa_server_cfg *cfg, pa_server **out);
 /* Queues a request: the problem's host arrays are copied, so the caller may
  * reuse them at once.  *ticket identifies it.  PA_EINVAL for an invalid
- * problem or parameters or one larger than the slots, PA_EAGAIN when the
- * queue is full.  Thread-safe. */
+ * problem or parameters or one above the server's maxima, PA_ENOMEM for one
+ * whose bytes exceed the whole arena, PA_EAGAIN when the queue is full.
+ * Thread-safe. */
 pa_status pa_server_submit(pa_server *srv, const pa_problem *prob, const pa_ga_params *params,
                            uint64_t *ticket);
 /* Result of a request: fills out as pa_solve would (best and trace are
@@ -379,6 +394,11 @@ pa_status pa_server_submit(pa_server *srv, const pa_problem *prob, const pa_ga_p
  * block = 0: PA_EAGAIN while the request runs; block != 0: waits.  A ticket
  * can be polled successfully once.  Thread-safe. */
 pa_status pa_server_poll(pa_server *srv, uint64_t ticket, pa_result *out, int32_t block);
+/* Cancels a request: a queued one ends at once, a resident one before the
+ * worker's next tick (its arena block and slot are freed); polling it then
+ * returns PA_ECANCELED.  PA_EINVAL for an unknown ticket or one that has
+ * already finished.  Thread-safe. */
+pa_status pa_server_cancel(pa_server *srv, uint64_t ticket);
 /* Counters of the server.  Thread-safe. */
 pa_status pa_server_stats(pa_server *srv, pa_server_counters *out);
 /* Stops the worker after its current tick and frees the server; requests

@@ -27,7 +27,7 @@ __all__ = [
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
     "pa_solve_shape", "pa_solve_batch_begin", "pa_solve_batch_next", "pa_solve_batch_state",
     "pa_solve_population", "pa_device_peaks", "pa_solve_noalloc", "release_all", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
-    "pa_server_destroy", "Server", "pa_exhaustive",
+    "pa_server_destroy", "pa_server_cancel", "Server", "pa_exhaustive",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
     "SE_ASYMPTOTIC", "SE_FINITE_M",
@@ -104,7 +104,10 @@ class _ServerCounters(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("resident", ctypes.c_int32),
                 ("queued", ctypes.c_int32), ("submitted", ctypes.c_uint64),
                 ("completed", ctypes.c_uint64), ("ticks", ctypes.c_uint64),
-                ("slot_bytes", ctypes.c_double), ("max_tasks_per_workgroup", ctypes.c_int32)]
+                ("slot_bytes", ctypes.c_double), ("max_tasks_per_workgroup", ctypes.c_int32),
+                ("max_resident", ctypes.c_int32), ("cancelled", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("arena_bytes", ctypes.c_double),
+                ("arena_peak_bytes", ctypes.c_double)]
 
 
 @dataclass
@@ -173,6 +176,7 @@ def lib():
                                   ctypes.POINTER(ctypes.c_uint64)]),
         "pa_server_poll": (st, [vp, ctypes.c_uint64, ctypes.POINTER(_Result), i32]),
         "pa_server_stats": (st, [vp, ctypes.POINTER(_ServerCounters)]),
+        "pa_server_cancel": (st, [vp, ctypes.c_uint64]),
         "pa_server_destroy": (None, [vp]),
         "pa_exhaustive": (st, [vp, ctypes.c_int64, ctypes.POINTER(_Result),
                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp]),
@@ -562,6 +566,12 @@ def pa_server_poll(srv: Server, ticket: int, block: bool = True):
     _check(st)
     del srv._shape[ticket]
     return Result(best, float(r.best_fit), int(r.best_index), trace, float(r.device_ms))
+
+
+def pa_server_cancel(srv: Server, ticket: int):
+    """Cancels a queued or resident request; polling it then raises PaError
+    with status PA_ECANCELED (-5)."""
+    _check(lib().pa_server_cancel(srv.h, ctypes.c_uint64(ticket)))
 
 
 def pa_server_stats(srv: Server) -> dict:

@@ -18,10 +18,24 @@ struct GenArgs {
   const GenInst *insts;
   const GenTask *tasks;
   int ntasks;
-  int chunk;           // tasks per workgroup
   int gen;             // -1: fitness of the initial populations
   const int32_t *gens; // non-null: a task's generation is gens[task.inst] (gen ignored)
 };
+
+// The range of tasks of this workgroup in a launch of `ntasks` tasks: the
+// tasks are cut into gridDim.x contiguous runs whose lengths differ by at most
+// one, and the runs are dealt so that the workgroups of one XCD take
+// neighbouring runs.  Workgroup b is dispatched to XCD b % 8, so the
+// workgroups of an XCD share the instances (tables, populations) of a
+// contiguous 1/8 of the task list, and its L2 serves them.
+constexpr int kXcds = 8;
+__device__ __forceinline__ void task_range(int ntasks, int &t0, int &t1) {
+  const int b = blockIdx.x, G = gridDim.x;
+  const int x = b % kXcds, r = b / kXcds, per = G / kXcds, rem = G % kXcds;
+  const int run = x * per + min(x, rem) + r;  // a bijection of [0, G)
+  t0 = (int)(((int64_t)run * ntasks) / G);
+  t1 = (int)(((int64_t)(run + 1) * ntasks) / G);
+}
 
 // LDS plan: table tile | children (<= block*L) | inverse rows (<= block*L) |
 // sums (block*4) | elite indices (64 ints) |
@@ -452,8 +466,8 @@ __device__ __forceinline__ void gen_tasks_exact(const GenInst *insts, const GenT
 template <int LT, int TPT, int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int t0 = blockIdx.x * a.chunk;
-  const int t1 = min(a.ntasks, t0 + a.chunk);
+  int t0, t1;
+  task_range(a.ntasks, t0, t1);
   LdsState st;
   gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, st, a.gens);
 }
@@ -612,8 +626,8 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
   float *sE = reinterpret_cast<float *>(smem + pl.e_off);
   int32_t *sIdx = reinterpret_cast<int32_t *>(smem + pl.idx_off);
   int32_t *sSel = reinterpret_cast<int32_t *>(smem + pl.sel_off);
-  const int t0 = blockIdx.x * a.chunk;
-  const int t1 = min(a.ntasks, t0 + a.chunk);
+  int t0, t1;
+  task_range(a.ntasks, t0, t1);
   int loaded = -1;
   for (int t = t0; t < t1; ++t) {
     const GenTask task = load_task(a.tasks, t);
@@ -644,15 +658,22 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
 // ---------------------------------------------------------------- host side
 namespace pa {
 
-inline GenArgs gen_args(const GenInst *insts, const GenClass &c, int gen, int grid) {
+inline GenArgs gen_args(const GenInst *insts, const GenClass &c, int gen) {
   GenArgs a;
   a.insts = insts;
   a.gen = gen;
   a.gens = c.gens;
   a.tasks = (gen < 0 && !c.gens) ? c.eval_tasks : c.tasks;
   a.ntasks = (gen < 0 && !c.gens) ? c.neval : c.ntasks;
-  a.chunk = (a.ntasks + grid - 1) / grid;
   return a;
+}
+
+// Workgroups of `kern` (block threads, lds bytes of dynamic LDS) one CU holds.
+inline hipError_t per_cu_query(const void *kern, int block, int lds, int *out) {
+  int nb = 0;
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, block, lds);
+  *out = e == hipSuccess ? nb : 0;
+  return e;
 }
 
 template <int LT, int TPT, int MODE, int BLOCK>
@@ -661,10 +682,12 @@ hipError_t gen_launch_exact(const GenInst *insts, const GenClass &c, int gen, hi
   auto kern = k_gen_exact<LT, TPT, MODE, BLOCK>;
   static LdsAttr attr;
   const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(kern), P::kTotal);
+  if (c.query_per_cu) return per_cu_query(reinterpret_cast<const void *>(kern), BLOCK, P::kTotal,
+                                          c.query_per_cu);
   const int n = gen < 0 ? c.neval : c.ntasks;
   if (n <= 0) return hipSuccess;
   const int grid = c.grid < 1 ? 1 : (c.grid > n ? n : c.grid);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), P::kTotal, s, gen_args(insts, c, gen, grid));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), P::kTotal, s, gen_args(insts, c, gen));
   return launch_status(ae);
 }
 

@@ -9,7 +9,6 @@ namespace {
 template <int LMAX, int MODE>
 hipError_t gen_launch_generic(const GenInst *insts, const GenClass &c, int gen, hipStream_t s) {
   const int n = gen < 0 ? c.neval : c.ntasks;
-  if (n <= 0) return hipSuccess;
   const int block = c.block;
   const int L = c.L, TP = c.TP;
   const int child = (block * L + 15) / 16 * 16;
@@ -30,8 +29,11 @@ hipError_t gen_launch_generic(const GenInst *insts, const GenClass &c, int gen, 
   auto kern = k_gen_generic<LMAX, MODE>;
   static LdsAttr attr;
   const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(kern), kLdsBytes);
+  if (c.query_per_cu)
+    return per_cu_query(reinterpret_cast<const void *>(kern), block, total, c.query_per_cu);
+  if (n <= 0) return hipSuccess;
   const int grid = c.grid < 1 ? 1 : (c.grid > n ? n : c.grid);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), total, s, gen_args(insts, c, gen, grid), pl);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(block), total, s, gen_args(insts, c, gen), pl);
   return launch_status(ae);
 }
 

@@ -56,6 +56,9 @@ pa_status use_device(pa_context *ctx);
 // ntasks tasks (0 when the table does not fit LDS).
 int gen_class_block(int L, int TP, int mode, int maxK);
 int gen_class_grid(int L, int TP, int mode, int block, int ntasks, int cus);
+// Workgroups of the class's generation kernel at `block` threads that one CU
+// holds at once (occupancy query, cached; 0 when none fits).
+int gen_class_per_cu(int L, int TP, int mode, int block);
 // Device address of the no-allocation scratch array of `device` (looked up
 // once per device, with that device current); its lookup error otherwise.
 hipError_t noalloc_scratch(int device, void **ptr);

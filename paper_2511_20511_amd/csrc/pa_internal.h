@@ -136,6 +136,9 @@ struct GenClass {
   // non-null: the launch runs `tasks` with each instance at its own
   // generation gens[inst] (device; -1 = the initial fitness, eval tasks)
   const int32_t *gens = nullptr;
+  // non-null: launch nothing, store how many workgroups of the class's
+  // kernel (at `block`) one CU holds at once
+  int *query_per_cu = nullptr;
 };
 
 // ---- launchers (return hipSuccess or the first HIP error) ----------------

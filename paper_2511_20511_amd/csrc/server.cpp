@@ -1,10 +1,13 @@
 // server.cpp -- continuous-batching solve server (pa_server_*).
 //
 // Requests (a problem and GA parameters) are queued by any thread; one worker
-// thread per server owns a HIP stream and a fixed set of slots, each a device
-// arena sized for the configured maximum problem.  The number of slots is set
-// by the HBM budget.  Every tick the worker
-//   1. admits queued requests into free slots (upload, per-BS normalisation,
+// thread per server owns a HIP stream, a table of slots (resident requests)
+// and one device arena of the HBM budget, from which each admitted request
+// takes exactly the bytes its own sizes need (first fit; freed blocks merge
+// with their free neighbours).  Every tick the worker
+//   0. retires requests cancelled while resident;
+//   1. admits queued requests, in arrival order, while a slot is free and the
+//      arena holds the head request's bytes (upload, per-BS normalisation,
 //      descriptor), and seeds them (K-means, initial population);
 //   2. runs ONE generation for every resident request -- each at its own
 //      generation number, read per task from a device array -- with one
@@ -15,9 +18,14 @@
 //      chromosome, copies the result to pinned host memory and frees the
 //      slot.
 // Requests therefore join and leave the running batch between generations.
-// A request's result is bit-identical to pa_solve of the same instance.
+// A request's result is bit-identical to pa_solve of the same instance.  A
+// tick that fails on the device fails the requests resident at that moment;
+// the worker keeps serving the queue if the device still answers, and stops
+// (failing everything) if it does not.
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
+#include <iterator>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -47,6 +55,8 @@ struct Request {
   pa_problem prob{};  // arrays point into the vectors below
   std::vector<double> beta, user_xy, bs_xy;
   pa_ga_params params{};
+  size_t bytes = 0;        // device bytes of its arena block
+  bool cancel = false;     // cancelled while resident: retired at the next tick
   bool done = false;
   pa_status status = PA_OK;
   std::string error;
@@ -57,16 +67,60 @@ struct Request {
   double t_submit = 0.0, t_done = 0.0;
 };
 
-// Device arena of one slot (sized for the configured maxima) and the pinned
-// host staging of its result.
+// A resident request: its block of the device arena (laid out for its own
+// sizes) and the pinned host staging of its result (sized for the largest
+// accepted request).
 struct Slot {
   DevProblem p;
   uint8_t *pop[2] = {nullptr, nullptr};
   float *fit[2] = {nullptr, nullptr};
-  uint8_t *result = nullptr;  // device: best_idx | best_fit | trace[Gmax+1] | best[Lmax*Kmax]
+  uint8_t *result = nullptr;  // device: best_idx | best_fit | trace[G+1] | best[L*K]
   uint8_t *h_result = nullptr;  // pinned copy of `result`
   Request *req = nullptr;
+  size_t off = 0;  // arena block
   int gen = 0;  // next generation to run (-1: initial fitness)
+};
+
+// First-fit sub-allocator over [0, size) in 256-byte granules; free blocks
+// are kept by offset and merged with their neighbours when released.
+struct Arena {
+  size_t size = 0, used = 0, peak = 0;
+  std::map<size_t, size_t> free_blocks;  // offset -> bytes
+  void reset(size_t bytes) {
+    size = bytes;
+    used = peak = 0;
+    free_blocks.clear();
+    if (bytes) free_blocks[0] = bytes;
+  }
+  bool take(size_t bytes, size_t *off) {
+    for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, at = it->first + bytes;
+      free_blocks.erase(it);
+      if (rest) free_blocks[at] = rest;
+      used += bytes;
+      peak = std::max(peak, used);
+      return true;
+    }
+    return false;
+  }
+  void give(size_t off, size_t bytes) {
+    used -= bytes;
+    auto next = free_blocks.lower_bound(off);
+    if (next != free_blocks.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_blocks.erase(next);
+    }
+    if (next != free_blocks.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_blocks[off] = bytes;
+  }
 };
 
 }  // namespace
@@ -81,10 +135,11 @@ struct pa_server {
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr;
   std::vector<pa::Slot> slots;
-  void *arena = nullptr;          // device memory of every slot
+  void *arena = nullptr;          // device memory of every resident request
+  pa::Arena heap;                 // its sub-allocation (worker thread only)
   void *pinned = nullptr;         // pinned staging (results, descriptors, tasks)
-  size_t slot_bytes = 0;
-  size_t result_bytes = 0;        // per slot
+  size_t max_request_bytes = 0;   // arena bytes of the largest accepted request
+  size_t result_bytes = 0;        // pinned staging per slot
   pa::GenInst *d_insts = nullptr, *h_insts = nullptr;
   int32_t *d_gens = nullptr, *h_gens = nullptr;
   int32_t *d_which = nullptr, *h_which = nullptr;  // [3][nslots]: kmeans | init | best lists
@@ -99,22 +154,24 @@ struct pa_server {
   bool stop = false;
   pa_status failed = PA_OK;
   std::string fail_msg;
-  uint64_t submitted = 0, completed = 0, ticks = 0;
-  int max_chunk = 0;  // most tasks one workgroup ran in a launch (worker thread)
+  uint64_t submitted = 0, completed = 0, ticks = 0, cancelled = 0, failed_reqs = 0;
+  int max_chunk = 0;     // most tasks one workgroup ran in a launch (worker thread)
+  int max_resident = 0;  // most requests resident at once
+  uint64_t fault_tick = 0;  // test hook: this tick reports an injected device error
   std::thread worker;
 };
 
 namespace pa {
 namespace {
 
-// Sub-allocation of a slot's arena (the same layout for every slot).
+// Layout of a request's arena block, for its own sizes.
 struct SlotLayout {
   size_t beta, T2, T1, T2z, Town, lconst, user_xy, bs_xy, seed, cent, labels, iters, pop0, pop1,
       fit0, fit1, result, total;
 };
 
-SlotLayout layout(const pa_server_cfg &c, size_t *result_bytes) {
-  const size_t L = c.max_L, K = c.max_K, TP = pad_pilots(c.max_K), N = c.max_pop;
+SlotLayout layout(int Lq, int Kq, int Nq, int Gq) {
+  const size_t L = Lq, K = Kq, TP = pad_pilots(Kq), N = Nq;
   SlotLayout a{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -138,10 +195,13 @@ SlotLayout layout(const pa_server_cfg &c, size_t *result_bytes) {
   a.pop1 = take(N * L * K);
   a.fit0 = take(4 * N);
   a.fit1 = take(4 * N);
-  *result_bytes = up256(8 + 4 * ((size_t)c.max_gens + 1) + L * K);
-  a.result = take(*result_bytes);
+  a.result = take(8 + 4 * ((size_t)Gq + 1) + L * K);
   a.total = o;
   return a;
+}
+
+size_t result_staging(const pa_server_cfg &c) {
+  return up256(8 + 4 * ((size_t)c.max_gens + 1) + (size_t)c.max_L * c.max_K);
 }
 
 void fail_all(pa_server *S, pa_status st, const std::string &msg) {
@@ -158,15 +218,54 @@ void fail_all(pa_server *S, pa_status st, const std::string &msg) {
   S->queue.clear();
   for (auto &sl : S->slots) sl.req = nullptr;
   S->resident = 0;
+  S->heap.reset(S->heap.size);
 }
 
-// Uploads request r into slot i and writes its descriptor.
+// Ends the resident request of slot i with status st (not OK): frees its
+// arena block and slot.  Caller holds S->mu.
+void retire(pa_server *S, int i, pa_status st, const std::string &msg) {
+  Slot &sl = S->slots[i];
+  Request *r = sl.req;
+  r->done = true;
+  r->status = st;
+  r->error = msg;
+  r->t_done = now_s();
+  S->heap.give(sl.off, r->bytes);
+  sl.req = nullptr;
+  --S->resident;
+  if (st == PA_ECANCELED) ++S->cancelled;
+  else ++S->failed_reqs;
+}
+
+// Lays out request r in its arena block (slot i, block at sl.off), uploads it
+// and writes its descriptor.
 hipError_t admit(pa_server *S, int i, Request *r) {
   Slot &sl = S->slots[i];
   sl.req = r;
   sl.gen = -1;
   const pa_problem &pr = r->prob;
   DevProblem &p = sl.p;
+  {
+    const SlotLayout lay = layout(pr.L, pr.K, r->params.pop, r->params.gens);
+    uint8_t *b = static_cast<uint8_t *>(S->arena) + sl.off;
+    p.beta = reinterpret_cast<double *>(b + lay.beta);
+    p.T2 = reinterpret_cast<float *>(b + lay.T2);
+    p.T1 = reinterpret_cast<float *>(b + lay.T1);
+    p.T2z = reinterpret_cast<float *>(b + lay.T2z);
+    p.Town = reinterpret_cast<float *>(b + lay.Town);
+    p.lconst = reinterpret_cast<float *>(b + lay.lconst);
+    p.user_xy = reinterpret_cast<double *>(b + lay.user_xy);
+    p.bs_xy = reinterpret_cast<double *>(b + lay.bs_xy);
+    p.seed = b + lay.seed;
+    p.km_cent = reinterpret_cast<int32_t *>(b + lay.cent);
+    p.km_labels = reinterpret_cast<int32_t *>(b + lay.labels);
+    p.km_iters = reinterpret_cast<int32_t *>(b + lay.iters);
+    sl.pop[0] = b + lay.pop0;
+    sl.pop[1] = b + lay.pop1;
+    sl.fit[0] = reinterpret_cast<float *>(b + lay.fit0);
+    sl.fit[1] = reinterpret_cast<float *>(b + lay.fit1);
+    sl.result = b + lay.result;
+  }
   p.L = pr.L;
   p.K = pr.K;
   p.TP = pad_pilots(pr.K);
@@ -199,7 +298,7 @@ hipError_t admit(pa_server *S, int i, Request *r) {
   I.best_idx = reinterpret_cast<int32_t *>(sl.result);
   I.best_fit = reinterpret_cast<float *>(sl.result + 4);
   I.trace = reinterpret_cast<float *>(sl.result + 8);
-  I.best_out = sl.result + 8 + 4 * ((size_t)S->cfg.max_gens + 1);
+  I.best_out = sl.result + 8 + 4 * ((size_t)r->params.gens + 1);
   I.user_xy = pr.user_xy ? p.user_xy : nullptr;
   I.bs_xy = pr.user_xy ? p.bs_xy : nullptr;
   I.seed = p.seed;
@@ -233,15 +332,25 @@ hipError_t tick(pa_server *S, std::vector<int> &finished) {
   std::vector<int> fresh;
   {
     std::lock_guard<std::mutex> lk(S->mu);
+    // requests cancelled while resident leave before this tick's work
+    for (int i = 0; i < ns; ++i)
+      if (S->slots[i].req && S->slots[i].req->cancel)
+        retire(S, i, PA_ECANCELED, "request cancelled");
+    // admission in arrival order while a slot is free and the arena holds the
+    // head request's own bytes
     for (int i = 0; i < ns && !S->queue.empty(); ++i) {
       if (S->slots[i].req) continue;
       Request *r = S->queue.front();
+      size_t off = 0;
+      if (!S->heap.take(r->bytes, &off)) break;
       S->queue.pop_front();
       S->slots[i].req = r;  // reserved; uploaded below
+      S->slots[i].off = off;
       S->slots[i].gen = -1;
       ++S->resident;
       fresh.push_back(i);
     }
+    S->max_resident = std::max(S->max_resident, S->resident);
   }
   hipError_t e = hipSuccess;
   int nkm = 0;
@@ -340,11 +449,23 @@ hipError_t tick(pa_server *S, std::vector<int> &finished) {
     for (int i : finished) {
       if (e != hipSuccess) break;
       const Slot &sl = S->slots[i];
-      e = hipMemcpyAsync(sl.h_result, sl.result, S->result_bytes, hipMemcpyDeviceToHost, s);
+      const size_t LK = (size_t)sl.p.L * sl.p.K;
+      e = hipMemcpyAsync(sl.h_result, sl.result, 8 + 4 * ((size_t)sl.req->params.gens + 1) + LK,
+                         hipMemcpyDeviceToHost, s);
     }
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && S->fault_tick != 0 && S->ticks + 1 == S->fault_tick)
+    e = hipErrorLaunchFailure;  // test hook (the tick's work itself completed)
   return e;
+}
+
+// Waits for every stream of the server (errors ignored): after it no kernel
+// or copy of the server is in flight.
+void drain(pa_server *S) {
+  for (hipStream_t st : S->side)
+    if (st) (void)hipStreamSynchronize(st);
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
 }
 
 void complete(pa_server *S, const std::vector<int> &finished) {
@@ -359,10 +480,11 @@ void complete(pa_server *S, const std::vector<int> &finished) {
     std::memcpy(&r->best_fit, h + 4, 4);
     r->trace.assign(reinterpret_cast<const float *>(h + 8),
                     reinterpret_cast<const float *>(h + 8) + r->params.gens + 1);
-    const uint8_t *b = h + 8 + 4 * ((size_t)S->cfg.max_gens + 1);
+    const uint8_t *b = h + 8 + 4 * ((size_t)r->params.gens + 1);
     r->best.assign(b, b + LK);
     r->done = true;
     r->t_done = t;
+    S->heap.give(sl.off, r->bytes);
     sl.req = nullptr;
     --S->resident;
     ++S->completed;
@@ -381,12 +503,26 @@ void worker_main(pa_server *S) {
     }
     const hipError_t e = tick(S, finished);
     if (e != hipSuccess) {
+      // no work of the failed tick may still run when its requests' memory
+      // is reused: wait for every stream first
+      drain(S);
+      (void)hipGetLastError();
+      const std::string msg = std::string("server worker: ") + hipGetErrorString(e);
       std::lock_guard<std::mutex> lk(S->mu);
-      S->failed = PA_EDEVICE;
-      S->fail_msg = std::string("server worker: ") + hipGetErrorString(e);
-      fail_all(S, PA_EDEVICE, S->fail_msg);
+      ++S->ticks;
+      for (int i = 0; i < (int)S->slots.size(); ++i)
+        if (S->slots[i].req) retire(S, i, PA_EDEVICE, msg);
+      // keep serving when the device still answers, else fail everything
+      const hipError_t h = hipStreamSynchronize(S->stream);
+      if (h != hipSuccess || hipGetLastError() != hipSuccess) {
+        S->failed = PA_EDEVICE;
+        S->fail_msg = msg;
+        fail_all(S, PA_EDEVICE, S->fail_msg);
+        S->cv_done.notify_all();
+        return;
+      }
       S->cv_done.notify_all();
-      return;
+      continue;
     }
     ++S->ticks;
     if (!finished.empty()) complete(S, finished);
@@ -396,7 +532,7 @@ void worker_main(pa_server *S) {
 void free_server(pa_server *S) {
   if (!S) return;
   if (S->ctx) (void)hipSetDevice(S->ctx->device);
-  if (S->stream) (void)hipStreamSynchronize(S->stream);
+  drain(S);  // no kernel or copy of the server runs when its memory is freed
   if (S->arena) (void)hipFree(S->arena);
   if (S->d_insts) (void)hipFree(S->d_insts);
   if (S->d_gens) (void)hipFree(S->d_gens);
@@ -404,10 +540,7 @@ void free_server(pa_server *S) {
   if (S->d_tasks) (void)hipFree(S->d_tasks);
   if (S->pinned) (void)hipHostFree(S->pinned);
   for (hipStream_t st : S->side)
-    if (st) {
-      (void)hipStreamSynchronize(st);
-      (void)hipStreamDestroy(st);
-    }
+    if (st) (void)hipStreamDestroy(st);
   for (hipEvent_t ev : S->join)
     if (ev) (void)hipEventDestroy(ev);
   if (S->fork) (void)hipEventDestroy(S->fork);
@@ -444,30 +577,32 @@ pa_status pa_server_create(pa_context *ctx, const pa_server_cfg *cfg, pa_server 
   if (!S) return set_error(PA_ENOMEM, "host allocation failed");
   std::unique_ptr<pa_server, void (*)(pa_server *)> guard(S, free_server);
   S->ctx = ctx;
-  size_t result_bytes = 0;
-  const SlotLayout lay = layout(c, &result_bytes);
-  S->slot_bytes = lay.total;
-  S->result_bytes = result_bytes;
+  S->max_request_bytes = layout(c.max_L, c.max_K, c.max_pop, c.max_gens).total;
+  S->result_bytes = result_staging(c);
   double budget = c.hbm_budget;
   if (budget == 0.0) {
     size_t freeb = 0, total = 0;
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) return set_error(PA_EDEVICE, "hipMemGetInfo");
     budget = 0.8 * (double)freeb;
   }
-  const long fit = (long)(budget / (double)lay.total);
-  if (fit < 1) return set_error(PA_ENOMEM, "HBM budget %.0f B holds no slot of %zu B", budget, lay.total);
-  const int ns = (int)std::min<long>(c.max_slots, fit);
-  c.max_slots = ns;
+  // the arena: the budget, but never more than max_slots largest requests
+  const double cap = (double)S->max_request_bytes * c.max_slots;
+  const size_t arena = (size_t)std::min(budget, cap) & ~(size_t)255;
+  if (arena < 256)
+    return set_error(PA_ENOMEM, "HBM budget %.0f B holds no request", budget);
+  const int ns = c.max_slots;
   c.hbm_budget = budget;
   S->cfg = c;
   S->slots.resize(ns);
   S->task_cap = (size_t)ns * (c.max_pop + 1);
-  hipError_t e = hipMalloc(&S->arena, lay.total * ns);
+  if (const char *f = std::getenv("PA_SERVER_FAULT_TICK")) S->fault_tick = std::strtoull(f, nullptr, 10);
+  hipError_t e = hipMalloc(&S->arena, arena);
+  if (e == hipSuccess) S->heap.reset(arena);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_insts), sizeof(GenInst) * ns);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_gens), sizeof(int32_t) * ns);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_which), sizeof(int32_t) * 3 * ns);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&S->d_tasks), sizeof(GenTask) * S->task_cap);
-  const size_t pin_bytes = up256(result_bytes * ns) + up256(sizeof(GenInst) * ns) +
+  const size_t pin_bytes = up256(S->result_bytes * ns) + up256(sizeof(GenInst) * ns) +
                            up256(sizeof(int32_t) * 4 * ns) + sizeof(GenTask) * S->task_cap;
   if (e == hipSuccess) e = hipHostMalloc(&S->pinned, pin_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
@@ -481,35 +616,14 @@ pa_status pa_server_create(pa_context *ctx, const pa_server_cfg *cfg, pa_server 
   if (e != hipSuccess) return hip_error(e, "server allocation");
   uint8_t *pin = static_cast<uint8_t *>(S->pinned);
   uint8_t *h_results = pin;
-  pin += up256(result_bytes * ns);
+  pin += up256(S->result_bytes * ns);
   S->h_insts = reinterpret_cast<GenInst *>(pin);
   pin += up256(sizeof(GenInst) * ns);
   S->h_gens = reinterpret_cast<int32_t *>(pin);
   S->h_which = S->h_gens + ns;
   pin += up256(sizeof(int32_t) * 4 * ns);
   S->h_tasks = reinterpret_cast<GenTask *>(pin);
-  for (int i = 0; i < ns; ++i) {
-    uint8_t *b = static_cast<uint8_t *>(S->arena) + lay.total * i;
-    Slot &sl = S->slots[i];
-    sl.p.beta = reinterpret_cast<double *>(b + lay.beta);
-    sl.p.T2 = reinterpret_cast<float *>(b + lay.T2);
-    sl.p.T1 = reinterpret_cast<float *>(b + lay.T1);
-    sl.p.T2z = reinterpret_cast<float *>(b + lay.T2z);
-    sl.p.Town = reinterpret_cast<float *>(b + lay.Town);
-    sl.p.lconst = reinterpret_cast<float *>(b + lay.lconst);
-    sl.p.user_xy = reinterpret_cast<double *>(b + lay.user_xy);
-    sl.p.bs_xy = reinterpret_cast<double *>(b + lay.bs_xy);
-    sl.p.seed = b + lay.seed;
-    sl.p.km_cent = reinterpret_cast<int32_t *>(b + lay.cent);
-    sl.p.km_labels = reinterpret_cast<int32_t *>(b + lay.labels);
-    sl.p.km_iters = reinterpret_cast<int32_t *>(b + lay.iters);
-    sl.pop[0] = b + lay.pop0;
-    sl.pop[1] = b + lay.pop1;
-    sl.fit[0] = reinterpret_cast<float *>(b + lay.fit0);
-    sl.fit[1] = reinterpret_cast<float *>(b + lay.fit1);
-    sl.result = b + lay.result;
-    sl.h_result = h_results + result_bytes * i;
-  }
+  for (int i = 0; i < ns; ++i) S->slots[i].h_result = h_results + S->result_bytes * i;
   S->worker = std::thread(worker_main, S);
   *out = guard.release();
   return PA_OK;
@@ -532,6 +646,13 @@ pa_status pa_server_submit(pa_server *S, const pa_problem *prob, const pa_ga_par
   if (prob->user_xy) {
     r->user_xy.assign(prob->user_xy, prob->user_xy + L * K * 2);
     r->bs_xy.assign(prob->bs_xy, prob->bs_xy + L * 2);
+  }
+  r->bytes = layout(prob->L, prob->K, params->pop, params->gens).total;
+  if (r->bytes > S->heap.size) {
+    const size_t need = r->bytes, have = S->heap.size;
+    delete r;
+    return set_error(PA_ENOMEM, "request needs %zu bytes of device memory, the server has %zu",
+                     need, have);
   }
   r->prob = *prob;
   r->prob.beta = r->beta.data();
@@ -584,6 +705,32 @@ pa_status pa_server_poll(pa_server *S, uint64_t ticket, pa_result *out, int32_t 
   return PA_OK;
 }
 
+pa_status pa_server_cancel(pa_server *S, uint64_t ticket) {
+  if (!S) return set_error(PA_EINVAL, "NULL argument");
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end())
+      return set_error(PA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    if (r->done) return set_error(PA_EINVAL, "ticket %llu has already finished", (unsigned long long)ticket);
+    auto q = std::find(S->queue.begin(), S->queue.end(), r);
+    if (q != S->queue.end()) {
+      S->queue.erase(q);
+      r->done = true;
+      r->status = PA_ECANCELED;
+      r->error = "request cancelled";
+      r->t_done = now_s();
+      ++S->cancelled;
+    } else {
+      r->cancel = true;  // resident: the worker retires it before its next tick
+    }
+  }
+  S->cv_done.notify_all();
+  S->cv_work.notify_one();
+  return PA_OK;
+}
+
 pa_status pa_server_stats(pa_server *S, pa_server_counters *out) {
   if (!S || !out) return set_error(PA_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> lk(S->mu);
@@ -593,8 +740,13 @@ pa_status pa_server_stats(pa_server *S, pa_server_counters *out) {
   out->submitted = S->submitted;
   out->completed = S->completed;
   out->ticks = S->ticks;
-  out->slot_bytes = (double)S->slot_bytes;
+  out->slot_bytes = (double)S->max_request_bytes;
   out->max_tasks_per_workgroup = S->max_chunk;
+  out->max_resident = S->max_resident;
+  out->cancelled = S->cancelled;
+  out->failed = S->failed_reqs;
+  out->arena_bytes = (double)S->heap.size;
+  out->arena_peak_bytes = (double)S->heap.peak;
   return PA_OK;
 }
 

@@ -11,8 +11,13 @@
 //    per-generation launch is paid.
 // Either way a solve ends with one copy of the results.
 #include <algorithm>
+#include <array>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 
 #include "pa_host.h"
 
@@ -22,6 +27,8 @@ struct PlanClass {
   GenClass c;
   int cpt_div = 1;  // children per task = ceil(block / K / cpt_div)
   GenTask *d_tasks = nullptr, *d_evals = nullptr;
+  double work = 0.0;     // table gathers of one generation (for the class order)
+  bool tuned = false;    // the shape came from timing candidates (not the cache)
 };
 
 struct SolvePlan {
@@ -47,6 +54,7 @@ struct SolvePlan {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   int cur_gen = -1;  // stepwise solve: generations done (-1: not started)
   int done_gen = -1; // generations the populations have reached (-1: never run)
+  bool seeded = false;  // the populations hold a seeded generation (tuning)
   std::vector<GenInst> h_inst;  // host copy of the descriptors
   std::vector<int32_t> h_idx;
   std::vector<float> h_fit, h_trace;
@@ -82,24 +90,10 @@ hipError_t alloc(SolvePlan *pl, T **p, size_t count) {
 
 bool exact_variant(int L, int TP) { return (L == 7 || L == 19 || L == 37) && TP <= 32; }
 
-// LDS bytes of the generation kernel (mirrors its compile-time plan).
-int gen_lds_bytes(int L, int TP, int mode, int block) {
-  const int child = (block * L + 15) / 16 * 16;
-  const int extra = 2 * child + block * 4 + 256 + L * TP * 4 + block * 8;
-  const int row = L * TP * 4 * (mode == 1 ? 2 : 1);
-  const int budget = 163840 - extra - 256;
-  const int max_rows = budget / row;
-  if (max_rows < 1) return -1;
-  const int tiles = (L + max_rows - 1) / max_rows;
-  const int tr = (L + tiles - 1) / tiles;
-  return tr * row + extra;
-}
-
-bool tiled(int L, int TP, int mode, int block) {
-  const int child = (block * L + 15) / 16 * 16;
-  const int extra = 2 * child + block * 4 + 256 + L * TP * 4 + block * 8;
-  const int row = L * TP * 4 * (mode == 1 ? 2 : 1);
-  return (163840 - extra - 256) / row < L;
+// A table too large to sit in LDS beside a 256-thread task's buffers (about
+// 40 KiB) is tiled by the generation kernel.
+bool big_table(int L, int TP, int mode) {
+  return (long)L * L * TP * 4 * (mode == 1 ? 2 : 1) + 40 * 1024 > 160 * 1024;
 }
 
 struct ClassKey {
@@ -122,27 +116,10 @@ int count_tasks(const std::vector<int> &members, const std::vector<pa_instance *
 }
 
 // Launch shape of a class: threads per workgroup and children per task
-// (<= block / K).  Large tables keep 512 threads and full tasks (one tile load
-// serves 16-32 chromosomes).  When full tasks would leave CUs idle (few,
-// small instances) the tasks shrink so every CU gets one, but the workgroup
-// keeps 256 threads so the GA phases of a task still run on four waves.
+// (ceil(block / K / cpt_div)).
 struct Shape {
-  int block, cpt_div;  // cpt = ceil(block / K / cpt_div)
+  int block, cpt_div;
 };
-
-Shape choose_shape(const ClassKey &k, const std::vector<int> &members,
-                   const std::vector<pa_instance *> &insts, const std::vector<pa_ga_params> &params,
-                   int cus) {
-  int maxK = 0;
-  for (int i : members) maxK = std::max(maxK, insts[i]->p.K);
-  if (!exact_variant(k.L, k.TP)) return {std::max(256, (maxK + 63) / 64 * 64), 1};
-  if (tiled(k.L, k.TP, k.mode, 512)) return {512, 1};
-  if (count_tasks(members, insts, params, 512) >= cus) return {512, 1};
-  if (count_tasks(members, insts, params, 256) >= cus) return {256, 1};
-  int div = 1;
-  while (div < 256 / maxK && count_tasks(members, insts, params, 256, div) < cus) div *= 2;
-  return {256, div};
-}
 
 // Task lists (device) of a class of instances for a launch shape.
 pa_status make_class(SolvePlan *pl, const ClassKey &key, const std::vector<int> &members,
@@ -156,15 +133,16 @@ pa_status make_class(SolvePlan *pl, const ClassKey &key, const std::vector<int> 
   std::vector<GenTask> tasks, evals;
   for (int i : members) {
     const int K = hi[i].K, N = hi[i].N, E = hi[i].E;
+    pc.work += (double)(N - E) * key.L * key.L * K;
     const int cpr = std::max(1, (pc.c.block / K + sh.cpt_div - 1) / sh.cpt_div);
     tasks.push_back(GenTask{i, kTaskElite, 0, E});
     for (int s = E; s < N; s += cpr) tasks.push_back(GenTask{i, kTaskChild, s, std::min(N, s + cpr)});
     for (int s = 0; s < N; s += cpr) evals.push_back(GenTask{i, kTaskEval, s, std::min(N, s + cpr)});
   }
-  const int lds = gen_lds_bytes(key.L, key.TP, key.mode, pc.c.block);
-  if (lds < 0) return set_error(PA_EUNSUPPORTED, "table of L=%d does not fit LDS", key.L);
-  int per_cu = 163840 / lds;
-  per_cu = std::max(1, std::min(per_cu, 2048 / pc.c.block));
+  const int per_cu = gen_class_per_cu(key.L, key.TP, key.mode, pc.c.block);
+  if (per_cu < 1)
+    return set_error(PA_EUNSUPPORTED, "no generation kernel of L=%d TP=%d at %d threads fits a CU",
+                     key.L, key.TP, pc.c.block);
   pc.c.grid = std::min((int)tasks.size(), cus * per_cu);
   pc.c.ntasks = (int)tasks.size();
   pc.c.neval = (int)evals.size();
@@ -258,6 +236,183 @@ pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
   return PA_OK;
 }
 
+// Releases the device task lists of a candidate class that was not kept.
+void drop_class(SolvePlan *pl, const PlanClass &pc) {
+  for (void *p : {(void *)pc.d_tasks, (void *)pc.d_evals}) {
+    auto it = std::find(pl->owned.begin(), pl->owned.end(), p);
+    if (it != pl->owned.end()) {
+      (void)hipFree(p);
+      pl->owned.erase(it);
+    }
+  }
+}
+
+// Tuned shapes of the graph form, keyed by device and class signature; kept
+// for the process and, when PA_TUNE_CACHE names a file, in that file (one
+// "key block div" line per entry).
+struct TuneCache {
+  std::mutex mu;
+  std::map<std::string, Shape> map;
+  bool loaded = false;
+};
+TuneCache &tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+std::string class_signature(const pa_context *ctx, const ClassKey &key,
+                            const std::vector<int> &members, const std::vector<GenInst> &hi) {
+  hipDeviceProp_t prop;
+  std::string arch = "gfx";
+  if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+  arch = arch.substr(0, arch.find(':'));
+  long sumN = 0;
+  int maxK = 0, minK = 1 << 30, maxG = 0;
+  for (int i : members) {
+    sumN += hi[i].N;
+    maxK = std::max(maxK, hi[i].K);
+    minK = std::min(minK, hi[i].K);
+    maxG = std::max(maxG, hi[i].G);
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s/cu%d/L%d/TP%d/m%d/n%d/N%ld/K%d-%d/G%d", arch.c_str(),
+                ctx->info.cus, key.L, key.TP, key.mode, (int)members.size(), sumN, minK, maxK,
+                maxG > 0 ? 1 : 0);
+  return buf;
+}
+
+bool cache_lookup(const std::string &sig, Shape *out) {
+  TuneCache &c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  if (!c.loaded) {
+    c.loaded = true;
+    if (const char *path = std::getenv("PA_TUNE_CACHE")) {
+      if (FILE *f = std::fopen(path, "r")) {
+        char k[200];
+        int b, d;
+        while (std::fscanf(f, "%199s %d %d", k, &b, &d) == 3) c.map[k] = Shape{b, d};
+        std::fclose(f);
+      }
+    }
+  }
+  auto it = c.map.find(sig);
+  if (it == c.map.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void cache_store(const std::string &sig, const Shape &sh) {
+  TuneCache &c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.map[sig] = sh;
+  if (const char *path = std::getenv("PA_TUNE_CACHE")) {
+    if (FILE *f = std::fopen(path, "a")) {
+      std::fprintf(f, "%s %d %d\n", sig.c_str(), sh.block, sh.cpt_div);
+      std::fclose(f);
+    }
+  }
+}
+
+// Autotuning of the graph form, one class at a time: the candidate shapes are
+// the workgroup sizes the class's kernel comes in (256 and 512 threads for the
+// unrolled variants, one size for the runtime-L variant) times children per
+// task ceil(block / K / div), div = 1, 2, 4, 8 (while the task count changes).
+// Each candidate's generation launch is timed on the plan's own instances
+// (seeded, initial fitness evaluated): two runs of kTuneGens launches, the
+// faster kept; the cheapest candidate wins, within 3% the one with fewer
+// tasks.  The winner is cached per device architecture and class signature
+// (process, and PA_TUNE_CACHE), so a replanned batch of the same shape is not
+// timed again.  Shapes change the schedule, never a result bit.
+constexpr int kTuneGens = 3;
+
+pa_status tune_graph_class(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
+                           const std::vector<int> &members, const std::vector<GenInst> &hi,
+                           PlanClass *out) {
+  const int cus = ctx->info.cus;
+  int maxK = 0, maxG = 0;
+  for (int i : members) {
+    maxK = std::max(maxK, hi[i].K);
+    maxG = std::max(maxG, hi[i].G);
+  }
+  std::vector<int> blocks;
+  if (exact_variant(key.L, key.TP)) {
+    if (!big_table(key.L, key.TP, key.mode)) blocks.push_back(256);
+    blocks.push_back(512);
+  } else {
+    blocks.push_back(std::max(256, (maxK + 63) / 64 * 64));
+  }
+  // PA_GRAPH_SHAPE="block,div" in the environment forces one shape when the
+  // class's kernel comes in that size (for tests and reproducible profiles)
+  if (const char *force = std::getenv("PA_GRAPH_SHAPE")) {
+    int b = 0, d = 0;
+    if (std::sscanf(force, "%d,%d", &b, &d) == 2 && d >= 1 &&
+        std::find(blocks.begin(), blocks.end(), b) != blocks.end() &&
+        gen_class_per_cu(key.L, key.TP, key.mode, b) >= 1)
+      return make_class(pl, key, members, hi, Shape{b, d}, cus, out);
+  }
+  const std::string sig = class_signature(ctx, key, members, hi);
+  Shape cached{0, 0};
+  if (cache_lookup(sig, &cached))
+    return make_class(pl, key, members, hi, cached, cus, out);
+  std::vector<Shape> cands;
+  for (int block : blocks) {
+    if (gen_class_per_cu(key.L, key.TP, key.mode, block) < 1) continue;
+    int last = -1;
+    for (int div = 1; div <= 8 && div <= std::max(1, block / maxK); div *= 2) {
+      const int nt = count_tasks(members, pl->insts, pl->params, block, div);
+      if (nt == last) continue;
+      last = nt;
+      cands.push_back(Shape{block, div});
+    }
+  }
+  if (cands.empty())
+    return set_error(PA_EUNSUPPORTED, "no generation kernel of L=%d TP=%d fits a CU", key.L, key.TP);
+  if (cands.size() == 1 || maxG < 1) {
+    const Shape sh = cands.size() == 1 ? cands[0] : Shape{blocks.back(), 1};
+    return make_class(pl, key, members, hi, sh, cus, out);
+  }
+  hipStream_t cs = ctx->stream;
+  if (!pl->seeded) {
+    PTRY(launch_start(pl, cs), "tuning");
+    pl->seeded = true;
+  }
+  std::vector<float> cost(cands.size(), 0.0f);
+  std::vector<int> ntasks(cands.size(), 0);
+  std::vector<PlanClass> built(cands.size());
+  for (size_t k = 0; k < cands.size(); ++k) {
+    pa_status st = make_class(pl, key, members, hi, cands[k], cus, &built[k]);
+    if (st != PA_OK) return st;
+    ntasks[k] = built[k].c.ntasks;
+    PTRY(launch_gen(pl->d_insts, built[k].c, -1, ctx->info, cs), "tuning");
+    float best = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {
+      PTRY(hipEventRecord(pl->ev0, cs), "hipEventRecord");
+      for (int g = 0; g < kTuneGens; ++g)
+        PTRY(launch_gen(pl->d_insts, built[k].c, std::min(g, maxG - 1), ctx->info, cs), "tuning");
+      PTRY(hipEventRecord(pl->ev1, cs), "hipEventRecord");
+      PTRY(hipEventSynchronize(pl->ev1), "hipEventSynchronize");
+      float ms = 0.0f;
+      PTRY(hipEventElapsedTime(&ms, pl->ev0, pl->ev1), "hipEventElapsedTime");
+      best = rep == 0 ? ms : std::min(best, ms);
+    }
+    cost[k] = best;
+  }
+  const float lo = *std::min_element(cost.begin(), cost.end());
+  size_t win = 0;
+  for (size_t k = 0; k < cands.size(); ++k) {
+    if (cost[k] > lo * 1.03f) continue;
+    if (cost[win] > lo * 1.03f || ntasks[k] < ntasks[win] ||
+        (ntasks[k] == ntasks[win] && cost[k] < cost[win]))
+      win = k;
+  }
+  for (size_t k = 0; k < cands.size(); ++k)
+    if (k != win) drop_class(pl, built[k]);
+  built[win].tuned = true;
+  *out = built[win];
+  cache_store(sig, cands[win]);
+  return PA_OK;
+}
+
 pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
                      const pa_ga_params *params, SolvePlan **out) {
   SolvePlan *pl = new (std::nothrow) SolvePlan;
@@ -338,7 +493,6 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
     if (it == groups.end()) groups.push_back({key, {i}});
     else it->second.push_back(i);
   }
-  const int cus = ctx->info.cus;
   // persistent form: one class with an unrolled variant whose full tasks
   // (block / K children each) all fit on the device at once, for 256- and
   // 512-thread workgroups (512 only for tiled tables; PA_PERSIST_BLOCK=256 or
@@ -350,7 +504,7 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
     const ClassKey &key = groups[0].first;
     for (int block : {256, 512}) {
       if (only != 0 && block != only) continue;
-      if (block == 256 && tiled(key.L, key.TP, key.mode, 256)) continue;
+      if (block == 256 && big_table(key.L, key.TP, key.mode)) continue;
       GenClass q;
       q.L = key.L;
       q.TP = key.TP;
@@ -373,12 +527,15 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
     if (st != PA_OK) return st;
   } else {
     for (auto &grp : groups) {
-      const Shape sh = choose_shape(grp.first, grp.second, pl->insts, pl->params, cus);
       PlanClass pc;
-      pa_status st = make_class(pl, grp.first, grp.second, hi, sh, cus, &pc);
+      pa_status st = tune_graph_class(pl, ctx, grp.first, grp.second, hi, &pc);
       if (st != PA_OK) return st;
       pl->classes.push_back(pc);
     }
+    // longest class first: the classes run as concurrent graph branches, so
+    // the one with the most work starts first (largest-processing-time order)
+    std::stable_sort(pl->classes.begin(), pl->classes.end(),
+                     [](const PlanClass &a, const PlanClass &b) { return a.work > b.work; });
   }
   pl->h_idx.resize(n);
   pl->h_fit.resize(n);
@@ -608,14 +765,33 @@ pa_status plan_state(SolvePlan *pl, pa_result *out, int32_t *gens_done, hipStrea
 
 int gen_class_block(int L, int TP, int mode, int maxK) {
   if (!exact_variant(L, TP)) return std::max(256, (maxK + 63) / 64 * 64);
-  return tiled(L, TP, mode, 256) ? 512 : 256;
+  return big_table(L, TP, mode) ? 512 : 256;
+}
+
+int gen_class_per_cu(int L, int TP, int mode, int block) {
+  static std::mutex mu;
+  static std::map<std::array<int, 4>, int> cache;
+  const std::array<int, 4> key{L, TP, mode, block};
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  GenClass q;
+  q.L = L;
+  q.TP = TP;
+  q.mode = mode;
+  q.block = block;
+  int nb = 0;
+  q.query_per_cu = &nb;
+  if (launch_gen(nullptr, q, 0, DeviceInfo{}, nullptr) != hipSuccess) nb = 0;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = nb;
+  return nb;
 }
 
 int gen_class_grid(int L, int TP, int mode, int block, int ntasks, int cus) {
-  const int lds = gen_lds_bytes(L, TP, mode, block);
-  if (lds < 0) return 0;
-  int per_cu = 163840 / lds;
-  per_cu = std::max(1, std::min(per_cu, 2048 / block));
+  const int per_cu = std::max(1, gen_class_per_cu(L, TP, mode, block));
   return std::max(1, std::min(ntasks, cus * per_cu));
 }
 

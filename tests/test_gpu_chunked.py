@@ -127,3 +127,38 @@ def test_server_ticks_with_more_tasks_than_workgroups():
     for i, inst in enumerate(insts):
         _same(results[i], pa.pa_solve(inst, params[i]))
         inst.close()
+
+
+def test_graph_shapes_keep_bits():
+    """Every shape the graph-form autotuner can pick (threads per workgroup,
+    children per task) gives the same bits: a mixed batch under forced shapes
+    against the tuned one."""
+    need_gpu()
+    import os
+    import paper_2511_20511_amd as pa
+    sizes = [(37, 32, 300, 3), (37, 20, 200, 3), (19, 16, 256, 4), (19, 25, 180, 4),
+             (7, 4, 128, 5), (7, 9, 150, 5), (12, 7, 64, 3)]
+    drops, insts, params = _instances(pa, sizes, 83)
+    saved = os.environ.get("PA_GRAPH_SHAPE")
+    results = {}
+    try:
+        for force in (None, "256,1", "512,1", "512,2", "256,4", "512,8"):
+            if force is None:
+                os.environ.pop("PA_GRAPH_SHAPE", None)
+            else:
+                os.environ["PA_GRAPH_SHAPE"] = force
+            # a new plan per setting: another instance set is planned in between
+            pa.pa_solve_batch(ctx(), insts[:1], params[:1])
+            results[force] = pa.pa_solve_batch(ctx(), insts, params)
+            flush(f"  shape {force}: {pa.pa_solve_shape(ctx(), None)}")
+    finally:
+        if saved is None:
+            os.environ.pop("PA_GRAPH_SHAPE", None)
+        else:
+            os.environ["PA_GRAPH_SHAPE"] = saved
+    ref = results[None]
+    for force, res in results.items():
+        for a, b in zip(res, ref):
+            _same(a, b)
+    for inst in insts:
+        inst.close()
