@@ -73,11 +73,13 @@ def lib():
         L.pao_kmeans_seed.argtypes = [i32, i32, f64p, f64p, u8p, i32p, i32p, i32p]
         L.pao_init_pop.argtypes = [i32, i32, i32, f64, f64, u64, u32, u8p, u8p]
         L.pao_ga_step.argtypes = [i32, i32, i32, i32, f64, f64, u64, u32, u32, u8p, f64p, u8p]
+        L.pao_mutation_codes.argtypes = [i32, i32, f64, u64, u32, u32, u32, u8p]
         L.pao_solve.argtypes = [i32, i32, i32, i32, f64, f64, f64p, f64p, f64p, i32, i32, i32,
                                 f64, f64, f64, f64, u64, u32, u8p, f64p, f64p, u8p]
         L.pao_bruteforce.argtypes = [i32, i32, i32, i32, f64, f64, f64p, u8p, f64p, i64p]
         for name in ("pao_fitness", "pao_fitness_obj", "pao_se_terms", "pao_rank", "pao_kmeans_seed",
-                     "pao_init_pop", "pao_ga_step", "pao_solve", "pao_bruteforce"):
+                     "pao_init_pop", "pao_ga_step", "pao_solve", "pao_bruteforce",
+                     "pao_mutation_codes"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -173,6 +175,17 @@ def init_pop(L, K, N, kmeans_frac, p_init, seed, instance_id, seed_chrom=None):
                             _p(sc, ctypes.c_uint8), _p(pop, ctypes.c_uint8))
     _check(rc, "init_pop")
     return pop
+
+
+def mutation_codes(L, K, p_mut, seed, slot, gen, instance_id):
+    """Mutation codes [L][K] of one child (k'+1 where gene (j, k) swaps with k', else 0):
+    the per-gene mutation of the GA step (Sec. 6.1) with bit-sliced decision words."""
+    out = np.zeros((L, K), dtype=np.uint8)
+    rc = lib().pao_mutation_codes(L, K, float(p_mut), int(seed) & ((1 << 64) - 1),
+                                  int(slot) & 0xFFFFFFFF, int(gen) & 0xFFFFFFFF,
+                                  int(instance_id) & 0xFFFFFFFF, _p(out, ctypes.c_uint8))
+    _check(rc, "mutation_codes")
+    return out
 
 
 def ga_step(pop, fit, E, p_cross, p_mut, seed, instance_id, gen):

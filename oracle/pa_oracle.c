@@ -362,6 +362,61 @@ static void swap_mutate(int L, int K, uint8_t *chrom, uint64_t thr, uint64_t see
   }
 }
 
+/* Mutation codes of a child of the generation loop (the per-gene swap
+ * mutation of the GA step; Sec. 6.1 mutates each gene with probability p_mut,
+ * the paper fixes no random streams).  Each gene's decision is the event "its
+ * 32-bit decision word is below thr(p_mut)", as for swap_mutate, but the
+ * decision words are laid out bit-sliced: genes go in groups of 32 (group q
+ * holds genes 32q .. 32q+31 of the row-major chromosome), and bit 31-k of the
+ * decision word of gene 32q + b is bit b of word 32q + k of the MUT_DECIDE
+ * stream (k = 0..31).  Distinct bits of independent uniform words are
+ * independent uniform bits, so every decision word is uniform on [0, 2^32)
+ * and independent of the others: the law of one word per gene.  The h-th
+ * mutating gene of group q (h = 0, 1, .. in increasing gene order) draws its
+ * partner from word 32q + h of the MUT_PARTNER stream: r = bounded(word,
+ * K-1), partner k' = r + (r >= k).  codes[i] = k' + 1 for a mutating gene
+ * i = j*K + k and 0 otherwise. */
+int pao_mutation_codes(int32_t L, int32_t K, double p_mut, uint64_t seed, uint32_t slot,
+                       uint32_t gen, uint32_t instance_id, uint8_t *codes) {
+  if (L < 1 || K < 1) return -1;
+  const int LK = L * K;
+  const uint64_t thr = pao_threshold(p_mut);
+  memset(codes, 0, (size_t)LK);
+  if (K < 2) return 0;
+  for (int q = 0; 32 * q < LK; ++q) {
+    uint32_t R[32];
+    for (int k = 0; k < 32; ++k)
+      R[k] = pao_word(seed, slot, gen, instance_id, PAO_TAG_MUT_DECIDE, (uint32_t)(32 * q + k));
+    int h = 0;
+    for (int b = 0; b < 32 && 32 * q + b < LK; ++b) {
+      uint32_t w = 0;
+      for (int k = 0; k < 32; ++k) w |= ((R[k] >> b) & 1u) << (31 - k);
+      if ((uint64_t)w < thr) {
+        const int i = 32 * q + b, k = i % K;
+        uint32_t r = pao_bounded(pao_word(seed, slot, gen, instance_id, PAO_TAG_MUT_PARTNER,
+                                          (uint32_t)(32 * q + h)),
+                                 (uint32_t)(K - 1));
+        codes[i] = (uint8_t)((int)r + ((int)r >= k ? 1 : 0) + 1);
+        ++h;
+      }
+    }
+  }
+  return 0;
+}
+
+/* Applies mutation codes to a chromosome: genes in increasing row-major
+ * order, each mutating gene swapping pilots with its partner in the current
+ * row.  Rows stay permutations. */
+static void apply_codes(int L, int K, uint8_t *chrom, const uint8_t *codes) {
+  for (int i = 0; i < L * K; ++i) {
+    if (!codes[i]) continue;
+    int j = i / K, k = i % K, kp = codes[i] - 1;
+    uint8_t t = chrom[j * K + k];
+    chrom[j * K + k] = chrom[j * K + kp];
+    chrom[j * K + kp] = t;
+  }
+}
+
 /* Initial population.  Individual 0 is the K-means seed, individuals
  * 1..n_km-1 are the seed after swap mutation at rate p_init, and the rest are
  * uniformly random rows (Fisher-Yates from the identity), i.e. the random
@@ -410,7 +465,8 @@ int pao_init_pop(int32_t L, int32_t K, int32_t N, double kmeans_frac, double p_i
  *    word 4 decides single-point crossover (probability p_cross, Sec. 6.1),
  *    applied on the cell axis so rows stay permutations, word 5 the cut;
  *  - each child is swap-mutated with per-gene probability p_mut, keyed by its
- *    own slot.  If N - E is odd the last pair keeps child a only. */
+ *    own slot (pao_mutation_codes).  If N - E is odd the last pair keeps
+ *    child a only. */
 int pao_ga_step(int32_t L, int32_t K, int32_t N, int32_t E, double p_cross, double p_mut,
                 uint64_t seed, uint32_t instance_id, uint32_t gen, const uint8_t *pop_in,
                 const double *fit_in, uint8_t *pop_out) {
@@ -422,7 +478,9 @@ int pao_ga_step(int32_t L, int32_t K, int32_t N, int32_t E, double p_cross, doub
   for (int e = 0; e < E; ++e) memcpy(pop_out + e * G, pop_in + (size_t)order[e] * G, G);
   free(order);
 
-  const uint64_t thr_c = pao_threshold(p_cross), thr_m = pao_threshold(p_mut);
+  const uint64_t thr_c = pao_threshold(p_cross);
+  uint8_t *codes = (uint8_t *)malloc(G);
+  if (!codes) return -2;
   for (int a = E; a < N; a += 2) {
     int b = a + 1;
     uint32_t w[6];
@@ -447,12 +505,14 @@ int pao_ga_step(int32_t L, int32_t K, int32_t N, int32_t E, double p_cross, doub
       memcpy(ca, P1, G);
       if (cb) memcpy(cb, P2, G);
     }
-    swap_mutate(L, K, ca, thr_m, seed, (uint32_t)a, gen, instance_id, PAO_TAG_MUT_DECIDE,
-                PAO_TAG_MUT_PARTNER);
-    if (cb)
-      swap_mutate(L, K, cb, thr_m, seed, (uint32_t)b, gen, instance_id, PAO_TAG_MUT_DECIDE,
-                  PAO_TAG_MUT_PARTNER);
+    pao_mutation_codes(L, K, p_mut, seed, (uint32_t)a, gen, instance_id, codes);
+    apply_codes(L, K, ca, codes);
+    if (cb) {
+      pao_mutation_codes(L, K, p_mut, seed, (uint32_t)b, gen, instance_id, codes);
+      apply_codes(L, K, cb, codes);
+    }
   }
+  free(codes);
   return 0;
 }
 

@@ -69,6 +69,11 @@ int pao_kmeans_seed(int32_t L, int32_t K, const double *user_xy, const double *b
 /* Initial population [N][L][K]; seed_chrom may be NULL when kmeans_frac == 0. */
 int pao_init_pop(int32_t L, int32_t K, int32_t N, double kmeans_frac, double p_init,
                  uint64_t seed, uint32_t instance_id, const uint8_t *seed_chrom, uint8_t *pop);
+/* Mutation codes [L*K] of the child in `slot` at generation `gen`: k'+1 for a
+ * gene (j, k) that swaps with user k' of its cell, 0 otherwise (decision
+ * words bit-sliced over groups of 32 genes, partners by hit rank). */
+int pao_mutation_codes(int32_t L, int32_t K, double p_mut, uint64_t seed, uint32_t slot,
+                       uint32_t gen, uint32_t instance_id, uint8_t *codes);
 /* One generation: elitism, tournament selection, row crossover, swap mutation. */
 int pao_ga_step(int32_t L, int32_t K, int32_t N, int32_t E, double p_cross, double p_mut,
                 uint64_t seed, uint32_t instance_id, uint32_t gen, const uint8_t *pop_in,

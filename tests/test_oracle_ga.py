@@ -255,3 +255,85 @@ def test_solve_trace_and_result(oracle_mod):
     _, bfm, tm = oracle_mod.solve(drop.beta, drop.user_xy, drop.bs_xy, 20, 5, 2, 0.8, 0.05, 0.5,
                                   0.1, 1, 0, T=196, se_mode=oracle_mod.SE_FINITE_M, M=128, rho=rho)
     assert np.all(np.diff(tm) >= 0) and bfm > 0
+
+
+# ---------------------------------------------------------------- mutation draws
+
+def _group_words(oracle_mod, seed, slot, gen, inst, tag, q, n=32):
+    return [oracle_mod.word(seed, slot, gen, inst, tag, 32 * q + k) for k in range(n)]
+
+
+@pytest.mark.parametrize("L,K", [(8, 8), (5, 7), (3, 32)])
+def test_mutation_decisions_at_dyadic_rates(oracle_mod, L, K):
+    """At p = 1/2, 1/4 and 3/4 the comparison 'decision word < thr' reads only
+    the first one or two bits of the word, so the mutating genes of group q
+    are fixed by the first words of the group: ~R0 (1/2), ~R0 & ~R1 (1/4),
+    ~(R0 & R1) (3/4), bit b for gene 32q + b.  A reversed bit order, a wrong
+    word index or a wrong gene-to-bit map fails this."""
+    LK = L * K
+    for p, rule in ((0.5, lambda r0, r1: ~r0), (0.25, lambda r0, r1: ~r0 & ~r1),
+                    (0.75, lambda r0, r1: ~(r0 & r1))):
+        for slot in range(3):
+            codes = oracle_mod.mutation_codes(L, K, p, 77, slot, 5, 2).reshape(-1)
+            for q in range((LK + 31) // 32):
+                r0, r1 = _group_words(oracle_mod, 77, slot, 5, 2, oracle_mod.TAG_MUT_DECIDE, q, 2)
+                m = rule(r0, r1) & 0xFFFFFFFF
+                for b in range(min(32, LK - 32 * q)):
+                    assert (codes[32 * q + b] != 0) == bool((m >> b) & 1), (p, slot, q, b)
+
+
+def test_mutation_partners_by_hit_rank(oracle_mod):
+    """The h-th mutating gene of group q swaps with the user drawn from word
+    32q + h of the partner stream (r = bounded(word, K-1), k' = r + (r >= k)):
+    at p = 1 every gene mutates (h = b), at p = 1/2 the hits are counted."""
+    L, K = 4, 12
+    for p in (1.0, 0.5):
+        codes = oracle_mod.mutation_codes(L, K, p, 9, 3, 1, 0).reshape(-1)
+        for q in range((L * K + 31) // 32):
+            h = 0
+            for b in range(min(32, L * K - 32 * q)):
+                i = 32 * q + b
+                if codes[i] == 0:
+                    continue
+                w = oracle_mod.word(9, 3, 1, 0, oracle_mod.TAG_MUT_PARTNER, 32 * q + h)
+                r = oracle_mod.bounded(w, K - 1)
+                k = i % K
+                assert codes[i] == r + (1 if r >= k else 0) + 1
+                h += 1
+            if p == 1.0:
+                assert h == min(32, L * K - 32 * q)
+
+
+def test_mutation_law(oracle_mod):
+    """The per-gene decisions are independent Bernoulli(p) events: each of the
+    32 bit positions of a group mutates at rate p (chi-square), the gaps
+    between consecutive mutating genes of a child follow the geometric law
+    P(gap = g) = (1-p)^g p (chi-square), and neighbouring genes are
+    uncorrelated."""
+    L, K, p, n = 8, 8, 0.05, 6000
+    hits = np.stack([oracle_mod.mutation_codes(L, K, p, 123, s, 7, 1).reshape(-1) != 0
+                     for s in range(n)])
+    # rate per bit position (genes b and 32 + b share bit b)
+    pos = hits.reshape(n, 2, 32).sum(axis=(0, 1))
+    exp = 2 * n * p
+    chi = ((pos - exp) ** 2 / (exp * (1 - p))).sum()
+    assert stats.chi2.sf(chi, 31) > 1e-3
+    # gaps between consecutive hits inside a child
+    gaps = np.concatenate([np.diff(np.flatnonzero(h)) - 1 for h in hits])
+    G = 12
+    obs = np.array([np.sum(gaps == g) for g in range(G)] + [np.sum(gaps >= G)])
+    # the gap law conditioned on the next hit falling inside the 64 genes is
+    # not exactly geometric; compare with the same statistic simulated with
+    # one independent Bernoulli(p) per gene
+    rng = np.random.default_rng(1)
+    sim = rng.random((20 * n, L * K)) < p
+    sg = np.concatenate([np.diff(np.flatnonzero(h)) - 1 for h in sim])
+    ref = np.array([np.sum(sg == g) for g in range(G)] + [np.sum(sg >= G)], dtype=float)
+    ref = ref / ref.sum() * obs.sum()
+    chi = ((obs - ref) ** 2 / ref).sum()
+    assert stats.chi2.sf(chi, G) > 1e-3
+    # the geometric head of the law: P(gap = 0) / P(gap = 1) = 1 / (1 - p)
+    assert abs(obs[0] / obs[1] - 1 / (1 - p)) < 0.1
+    # neighbouring genes independent
+    a, b = hits[:, :-1].reshape(-1), hits[:, 1:].reshape(-1)
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.02
