@@ -166,33 +166,6 @@ __device__ __forceinline__ void copy_elites(const uint8_t *__restrict__ pin,
   }
 }
 
-// Mutation codes of genes 4b .. 4b+3 of the child in slot `slot` as one
-// little-endian word: byte u = kp + 1 when gene i = 4b + u (cell j = i / K,
-// user k = i % K) mutates and swaps with user kp of its row, 0 otherwise (and
-// 0 past the chromosome's LK genes).  The decision of gene i is word i of the
-// MUT_DECIDE stream, its partner word i of the MUT_PARTNER stream.  Both
-// Philox blocks are drawn unconditionally, as two independent dependence
-// chains the scheduler can overlap (a wave almost always has a lane that needs
-// the partner block anyway).
-__device__ __forceinline__ uint32_t mutation_codes(int b, int LK, int K, const DevGa &ga,
-                                                   uint32_t gen, uint32_t slot) {
-  const Stream dec{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutDecide};
-  const Stream par{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutPartner};
-  const Words4 w = dec.block((uint32_t)b);
-  const Words4 pw = par.block((uint32_t)b);
-  uint32_t out = 0u;
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int i = 4 * b + u;
-    if (hit(pick(w, (uint32_t)u), ga.thr_mut) && i < LK) {
-      const int k = i % K;
-      const uint32_t r = bounded(pick(pw, (uint32_t)u), (uint32_t)(K - 1));
-      out |= (uint32_t)((int)r + ((int)r >= k ? 1 : 0) + 1) << (8 * u);
-    }
-  }
-  return out;
-}
-
 // Stores the code word of genes 4b .. 4b+3 of a child whose codes start at
 // `dst` (byte-aligned when LK is not a multiple of 4).
 __device__ __forceinline__ void store_code_word(uint8_t *codes, int LK, int b, uint32_t v) {
@@ -205,25 +178,156 @@ __device__ __forceinline__ void store_code_word(uint8_t *codes, int LK, int b, u
   }
 }
 
+// Mutation codes of group q (genes 32q .. 32q+31, row-major i = j*K + k) of
+// the child in `slot`: byte code[b] = k' + 1 when gene 32q + b mutates and
+// swaps with user k' of its cell, 0 otherwise (in out[b / 4], byte b % 4).
+// The decision word of gene 32q + b has as its bit 31 - k the bit b of word
+// 32q + k of the MUT_DECIDE stream, and the gene mutates when that word is
+// below thr: the comparison runs from the most significant bit, one stream
+// word (one bit of every gene of the group) at a time -- where thr's bit is 1
+// a 0 bit decides "below", where it is 0 a 1 bit decides "not below" -- and
+// stops drawing Philox blocks once every gene is decided.  The h-th mutating
+// gene takes its partner from word 32q + h of the MUT_PARTNER stream.
+__device__ __forceinline__ void group_codes(int q, int LK, int K, const DevGa &ga, uint32_t gen,
+                                            uint32_t slot, uint32_t (&out)[8]) {
+#pragma unroll
+  for (int w = 0; w < 8; ++w) out[w] = 0u;
+  const int g0 = 32 * q;
+  const int n = LK - g0 < 32 ? LK - g0 : 32;
+  const uint32_t valid = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+  uint32_t hitm = 0u;
+  if (ga.thr_mut >= (1ull << 32)) {
+    hitm = valid;
+  } else {
+    const uint32_t th = (uint32_t)ga.thr_mut;
+    const Stream dec{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutDecide};
+    uint32_t und = valid;
+    for (int k4 = 0; k4 < 8 && und != 0u; ++k4) {
+      const Words4 wb = dec.block((uint32_t)(8 * q + k4));
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t R = pick(wb, (uint32_t)u);
+        if ((th >> (31 - (4 * k4 + u))) & 1u) {
+          hitm |= und & ~R;
+          und &= R;
+        } else {
+          und &= ~R;
+        }
+      }
+    }
+  }
+  if (hitm == 0u) return;
+  const Stream par{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutPartner};
+  Words4 pw{0u, 0u, 0u, 0u};
+  int h = 0;
+  while (hitm != 0u) {
+    const int b = __builtin_ctz(hitm);
+    hitm &= hitm - 1u;
+    if ((h & 3) == 0) pw = par.block((uint32_t)(8 * q + (h >> 2)));
+    const int k = (g0 + b) % K;
+    const uint32_t r = bounded(pick(pw, (uint32_t)(h & 3)), (uint32_t)(K - 1));
+    const uint32_t code = r + ((int)r >= k ? 1u : 0u) + 1u;
+    // b is lane-varying: select the word without dynamic register indexing
+#pragma unroll
+    for (int w = 0; w < 8; ++w)
+      if ((b >> 2) == w) out[w] |= code << (8 * (b & 3));
+    ++h;
+  }
+}
+
+// The latency form of group_codes: eight lanes (u = 0..7, consecutive lanes
+// of one wave) per group, lane u drawing the decision block 8q + u (bits 4u ..
+// 4u+3 of every gene's word, most significant first) at once.  Each lane
+// compares its four bits ("below", "equal so far" masks), the lanes combine
+// in order of significance (a more significant segment decides unless it is
+// equal: below = below_a | (equal_a & below_b), equal = equal_a & equal_b) with
+// three shuffle steps, and lane u writes the codes of genes 4u .. 4u+3 (their
+// partner words by hit rank, as in group_codes).  Same codes as group_codes;
+// more Philox blocks (all eight), far shorter dependence chains.  Every lane
+// of the wave must call it (inactive ones with act = false).
+__device__ __forceinline__ uint32_t group_codes_x8(bool act, int q, int u, int LK, int K,
+                                                   const DevGa &ga, uint32_t gen, uint32_t slot) {
+  const int g0 = 32 * q;
+  const int n = LK - g0 < 32 ? (LK - g0 < 0 ? 0 : LK - g0) : 32;
+  const uint32_t valid = n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+  uint32_t lt = 0u, eq = valid;
+  const bool all = ga.thr_mut >= (1ull << 32);
+  if (act && !all) {
+    const uint32_t th = (uint32_t)ga.thr_mut;
+    const Stream dec{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutDecide};
+    const Words4 wb = dec.block((uint32_t)(8 * q + u));
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const uint32_t R = pick(wb, (uint32_t)v);
+      if ((th >> (31 - (4 * u + v))) & 1u) {
+        lt |= eq & ~R;
+        eq &= R;
+      } else {
+        eq &= ~R;
+      }
+    }
+  }
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+#pragma unroll
+  for (int st = 1; st < 8; st <<= 1) {
+    const bool has = u + st < 8;
+    const uint32_t lt2 = (uint32_t)__shfl((int)lt, has ? lane + st : lane);
+    const uint32_t eq2 = (uint32_t)__shfl((int)eq, has ? lane + st : lane);
+    if (has) {
+      lt = lt | (eq & lt2);
+      eq = eq & eq2;
+    }
+  }
+  uint32_t hitm = (uint32_t)__shfl((int)lt, lane - u);  // the group's lane 0 holds all bits
+  if (all) hitm = valid;
+  if (!act) return 0u;
+  uint32_t out = 0u;
+  const uint32_t mine = hitm & (0xFu << (4 * u));
+  if (mine != 0u) {
+    const Stream par{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutPartner};
+    int hb = -1;
+    Words4 pw{0u, 0u, 0u, 0u};
+    for (uint32_t m = mine; m != 0u; m &= m - 1u) {
+      const int b = __builtin_ctz(m);
+      const int h = __builtin_popcount(hitm & ((1u << b) - 1u));
+      if ((h >> 2) != hb) {
+        hb = h >> 2;
+        pw = par.block((uint32_t)(8 * q + hb));
+      }
+      const int k = (g0 + b) % K;
+      const uint32_t r = bounded(pick(pw, (uint32_t)(h & 3)), (uint32_t)(K - 1));
+      out |= (r + ((int)r >= k ? 1u : 0u) + 1u) << (8 * (b & 3));
+    }
+  }
+  return out;
+}
+
 // Mutation codes of the children of slots [s0, s0 + nc) into `codes` (child c
-// at byte c*LK) with the whole workgroup, two (child, Philox block) pairs per
-// thread and step, their four Philox blocks drawn together.  No barrier: the
-// caller's next one publishes the codes.
+// at byte c*LK) with the whole workgroup: one thread per (child, group of 32
+// genes) when there are more groups than an eighth of the workgroup (the
+// early-stopping group_codes), else eight lanes per group (group_codes_x8).
+// No barrier: the caller's next one publishes the codes.
 __device__ __forceinline__ void mutation_codes_block(uint8_t *codes, int nc, int LK, int K,
                                                      const DevGa &ga, uint32_t gen, int s0,
                                                      int block) {
-  const int nb = (LK + 3) >> 2;
-  const int total = nc * nb;
-  for (int i = threadIdx.x; i < total; i += 2 * block) {
-    const int i2 = i + block;
-    const bool two = i2 < total;
-    const int j2 = two ? i2 : i;  // a valid pair to draw for (not stored)
-    const int c = i / nb, b = i - c * nb;
-    const int c2 = j2 / nb, b2 = j2 - c2 * nb;
-    const uint32_t v = mutation_codes(b, LK, K, ga, gen, (uint32_t)(s0 + c));
-    const uint32_t v2 = mutation_codes(b2, LK, K, ga, gen, (uint32_t)(s0 + c2));
-    store_code_word(codes + c * LK, LK, b, v);
-    if (two) store_code_word(codes + c2 * LK, LK, b2, v2);
+  const int ng = (LK + 31) >> 5;
+  const int total = nc * ng;
+  if (8 * total <= block) {
+    const int t = (int)threadIdx.x >> 3, u = (int)threadIdx.x & 7;
+    const bool act = t < total;
+    const int c = act ? t / ng : 0, q = act ? t - c * ng : 0;
+    const uint32_t v = group_codes_x8(act, q, u, LK, K, ga, gen, (uint32_t)(s0 + c));
+    if (act && 32 * q + 4 * u < LK) store_code_word(codes + (size_t)c * LK, LK, 8 * q + u, v);
+    return;
+  }
+  for (int t = threadIdx.x; t < total; t += block) {
+    const int c = t / ng, q = t - c * ng;
+    uint32_t out[8];
+    group_codes(q, LK, K, ga, gen, (uint32_t)(s0 + c), out);
+    uint8_t *dst = codes + (size_t)c * LK;
+#pragma unroll
+    for (int w = 0; w < 8; ++w)
+      if (32 * q + 4 * w < LK) store_code_word(dst, LK, 8 * q + w, out[w]);
   }
 }
 
