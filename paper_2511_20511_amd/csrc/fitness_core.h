@@ -598,6 +598,96 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
   return acc;
 }
 
+// Global-to-LDS copy without registers (global_load_lds): one wave
+// instruction moves 64 x SIZE bytes from per-lane global addresses into LDS at
+// a wave-uniform base + lane x SIZE (lanes switched off write nothing).  The
+// data is in LDS once the wave's vector-memory counter has drained.
+template <int SIZE>
+__device__ __forceinline__ void lds_dma(const void *gsrc, void *lds_base) {
+  static_assert(SIZE == 4 || SIZE == 16, "4 or 16 bytes per lane");
+  const auto g = (const __attribute__((address_space(1))) void *)gsrc;
+  const auto l = (__attribute__((address_space(3))) void *)lds_base;
+  if constexpr (SIZE == 16)
+    __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+}
+__device__ __forceinline__ void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// BS rows [r0, r0 + TR) of the zero-diagonal table (and T1) into the tile
+// layout T[j][lr][..] of load_tile, by global_load_lds, 16 bytes per lane
+// (a row past the table's last is read clamped and lands in tile rows that are
+// never used).  Issues only: wait_vmem() and a barrier publish the tile.
+template <int LT, int TPT, int MODE, int TR>
+__device__ __forceinline__ void dma_tile(const float *__restrict__ T2z,
+                                         const float *__restrict__ T1, int r0, float *sT) {
+  constexpr int HALF = TPT * 4;                      // one table row (bytes)
+  constexpr int ROWB = HALF * (MODE == 1 ? 2 : 1);   // one tile row
+  constexpr int CELLB = TR * ROWB;
+  constexpr int TOTAL = LT * CELLB;
+  constexpr int CHUNKS = (TOTAL + 1023) / 1024;
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int nw = (int)(blockDim.x >> 6);
+  char *base = reinterpret_cast<char *>(sT);
+  for (int k = wave; k < CHUNKS; k += nw) {
+    const int o = k * 1024 + lane * 16;
+    if (o < TOTAL) {
+      const int j = o / CELLB, rem = o - j * CELLB;
+      const int lr = rem / ROWB, pb = rem - lr * ROWB;
+      const int l = min(r0 + lr, LT - 1);
+      const float *tab = (MODE == 1 && pb >= HALF) ? T1 : T2z;
+      const int off = (MODE == 1 && pb >= HALF) ? pb - HALF : pb;
+      const char *src = reinterpret_cast<const char *>(tab) + ((size_t)(j * LT + l) * TPT) * 4 + off;
+      lds_dma<16>(src, base + __builtin_amdgcn_readfirstlane(k) * 1024);
+    }
+  }
+}
+
+// lane_sum_tiled whose last visit's tile comes in by dma_tile, with hooks:
+// hook.before_load() runs before the barrier that precedes that load (all
+// threads), hook.issue() after it and before the tile's loads are issued (its
+// own global_load_lds traffic is then in flight with the tile's); the barrier
+// after the tile waits for both.  Same sum, same bits as lane_sum_tiled.
+template <int LT, int TPT, int MODE, int TR, class Hook>
+__device__ __forceinline__ float lane_sum_tiled_hook(const uint8_t *ip, bool active, float *sT,
+                                                     const float *sOwn,
+                                                     const float *__restrict__ T2z,
+                                                     const float *__restrict__ T1,
+                                                     const float *__restrict__ lconst, int &held,
+                                                     bool mn, Hook &hook) {
+  constexpr int NT = (LT + TR - 1) / TR;
+  static_assert(NT >= 2, "tiled sums hold more than one tile");
+  uint32_t A[LT];
+  tiled_offsets<LT, TPT, MODE, TR>(ip, active, A);
+  float acc = obj_init(mn);
+  float hold[LT - TR];
+  const bool down = held == NT - 1;
+#pragma unroll 1
+  for (int v = 0; v < NT; ++v) {
+    const int t = down ? NT - 1 - v : v;
+    if (v != 0 || held != t) {
+      const bool last = v == NT - 1;
+      if (last) hook.before_load();
+      __syncthreads();
+      if (last) hook.issue();
+      dma_tile<LT, TPT, MODE, TR>(T2z, T1, t * TR, sT);
+      wait_vmem();
+      __syncthreads();
+    }
+    tiled_visit<LT, TPT, MODE, TR, 0>(t, A, ip, active, sT, sOwn, lconst, acc, hold, mn);
+  }
+#pragma unroll
+  for (int l = TR; l < LT; ++l) acc = obj_add(acc, hold[l - TR], mn);
+  held = down ? 0 : NT - 1;
+  return acc;
+}
+
+// No work around the tile loads.
+struct NoTileHook {
+  __device__ __forceinline__ void before_load() {}
+  __device__ __forceinline__ void issue() {}
+};
+
 // Copies the own-cell squares T2[l][l][.] of every BS row into LDS as
 // sOwn[l][p] (L x TP floats).
 __device__ __forceinline__ void load_own(const float *__restrict__ Town, int L, int TP, float *sOwn) {

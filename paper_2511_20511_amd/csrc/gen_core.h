@@ -463,11 +463,257 @@ __device__ __forceinline__ void gen_tasks_exact(const GenInst *insts, const GenT
   }
 }
 
+// ---- batch form with tiled tables: the next child task prepared during the
+// current one's gathers
+//
+// A child task's preparation is latency: the tournament candidates' fitness,
+// the parents' rows (global memory) and the mutation draws (Philox chains).
+// When the next task of a workgroup's run is a child task of the same
+// instance, these move into the current task's lane sum: its SELECT words and
+// candidate fitness loads are issued before the first tile's gathers, the
+// tournaments are resolved and the children's source rows (one parent row
+// each: the crossover cuts between rows) fetched into sChild around the load
+// of the last tile, and the mutation codes drawn after the last tile's
+// gathers.  The task then starts with its rows in LDS: swaps, write-out and
+// inverse rows.  Same draws, same children, same bits.  With K = 32 a row is
+// one group of 32 genes, and the row's thread draws its codes itself
+// (group_codes), with no code buffer.
+
+// Selection of one child (thread c < nc of the task): the pair's SELECT words
+// and the four candidates' fitness, in registers.
+struct SelRegs {
+  uint32_t u0, v0, u1, v1, w4, w5;
+  float f0, f1, f2, f3;
+};
+
+__device__ __forceinline__ SelRegs sel_issue(const GenInst &I, const GenTask &task, int gen) {
+  SelRegs r{0u, 0u, 0u, 0u, 0u, 0u, 0.0f, 0.0f, 0.0f, 0.0f};
+  const int nc = task.s1 - task.s0;
+  const int tid = threadIdx.x;
+  if (tid < nc) {
+    const int slot = task.s0 + tid;
+    const int pair_a = I.E + ((slot - I.E) & ~1);
+    const Stream st{I.ga.seed_lo, I.ga.seed_hi, (uint32_t)pair_a, (uint32_t)gen,
+                    I.ga.instance_id, kTagSelect};
+    const Words4 b0 = st.block(0u), b1 = st.block(1u);
+    const uint32_t N = (uint32_t)I.N;
+    r.u0 = bounded(b0.x, N);
+    r.v0 = bounded(b0.y, N);
+    r.u1 = bounded(b0.z, N);
+    r.v1 = bounded(b0.w, N);
+    r.w4 = b1.x;
+    r.w5 = b1.y;
+    const float *fin = fit_buf(I, gen & 1);
+    r.f0 = gp(fin)[r.u0];
+    r.f1 = gp(fin)[r.v0];
+    r.f2 = gp(fin)[r.u1];
+    r.f3 = gp(fin)[r.v1];
+  }
+  return r;
+}
+
+// Tournaments, crossover decision and cut of thread c's child into sSel (as
+// build_children_block leaves them).  No barrier.
+__device__ __forceinline__ void sel_resolve(const GenInst &I, const GenTask &task,
+                                            const SelRegs &r, int32_t *sSel) {
+  const int nc = task.s1 - task.s0;
+  const int tid = threadIdx.x;
+  if (tid < nc) {
+    const int slot = task.s0 + tid;
+    const bool second = ((slot - I.E) & 1) != 0;
+    const uint32_t p1 = beats(rank_key(r.f1), r.v0, rank_key(r.f0), r.u0) ? r.v0 : r.u0;
+    const uint32_t p2 = beats(rank_key(r.f3), r.v1, rank_key(r.f2), r.u1) ? r.v1 : r.u1;
+    const bool cross = I.L >= 2 && hit(r.w4, I.ga.thr_cross);
+    const int cut = cross ? 1 + (int)bounded(r.w5, (uint32_t)(I.L - 1)) : I.L;
+    const uint32_t first = second ? p2 : p1, rest = second ? p1 : p2;
+    sSel[2 * tid] = (int32_t)(first | (rest << 16));
+    sSel[2 * tid + 1] = cut * I.K;
+  }
+}
+
+// The source rows of a task's children into sChild (row (c, j) from the
+// first parent when j < cut, else from the second; K % 4 == 0, K <= 32) by
+// global_load_lds: 16 bytes per lane when K % 16 == 0, else 4.  Issues only:
+// wait_vmem() and a barrier publish the rows.
+__device__ __forceinline__ void dma_rows(const GenInst &I, const GenTask &task, int gen,
+                                         const int32_t *sSel, uint8_t *sChild) {
+  const int L = I.L, K = I.K, LK = L * K;
+  const int total = (task.s1 - task.s0) * LK;
+  const uint8_t *pin = pop_buf(I, gen & 1);
+  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int nw = (int)(blockDim.x >> 6);
+  const bool wide = (K & 15) == 0;
+  const int span = wide ? 1024 : 256;
+  const int chunks = (total + span - 1) / span;
+  for (int k = wave; k < chunks; k += nw) {
+    const int o = k * span + lane * (wide ? 16 : 4);
+    if (o < total) {
+      const int q = o / K, w = o - q * K;
+      const int c = q / L, j = q - c * L;
+      const uint32_t pr = (uint32_t)sSel[2 * c];
+      const uint32_t par = j * K < sSel[2 * c + 1] ? (pr & 0xFFFFu) : (pr >> 16);
+      const uint8_t *src = pin + (size_t)par * LK + j * K + w;
+      uint8_t *dst = sChild + (size_t)__builtin_amdgcn_readfirstlane(k) * span;
+      if (wide)
+        lds_dma<16>(src, dst);
+      else
+        lds_dma<4>(src, dst);
+    }
+  }
+}
+
+// The children of a task from their source rows in sChild: each row's swaps
+// (codes from sCode, or with K = 32 drawn here), its write-out and its inverse
+// entries.  Ends with a barrier.
+__device__ __forceinline__ void rows_finish(const GenInst &I, const GenTask &task, int gen,
+                                            uint8_t *sChild, const uint8_t *sCode, uint8_t *sInv,
+                                            int block) {
+  const int L = I.L, K = I.K, LK = L * K, nw = K >> 2;
+  const int nc = task.s1 - task.s0, rows = nc * L;
+  const bool mutate = K >= 2 && I.ga.thr_mut != 0;
+  uint8_t *pout = pop_buf(I, gen < 0 ? 0 : 1 - (gen & 1)) + (size_t)task.s0 * LK;
+  for (int q = threadIdx.x; q < rows; q += block) {
+    const int c = q / L, j = q - c * L;
+    uint8_t *rowb = sChild + q * K;
+    if (mutate) {
+      if (K == 32) {
+        uint32_t code[8];
+        group_codes(j, LK, K, I.ga, (uint32_t)gen, (uint32_t)(task.s0 + c), code);
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int cd = (int)((code[w] >> (8 * b)) & 0xFFu);
+            if (cd != 0) {
+              const int k = 4 * w + b;
+              const uint8_t t = rowb[k];
+              rowb[k] = rowb[cd - 1];
+              rowb[cd - 1] = t;
+            }
+          }
+        }
+      } else {
+        apply_swaps(rowb, sCode + q * K, q * K, K);
+      }
+    }
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(rowb);
+    gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)q * K));
+    uint8_t *dst = sInv + c * K * L + j;
+    for (int w = 0; w < nw; ++w) {
+      const uint32_t x = row[w];
+      gw[w] = x;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int t = (int)((x >> (8 * b)) & 0xFFu);
+        if (t < K) dst[t * L] = (uint8_t)(4 * w + b);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Whether the children of a task can be built by this path (rows whole
+// aligned words) and whether it draws the K = 32 codes in the row pass.
+__device__ __forceinline__ bool rows_path(const GenInst &I) { return (I.K & 3) == 0 && I.K <= 32; }
+
+// Hook around the last tile load of the current task: resolves the next
+// task's tournaments, then fetches its source rows along with the tile.
+struct PrepHook {
+  const GenInst *I;
+  const GenTask *next;
+  int gen;
+  const SelRegs *sel;
+  int32_t *sSel;
+  uint8_t *sChild;
+  __device__ __forceinline__ void before_load() { sel_resolve(*I, *next, *sel, sSel); }
+  __device__ __forceinline__ void issue() { dma_rows(*I, *next, gen, sSel, sChild); }
+};
+
+template <int LT, int TPT, int MODE, int BLOCK>
+__device__ __forceinline__ void gen_tasks_tiled(const GenInst *insts, const GenTask *tasks,
+                                                int t0, int t1, int gen_arg, unsigned char *smem,
+                                                const int32_t *gens) {
+  using P = GenPlan<LT, TPT, MODE, BLOCK>;
+  constexpr int TR = P::kTileRows;
+  float *sT = reinterpret_cast<float *>(smem);
+  uint8_t *sChild = smem + P::kChildOff;
+  uint8_t *sInv = smem + P::kInvOff;
+  float *sE = reinterpret_cast<float *>(smem + P::kEOff);
+  float *sOwn = reinterpret_cast<float *>(smem + P::kOwnOff);
+  int32_t *sSel = reinterpret_cast<int32_t *>(smem + P::kSelOff);
+  uint8_t *sCode = smem + P::kCodeOff;
+  LdsState st;
+  bool ready = false;  // this task's source rows are in sChild (and its codes in sCode)
+  GenTask task = t0 < t1 ? load_task(tasks, t0) : GenTask{0, kTaskElite, 0, 0};
+  for (int t = t0; t < t1; ++t) {
+    const GenInst I = insts[task.inst];
+    const int g = gens ? gp(gens)[task.inst] : gen_arg;
+    const GenTask next = t + 1 < t1 ? load_task(tasks, t + 1) : GenTask{0, kTaskElite, 0, 0};
+    const bool child = task.kind == kTaskChild && g >= 0 && g < I.G && rows_path(I);
+    if (!child) {
+      run_task<LT, TPT, MODE, BLOCK>(I, task, g, smem, st, false);
+      ready = false;
+      task = next;
+      continue;
+    }
+    if (task.inst != st.inst) {
+      load_own(I.Town, LT, TPT, sOwn);
+      st.inst = task.inst;
+      st.tile = -1;
+    }
+    const int nc = task.s1 - task.s0;
+    const bool mutate = I.K >= 2 && I.ga.thr_mut != 0;
+    if (!ready) {
+      // cold start: this task's selection, codes and rows now
+      const SelRegs r = sel_issue(I, task, g);
+      if (mutate && I.K != 32)
+        mutation_codes_block(sCode, nc, I.L * I.K, I.K, I.ga, (uint32_t)g, task.s0, BLOCK);
+      sel_resolve(I, task, r, sSel);
+      __syncthreads();
+      dma_rows(I, task, g, sSel, sChild);
+      wait_vmem();
+      __syncthreads();
+    }
+    rows_finish(I, task, g, sChild, sCode, sInv, BLOCK);
+    // the next task is prepared inside this one's lane sum when it is a child
+    // task of the same instance at the same generation
+    const bool pipe = next.kind == kTaskChild && next.inst == task.inst;
+    const int q = threadIdx.x;
+    const bool active = q / I.K < nc;
+    float acc;
+    if (pipe) {
+      const SelRegs r = sel_issue(I, next, g);
+      PrepHook hook{&I, &next, g, &r, sSel, sChild};
+      acc = lane_sum_tiled_hook<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z,
+                                                   I.T1, I.lconst, st.tile, I.objective != 0,
+                                                   hook);
+      if (mutate && I.K != 32)
+        mutation_codes_block(sCode, next.s1 - next.s0, I.L * I.K, I.K, I.ga, (uint32_t)g,
+                             next.s0, BLOCK);
+    } else {
+      NoTileHook hook;
+      acc = lane_sum_tiled_hook<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z,
+                                                   I.T1, I.lconst, st.tile, I.objective != 0,
+                                                   hook);
+    }
+    float *const fit_out = fit_buf(I, 1 - (g & 1)) + task.s0;
+    reduce_round(sE, acc, active, nc, I.K, I.prelog, fit_out, I.objective != 0);
+    ready = pipe;
+    task = next;
+  }
+}
+
 template <int LT, int TPT, int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   int t0, t1;
   task_range(a.ntasks, t0, t1);
+  if constexpr (GenPlan<LT, TPT, MODE, BLOCK>::kTiles > 1) {
+    if (a.gen >= 0 || a.gens) {
+      gen_tasks_tiled<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, a.gens);
+      return;
+    }
+  }
   LdsState st;
   gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, st, a.gens);
 }
