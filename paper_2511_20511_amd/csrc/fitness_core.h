@@ -510,10 +510,11 @@ __device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip
     const float se = tiled_row_se<LT, TPT, MODE>(A, ip, active, lds, sOwn, lconst, l, lr, mn);
     const float next = obj_add(acc, se, mn);
     acc = lr < rows ? next : acc;
-    // the gathers of rows lr + 2, lr + 3 wait for the sum up to this row (two
-    // rows in flight): without this the compiler hoists every row's loads to
-    // the top of the tile and spills
-    if (lr % 2 == 1) {
+    // the gathers of rows lr + 1 .. lr + 4 wait for the sum up to this row
+    // (four rows in flight; one, two, three, six and eight measured slower):
+    // without this the compiler hoists every row's loads to the top of the
+    // tile and spills
+    if (lr % 4 == 3) {
 #pragma unroll
       for (int j = 0; j < LT; ++j) asm volatile("" : "+v"(A[j]) : "v"(acc));
     }
@@ -536,7 +537,7 @@ __device__ __forceinline__ void tiled_terms(uint32_t (&A)[LT], const uint8_t *ip
     const int l = T * TR + lr;
     const float se = tiled_row_se<LT, TPT, MODE>(A, ip, active, lds, sOwn, lconst, l, lr, mn);
     hold[l - TR] = se;
-    if (lr % 2 == 1) {  // two rows in flight, as in tiled_rows
+    if (lr % 4 == 3) {  // four rows in flight, as in tiled_rows
 #pragma unroll
       for (int j = 0; j < LT; ++j) asm volatile("" : "+v"(A[j]) : "v"(se));
     }
