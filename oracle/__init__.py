@@ -74,12 +74,19 @@ def lib():
         L.pao_init_pop.argtypes = [i32, i32, i32, f64, f64, u64, u32, u8p, u8p]
         L.pao_ga_step.argtypes = [i32, i32, i32, i32, f64, f64, u64, u32, u32, u8p, f64p, u8p]
         L.pao_mutation_codes.argtypes = [i32, i32, f64, u64, u32, u32, u32, u8p]
+        L.pao_pop_kmeans.argtypes = [i32, i32, i32, i32, u8p, f64p, i32, i32p, u8p, i32p]
+        L.pao_island_step.argtypes = [i32, i32, i32, i32, i32, i32p, f64, f64, u64, u32, u32,
+                                      u8p, f64p, u8p]
+        L.pao_island_solve.argtypes = [i32, i32, i32, i32, f64, f64, f64p, f64p, f64p, i32, i32,
+                                       i32, f64, f64, f64, f64, u64, u32, i32, i32, i32, u8p,
+                                       f64p, f64p, u8p, i32p]
         L.pao_solve.argtypes = [i32, i32, i32, i32, f64, f64, f64p, f64p, f64p, i32, i32, i32,
                                 f64, f64, f64, f64, u64, u32, u8p, f64p, f64p, u8p]
         L.pao_bruteforce.argtypes = [i32, i32, i32, i32, f64, f64, f64p, u8p, f64p, i64p]
         for name in ("pao_fitness", "pao_fitness_obj", "pao_se_terms", "pao_rank", "pao_kmeans_seed",
                      "pao_init_pop", "pao_ga_step", "pao_solve", "pao_bruteforce",
-                     "pao_mutation_codes"):
+                     "pao_mutation_codes", "pao_pop_kmeans", "pao_island_step",
+                     "pao_island_solve"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -221,6 +228,60 @@ def solve(beta, user_xy, bs_xy, N, gens, E, p_cross, p_mut, kmeans_frac, p_init,
     if want_pop:
         return best, float(bf[0]), trace, fpop
     return best, float(bf[0]), trace
+
+
+def pop_kmeans(pop, fit, C, max_iters=20):
+    """K-means of a population into C islands (PK-means GA, Alg. 2): (labels [N],
+    centroids [C][L][K], iterations)."""
+    pop = np.ascontiguousarray(pop, dtype=np.uint8)
+    N, L, K = pop.shape
+    fit = np.ascontiguousarray(fit, dtype=np.float64)
+    labels = np.zeros(N, dtype=np.int32)
+    cent = np.zeros((C, L, K), dtype=np.uint8)
+    it = np.zeros(1, dtype=np.int32)
+    rc = lib().pao_pop_kmeans(L, K, N, C, _p(pop, ctypes.c_uint8), _p(fit, ctypes.c_double),
+                              max_iters, _p(labels, ctypes.c_int32), _p(cent, ctypes.c_uint8),
+                              _p(it, ctypes.c_int32))
+    _check(rc, "pop_kmeans")
+    return labels, cent, int(it[0])
+
+
+def island_step(pop, fit, labels, C, E, p_cross, p_mut, seed, instance_id, gen):
+    """One generation of every island (Alg. 2 loop body) for the given partition."""
+    pop = np.ascontiguousarray(pop, dtype=np.uint8)
+    N, L, K = pop.shape
+    fit = np.ascontiguousarray(fit, dtype=np.float64)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    out = np.zeros_like(pop)
+    rc = lib().pao_island_step(L, K, N, E, C, _p(labels, ctypes.c_int32), p_cross, p_mut,
+                               int(seed) & ((1 << 64) - 1), instance_id & 0xFFFFFFFF,
+                               gen & 0xFFFFFFFF, _p(pop, ctypes.c_uint8),
+                               _p(fit, ctypes.c_double), _p(out, ctypes.c_uint8))
+    _check(rc, "island_step")
+    return out
+
+
+def island_solve(beta, user_xy, bs_xy, N, gens, E, p_cross, p_mut, kmeans_frac, p_init, seed,
+                 instance_id, C, recluster_every, max_iters=20, T=0, se_mode=SE_ASYMPTOTIC,
+                 M=1, rho=1.0):
+    """PK-means GA (Alg. 2): (best, best_fit, trace, final_pop, final_labels)."""
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    L, _, K = beta.shape
+    ux = None if user_xy is None else np.ascontiguousarray(user_xy, dtype=np.float64)
+    bx = None if bs_xy is None else np.ascontiguousarray(bs_xy, dtype=np.float64)
+    best = np.zeros((L, K), dtype=np.uint8)
+    bf = np.zeros(1, dtype=np.float64)
+    trace = np.zeros(gens + 1, dtype=np.float64)
+    fpop = np.zeros((N, L, K), dtype=np.uint8)
+    flab = np.zeros(N, dtype=np.int32)
+    rc = lib().pao_island_solve(L, K, T, se_mode, M, rho, _p(beta, ctypes.c_double),
+                                _p(ux, ctypes.c_double), _p(bx, ctypes.c_double), N, gens, E,
+                                p_cross, p_mut, kmeans_frac, p_init, seed, instance_id, C,
+                                recluster_every, max_iters, _p(best, ctypes.c_uint8),
+                                _p(bf, ctypes.c_double), _p(trace, ctypes.c_double),
+                                _p(fpop, ctypes.c_uint8), _p(flab, ctypes.c_int32))
+    _check(rc, "island_solve")
+    return best, float(bf[0]), trace, fpop, flab
 
 
 def bruteforce(beta, T=0, se_mode=SE_ASYMPTOTIC, M=1, rho=1.0):

@@ -376,8 +376,18 @@ static void swap_mutate(int L, int K, uint8_t *chrom, uint64_t thr, uint64_t see
  * partner from word 32q + h of the MUT_PARTNER stream: r = bounded(word,
  * K-1), partner k' = r + (r >= k).  codes[i] = k' + 1 for a mutating gene
  * i = j*K + k and 0 otherwise. */
+static int mutation_codes_off(int32_t L, int32_t K, double p_mut, uint64_t seed, uint32_t slot,
+                              uint32_t gen, uint32_t instance_id, uint32_t woff, uint8_t *codes);
 int pao_mutation_codes(int32_t L, int32_t K, double p_mut, uint64_t seed, uint32_t slot,
                        uint32_t gen, uint32_t instance_id, uint8_t *codes) {
+  return mutation_codes_off(L, K, p_mut, seed, slot, gen, instance_id, 0u, codes);
+}
+
+/* The same with every stream word index offset by woff (the island streams of
+ * the island GA below use woff = island << 18: block bits 16..23 of the
+ * counter). */
+static int mutation_codes_off(int32_t L, int32_t K, double p_mut, uint64_t seed, uint32_t slot,
+                              uint32_t gen, uint32_t instance_id, uint32_t woff, uint8_t *codes) {
   if (L < 1 || K < 1) return -1;
   const int LK = L * K;
   const uint64_t thr = pao_threshold(p_mut);
@@ -386,7 +396,8 @@ int pao_mutation_codes(int32_t L, int32_t K, double p_mut, uint64_t seed, uint32
   for (int q = 0; 32 * q < LK; ++q) {
     uint32_t R[32];
     for (int k = 0; k < 32; ++k)
-      R[k] = pao_word(seed, slot, gen, instance_id, PAO_TAG_MUT_DECIDE, (uint32_t)(32 * q + k));
+      R[k] = pao_word(seed, slot, gen, instance_id, PAO_TAG_MUT_DECIDE,
+                      woff + (uint32_t)(32 * q + k));
     int h = 0;
     for (int b = 0; b < 32 && 32 * q + b < LK; ++b) {
       uint32_t w = 0;
@@ -394,7 +405,7 @@ int pao_mutation_codes(int32_t L, int32_t K, double p_mut, uint64_t seed, uint32
       if ((uint64_t)w < thr) {
         const int i = 32 * q + b, k = i % K;
         uint32_t r = pao_bounded(pao_word(seed, slot, gen, instance_id, PAO_TAG_MUT_PARTNER,
-                                          (uint32_t)(32 * q + h)),
+                                          woff + (uint32_t)(32 * q + h)),
                                  (uint32_t)(K - 1));
         codes[i] = (uint8_t)((int)r + ((int)r >= k ? 1 : 0) + 1);
         ++h;
@@ -566,6 +577,225 @@ int pao_solve(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double
   if (final_pop) memcpy(final_pop, popA, G * N);
 out:
   free(popA); free(popB); free(fit); free(seed_chrom);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The parallel K-means GA (PK-means GA, Alg. 2, Sec. 4.3): the population is */
+/* partitioned by K-means into C clusters (islands) that evolve on their own;  */
+/* K-means is applied again every few generations (three in Sec. 6.1).  The   */
+/* paper fixes neither the feature space nor the per-island operators; the    */
+/* reading here:                                                              */
+/*  - a chromosome is the point (g_0, .., g_{LK-1}) of Z^{LK} (its pilot       */
+/*    indices), squared Euclidean distance in integers;                       */
+/*  - farthest-point start: centroid 0 is the best-ranked chromosome, centroid */
+/*    m the chromosome farthest from centroids 0..m-1 (distance to the nearest */
+/*    one; ties to the lowest index); then Lloyd iterations (assign to the     */
+/*    nearest centroid, ties to the lowest cluster; centroid = per-gene        */
+/*    rounded mean floor((2 s + n) / (2 n)); an empty cluster keeps its        */
+/*    centroid) until no label changes or max_iters;                          */
+/*  - island c holds the positions labelled c (increasing order) and keeps them*/
+/*    until the next clustering: its children take its positions;            */
+/*  - per island, the GA step of pao_ga_step restricted to the island: E_c =  */
+/*    0 if E = 0, else min(n_c, max(1, floor(E n_c / N + 1/2))) elites (the    */
+/*    island's best in rank order) in its first E_c positions; children in    */
+/*    pairs over the following positions (a, b consecutive positions of the   */
+/*    island), tournament candidates drawn among the island's members;       */
+/*  - the island's random streams are those of pao_ga_step (keyed by the      */
+/*    global slot of the pair's first child, or of the child) with the island */
+/*    index in bits 16..23 of the block counter, so with C = 1 the island GA   */
+/*    is the panmictic GA bit for bit.                                         */
+/* ------------------------------------------------------------------------ */
+
+static int64_t chrom_dist2(const uint8_t *a, const uint8_t *b, int n) {
+  int64_t d = 0;
+  for (int i = 0; i < n; ++i) {
+    int64_t t = (int64_t)a[i] - (int64_t)b[i];
+    d += t * t;
+  }
+  return d;
+}
+
+int pao_pop_kmeans(int32_t L, int32_t K, int32_t N, int32_t C, const uint8_t *pop,
+                   const double *fit, int32_t max_iters, int32_t *labels, uint8_t *centroids,
+                   int32_t *iters) {
+  if (L < 1 || K < 1 || N < 1 || C < 1 || C > N || max_iters < 1) return -1;
+  const int G = L * K;
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * N);
+  int64_t *sums = (int64_t *)malloc(sizeof(int64_t) * (size_t)C * G);
+  int32_t *cnt = (int32_t *)malloc(sizeof(int32_t) * C);
+  uint8_t *cent = (uint8_t *)malloc((size_t)C * G);
+  int rc = 0;
+  if (!order || !sums || !cnt || !cent) { rc = -2; goto done; }
+  pao_rank(fit, N, order);
+  memcpy(cent, pop + (size_t)order[0] * G, (size_t)G);
+  for (int m = 1; m < C; ++m) {
+    int far = 0;
+    int64_t far_d = -1;
+    for (int n = 0; n < N; ++n) {
+      int64_t dmin = -1;
+      for (int c = 0; c < m; ++c) {
+        int64_t d = chrom_dist2(pop + (size_t)n * G, cent + (size_t)c * G, G);
+        if (dmin < 0 || d < dmin) dmin = d;
+      }
+      if (dmin > far_d) { far_d = dmin; far = n; }
+    }
+    memcpy(cent + (size_t)m * G, pop + (size_t)far * G, (size_t)G);
+  }
+  for (int n = 0; n < N; ++n) labels[n] = -1;
+  int it = 0;
+  for (; it < max_iters; ++it) {
+    int changed = 0;
+    for (int n = 0; n < N; ++n) {
+      int best = 0;
+      int64_t bd = -1;
+      for (int c = 0; c < C; ++c) {
+        int64_t d = chrom_dist2(pop + (size_t)n * G, cent + (size_t)c * G, G);
+        if (bd < 0 || d < bd) { bd = d; best = c; }
+      }
+      if (labels[n] != best) { labels[n] = best; changed = 1; }
+    }
+    if (!changed) break;
+    memset(sums, 0, sizeof(int64_t) * (size_t)C * G);
+    memset(cnt, 0, sizeof(int32_t) * C);
+    for (int n = 0; n < N; ++n) {
+      ++cnt[labels[n]];
+      for (int i = 0; i < G; ++i) sums[(size_t)labels[n] * G + i] += pop[(size_t)n * G + i];
+    }
+    for (int c = 0; c < C; ++c) {
+      if (cnt[c] == 0) continue;
+      for (int i = 0; i < G; ++i) {
+        int64_t s2 = 2 * sums[(size_t)c * G + i] + cnt[c];
+        cent[(size_t)c * G + i] = (uint8_t)(s2 / (2 * (int64_t)cnt[c]));  /* s >= 0: floor */
+      }
+    }
+  }
+  if (centroids) memcpy(centroids, cent, (size_t)C * G);
+  if (iters) *iters = it;
+done:
+  free(order); free(sums); free(cnt); free(cent);
+  return rc;
+}
+
+static int island_elites(int E, int N, int n) {
+  if (E == 0 || n == 0) return 0;
+  int e = (int)((2 * (int64_t)E * n + N) / (2 * (int64_t)N));
+  if (e < 1) e = 1;
+  return e > n ? n : e;
+}
+
+int pao_island_step(int32_t L, int32_t K, int32_t N, int32_t E, int32_t C,
+                    const int32_t *labels, double p_cross, double p_mut, uint64_t seed,
+                    uint32_t instance_id, uint32_t gen, const uint8_t *pop_in,
+                    const double *fit_in, uint8_t *pop_out) {
+  if (L < 1 || K < 1 || N < 1 || E < 0 || E > N || C < 1 || C > 255) return -1;
+  const size_t G = (size_t)L * K;
+  int32_t *M = (int32_t *)malloc(sizeof(int32_t) * N);
+  double *sub = (double *)malloc(sizeof(double) * N);
+  int32_t *order = (int32_t *)malloc(sizeof(int32_t) * N);
+  uint8_t *codes = (uint8_t *)malloc(G);
+  if (!M || !sub || !order || !codes) { free(M); free(sub); free(order); free(codes); return -2; }
+  const uint64_t thr_c = pao_threshold(p_cross);
+  for (int c = 0; c < C; ++c) {
+    int n = 0;
+    for (int i = 0; i < N; ++i)
+      if (labels[i] == c) M[n++] = i;
+    if (n == 0) continue;
+    const uint32_t woff = (uint32_t)c << 18;
+    /* the island's members ranked: order[] indexes M[] */
+    for (int t = 0; t < n; ++t) sub[t] = fit_in[M[t]];
+    pao_rank(sub, n, order);
+    const int Ec = island_elites(E, N, n);
+    for (int e = 0; e < Ec; ++e)
+      memcpy(pop_out + (size_t)M[e] * G, pop_in + (size_t)M[order[e]] * G, G);
+    for (int t = Ec; t < n; t += 2) {
+      const int a = M[t];
+      const int has_b = t + 1 < n;
+      const int b = has_b ? M[t + 1] : -1;
+      uint32_t w[6];
+      for (int i = 0; i < 6; ++i)
+        w[i] = pao_word(seed, (uint32_t)a, gen, instance_id, PAO_TAG_SELECT, woff + (uint32_t)i);
+      int u0 = M[pao_bounded(w[0], (uint32_t)n)], v0 = M[pao_bounded(w[1], (uint32_t)n)];
+      int u1 = M[pao_bounded(w[2], (uint32_t)n)], v1 = M[pao_bounded(w[3], (uint32_t)n)];
+      int p1 = beats(fit_in, v0, u0) ? v0 : u0;
+      int p2 = beats(fit_in, v1, u1) ? v1 : u1;
+      uint8_t *ca = pop_out + (size_t)a * G;
+      uint8_t *cb = has_b ? pop_out + (size_t)b * G : NULL;
+      const uint8_t *P1 = pop_in + (size_t)p1 * G, *P2 = pop_in + (size_t)p2 * G;
+      if (L >= 2 && (uint64_t)w[4] < thr_c) {
+        int cut = 1 + (int)pao_bounded(w[5], (uint32_t)(L - 1));
+        for (int j = 0; j < L; ++j) {
+          memcpy(ca + j * K, ((j < cut) ? P1 : P2) + j * K, (size_t)K);
+          if (cb) memcpy(cb + j * K, ((j < cut) ? P2 : P1) + j * K, (size_t)K);
+        }
+      } else {
+        memcpy(ca, P1, G);
+        if (cb) memcpy(cb, P2, G);
+      }
+      mutation_codes_off(L, K, p_mut, seed, (uint32_t)a, gen, instance_id, woff, codes);
+      apply_codes(L, K, ca, codes);
+      if (cb) {
+        mutation_codes_off(L, K, p_mut, seed, (uint32_t)b, gen, instance_id, woff, codes);
+        apply_codes(L, K, cb, codes);
+      }
+    }
+  }
+  free(M); free(sub); free(order); free(codes);
+  return 0;
+}
+
+int pao_island_solve(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
+                     const double *beta, const double *user_xy, const double *bs_xy, int32_t N,
+                     int32_t gens, int32_t E, double p_cross, double p_mut, double kmeans_frac,
+                     double p_init, uint64_t seed, uint32_t instance_id, int32_t C,
+                     int32_t recluster_every, int32_t max_iters, uint8_t *best, double *best_fit,
+                     double *trace, uint8_t *final_pop, int32_t *final_labels) {
+  if (L < 1 || K < 1 || N < 1 || gens < 0 || E < 0 || E > N || C < 1 || C > N ||
+      recluster_every < 0)
+    return -1;
+  const size_t G = (size_t)L * K;
+  uint8_t *popA = (uint8_t *)malloc(G * N), *popB = (uint8_t *)malloc(G * N);
+  double *fit = (double *)malloc(sizeof(double) * N);
+  uint8_t *seed_chrom = (uint8_t *)malloc(G);
+  int32_t *labels = (int32_t *)calloc((size_t)N, sizeof(int32_t));
+  int rc = 0;
+  if (!popA || !popB || !fit || !seed_chrom || !labels) { rc = -2; goto out; }
+  if (kmeans_frac > 0.0) {
+    rc = pao_kmeans_seed(L, K, user_xy, bs_xy, seed_chrom, NULL, NULL, NULL);
+    if (rc) goto out;
+  }
+  rc = pao_init_pop(L, K, N, kmeans_frac, p_init, seed, instance_id,
+                    kmeans_frac > 0.0 ? seed_chrom : NULL, popA);
+  if (rc) goto out;
+  rc = pao_fitness(L, K, T, se_mode, M, rho, beta, popA, N, fit);
+  if (rc) goto out;
+  for (int g = 0; g < gens; ++g) {
+    if (trace) trace[g] = max_fit(fit, N);
+    /* Alg. 2: apply K-means (every recluster_every generations; 0 = only at
+       the start) */
+    if (C > 1 && (g == 0 || (recluster_every > 0 && g % recluster_every == 0))) {
+      rc = pao_pop_kmeans(L, K, N, C, popA, fit, max_iters, labels, NULL, NULL);
+      if (rc) goto out;
+    }
+    rc = pao_island_step(L, K, N, E, C, labels, p_cross, p_mut, seed, instance_id,
+                         (uint32_t)g, popA, fit, popB);
+    if (rc) goto out;
+    uint8_t *t = popA; popA = popB; popB = t;
+    rc = pao_fitness(L, K, T, se_mode, M, rho, beta, popA, N, fit);
+    if (rc) goto out;
+  }
+  if (trace) trace[gens] = max_fit(fit, N);
+  {
+    int b = 0;
+    for (int i = 1; i < N; ++i)
+      if (beats(fit, i, b)) b = i;
+    memcpy(best, popA + (size_t)b * G, G);
+    *best_fit = fit[b];
+  }
+  if (final_pop) memcpy(final_pop, popA, G * N);
+  if (final_labels) memcpy(final_labels, labels, sizeof(int32_t) * N);
+out:
+  free(popA); free(popB); free(fit); free(seed_chrom); free(labels);
   return rc;
 }
 

@@ -84,6 +84,25 @@ int pao_solve(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double
               int32_t gens, int32_t E, double p_cross, double p_mut, double kmeans_frac,
               double p_init, uint64_t seed, uint32_t instance_id, uint8_t *best,
               double *best_fit, double *trace, uint8_t *final_pop);
+/* Island GA (PK-means GA, Alg. 2): K-means of the population into C islands
+ * (chromosomes as points of Z^{LK}, farthest-point start from the best, at
+ * most max_iters Lloyd iterations), labels[N] and centroids[C][L*K]. */
+int pao_pop_kmeans(int32_t L, int32_t K, int32_t N, int32_t C, const uint8_t *pop,
+                   const double *fit, int32_t max_iters, int32_t *labels, uint8_t *centroids,
+                   int32_t *iters);
+/* One generation of every island (members = positions labelled c). */
+int pao_island_step(int32_t L, int32_t K, int32_t N, int32_t E, int32_t C,
+                    const int32_t *labels, double p_cross, double p_mut, uint64_t seed,
+                    uint32_t instance_id, uint32_t gen, const uint8_t *pop_in,
+                    const double *fit_in, uint8_t *pop_out);
+/* Whole island solve: K-means of the population at generation 0 and every
+ * recluster_every generations (0 = only at 0). */
+int pao_island_solve(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
+                     const double *beta, const double *user_xy, const double *bs_xy, int32_t N,
+                     int32_t gens, int32_t E, double p_cross, double p_mut, double kmeans_frac,
+                     double p_init, uint64_t seed, uint32_t instance_id, int32_t C,
+                     int32_t recluster_every, int32_t max_iters, uint8_t *best, double *best_fit,
+                     double *trace, uint8_t *final_pop, int32_t *final_labels);
 /* Exhaustive search over the K!^(L-1) classes (row 0 fixed to the identity). */
 int pao_bruteforce(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
                    const double *beta, uint8_t *best, double *best_fit, int64_t *count);
