@@ -314,6 +314,47 @@ pa_status pa_fitness_shaped(pa_instance *inst, const uint8_t *d_pop, int32_t n, 
 pa_status pa_solve_shape(pa_context *ctx, pa_instance *inst, int32_t *persistent, int32_t *block,
                          int32_t *children_per_task, int32_t *workgroups);
 
+/* ---- the parallel K-means GA (islands) ------------------------------- */
+
+/* K-means of a population into `clusters` islands (the "apply K-means" step
+ * of Alg. 2, PK-means GA, Sec. 4.3): each chromosome is the point of Z^{LK}
+ * formed by its pilot indices (squared Euclidean distance, exact integers);
+ * farthest-point start from the best-ranked chromosome of d_fit (fitness
+ * descending, lower index first; ties of distance to the lowest index), then
+ * at most kmeans_iters Lloyd iterations (nearest centroid, ties to the lowest
+ * cluster; centroid = per-gene rounded mean floor((2 s + n) / (2 n)); an empty
+ * cluster keeps its centroid) until no label changes.
+ *   d_pop [n][L][K], d_fit [n] (DEVICE): the population and its fitness
+ *   d_labels [n] (DEVICE, out): island of each chromosome, 0..clusters-1
+ * 1 <= clusters <= 16, clusters <= n <= 4096.  Async. */
+pa_status pa_population_kmeans(pa_instance *inst, int32_t clusters, int32_t kmeans_iters,
+                               const uint8_t *d_pop, const float *d_fit, int32_t n,
+                               int32_t *d_labels, void *stream);
+
+/* One generation of every island (Alg. 2 loop body: selection, crossover and
+ * mutation inside each cluster), island c being the positions labelled c in
+ * d_labels [N] (DEVICE): its first E_c positions receive its E_c best (in
+ * rank order; E_c = 0 if E = 0, else min(n_c, max(1, floor(E n_c / N + 1/2)))),
+ * its other positions children in pairs of consecutive island positions,
+ * from binary tournaments among its members, cell-axis crossover and swap
+ * mutation as in pa_ga_step.  The random streams are pa_ga_step's with the
+ * island index in bits 16..23 of the block counter: with every label 0 the
+ * result is pa_ga_step's, bit for bit.  pop <= 4096, 1 <= clusters <= 16.
+ * Async. */
+pa_status pa_island_step(pa_instance *inst, const pa_ga_params *params, int32_t clusters,
+                         int32_t gen, const int32_t *d_labels, const uint8_t *d_pop_in,
+                         const float *d_fit_in, uint8_t *d_pop_out, void *stream);
+
+/* The whole PK-means GA (Alg. 2): seeding and initial population as in
+ * pa_solve, then per generation: K-means of the population into `clusters`
+ * islands at generation 0 and every recluster_every generations (0: only at
+ * 0; Sec. 6.1 uses 3), one island step, the fitness of the new population.
+ * Fills out as pa_solve does; labels (HOST [pop] or NULL) receives the last
+ * partition.  clusters = 1 gives pa_solve's result.  Blocking. */
+pa_status pa_island_solve(pa_instance *inst, const pa_ga_params *params, int32_t clusters,
+                          int32_t recluster_every, int32_t kmeans_iters, pa_result *out,
+                          int32_t *labels, void *stream);
+
 /* ---- exhaustive search ------------------------------------------------ */
 
 /* Exhaustive search (the EX-PA reference, Sec. 3.3 and Sec. 6): every

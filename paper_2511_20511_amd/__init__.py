@@ -26,7 +26,8 @@ __all__ = [
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
     "pa_solve_shape", "pa_solve_batch_begin", "pa_solve_batch_next", "pa_solve_batch_state",
-    "pa_solve_population", "pa_device_peaks", "pa_solve_noalloc", "release_all", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
+    "pa_solve_population", "pa_device_peaks", "pa_solve_noalloc", "pa_population_kmeans", "pa_island_step",
+    "pa_island_solve", "release_all", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
     "pa_server_destroy", "pa_server_cancel", "Server", "pa_exhaustive",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
     "pa_status_string", "pa_last_error", "pa_version",
@@ -182,6 +183,10 @@ def lib():
                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), vp]),
         "pa_device_peaks": (st, [vp, ctypes.POINTER(_PeakRates)]),
         "pa_solve_noalloc": (st, [vp, ctypes.POINTER(_Params), vp, vp, vp, vp]),
+        "pa_population_kmeans": (st, [vp, i32, i32, vp, vp, i32, vp, vp]),
+        "pa_island_step": (st, [vp, ctypes.POINTER(_Params), i32, i32, vp, vp, vp, vp, vp]),
+        "pa_island_solve": (st, [vp, ctypes.POINTER(_Params), i32, i32, i32,
+                                 ctypes.POINTER(_Result), vp, vp]),
         "pa_problem_check": (st, [ctypes.POINTER(_Problem)]),
         "pa_params_check": (st, [ctypes.POINTER(_Problem), ctypes.POINTER(_Params)]),
         "pa_status_string": (ctypes.c_char_p, [st]),
@@ -439,6 +444,40 @@ def pa_solve_noalloc(inst: Instance, params: GaParams, d_best, d_best_fit, d_tra
                                   _dev(d_best_fit, torch.float32),
                                   None if d_trace is None else _dev(d_trace, torch.float32),
                                   _stream(stream)))
+
+
+def pa_population_kmeans(inst: Instance, clusters: int, d_pop, d_fit, n: int, d_labels,
+                         kmeans_iters: int = 20, stream=None):
+    """K-means of a device population into islands (Alg. 2); labels into d_labels."""
+    import torch
+    _check(lib().pa_population_kmeans(inst.h, int(clusters), int(kmeans_iters),
+                                      _dev(d_pop, torch.uint8), _dev(d_fit, torch.float32),
+                                      int(n), _dev(d_labels, torch.int32), _stream(stream)))
+
+
+def pa_island_step(inst: Instance, params: GaParams, clusters: int, gen: int, d_labels,
+                   d_pop_in, d_fit_in, d_pop_out, stream=None):
+    """One generation of every island (Alg. 2 loop body)."""
+    import torch
+    p = params.to_c()
+    _check(lib().pa_island_step(inst.h, ctypes.byref(p), int(clusters), int(gen),
+                                _dev(d_labels, torch.int32), _dev(d_pop_in, torch.uint8),
+                                _dev(d_fit_in, torch.float32), _dev(d_pop_out, torch.uint8),
+                                _stream(stream)))
+
+
+def pa_island_solve(inst: Instance, params: GaParams, clusters: int, recluster_every: int = 3,
+                    kmeans_iters: int = 20, stream=None):
+    """The PK-means GA (Alg. 2): (Result, labels of the last partition)."""
+    best = np.zeros((inst.L, inst.K), dtype=np.uint8)
+    trace = np.zeros(params.gens + 1, dtype=np.float32)
+    labels = np.zeros(params.pop, dtype=np.int32)
+    r = _Result(best.ctypes.data, 0.0, 0, trace.ctypes.data, 0.0)
+    p = params.to_c()
+    _check(lib().pa_island_solve(inst.h, ctypes.byref(p), int(clusters), int(recluster_every),
+                                 int(kmeans_iters), ctypes.byref(r), labels.ctypes.data,
+                                 _stream(stream)))
+    return Result(best, float(r.best_fit), int(r.best_index), trace, float(r.device_ms)), labels
 
 
 def pa_solve_begin(inst: Instance, params: GaParams, stream=None):

@@ -187,9 +187,11 @@ __device__ __forceinline__ void store_code_word(uint8_t *codes, int LK, int b, u
 // word (one bit of every gene of the group) at a time -- where thr's bit is 1
 // a 0 bit decides "below", where it is 0 a 1 bit decides "not below" -- and
 // stops drawing Philox blocks once every gene is decided.  The h-th mutating
-// gene takes its partner from word 32q + h of the MUT_PARTNER stream.
+// gene takes its partner from word 32q + h of the MUT_PARTNER stream.  boff is
+// or-ed into the block counter (the island streams of the island GA).
 __device__ __forceinline__ void group_codes(int q, int LK, int K, const DevGa &ga, uint32_t gen,
-                                            uint32_t slot, uint32_t (&out)[8]) {
+                                            uint32_t slot, uint32_t (&out)[8],
+                                            uint32_t boff = 0u) {
 #pragma unroll
   for (int w = 0; w < 8; ++w) out[w] = 0u;
   const int g0 = 32 * q;
@@ -203,7 +205,7 @@ __device__ __forceinline__ void group_codes(int q, int LK, int K, const DevGa &g
     const Stream dec{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutDecide};
     uint32_t und = valid;
     for (int k4 = 0; k4 < 8 && und != 0u; ++k4) {
-      const Words4 wb = dec.block((uint32_t)(8 * q + k4));
+      const Words4 wb = dec.block(boff | (uint32_t)(8 * q + k4));
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const uint32_t R = pick(wb, (uint32_t)u);
@@ -223,7 +225,7 @@ __device__ __forceinline__ void group_codes(int q, int LK, int K, const DevGa &g
   while (hitm != 0u) {
     const int b = __builtin_ctz(hitm);
     hitm &= hitm - 1u;
-    if ((h & 3) == 0) pw = par.block((uint32_t)(8 * q + (h >> 2)));
+    if ((h & 3) == 0) pw = par.block(boff | (uint32_t)(8 * q + (h >> 2)));
     const int k = (g0 + b) % K;
     const uint32_t r = bounded(pick(pw, (uint32_t)(h & 3)), (uint32_t)(K - 1));
     const uint32_t code = r + ((int)r >= k ? 1u : 0u) + 1u;

@@ -1,0 +1,450 @@
+// k_island.hip -- the parallel K-means GA (PK-means GA, Alg. 2, Sec. 4.3):
+// the population is partitioned by K-means into C clusters (islands) that
+// evolve on their own, and K-means is applied again every few generations
+// (three in Sec. 6.1).  The reading (the paper fixes neither the feature
+// space nor the per-island operators):
+//   - a chromosome is the point (g_0, .., g_{LK-1}) of Z^{LK}, squared
+//     Euclidean distance in integers (exact: at most 63^2 x 4096 < 2^31);
+//   - farthest-point start from the best-ranked chromosome (ties to the lowest
+//     index), then Lloyd iterations: assign to the nearest centroid (ties to
+//     the lowest cluster), centroid = per-gene rounded mean
+//     floor((2 s + n) / (2 n)) (an empty cluster keeps its centroid), until no
+//     label changes or max_iters;
+//   - island c holds the positions labelled c until the next clustering; its
+//     next generation: E_c = 0 if E = 0, else min(n_c, max(1, floor(E n_c / N
+//     + 1/2))) elites (its best, in rank order) in its first E_c positions,
+//     children in pairs over its following positions, tournament candidates
+//     among its members, crossover and mutation as in the panmictic step;
+//   - the random streams are those of the panmictic step with the island
+//     index in bits 16..23 of the block counter, so C = 1 is the panmictic GA.
+// Kernels: k_pop_kmeans (one workgroup per population) and k_island_step (one
+// workgroup per island, the processing unit of an island in Sec. 5).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "fitness_core.h"
+#include "ga_core.h"
+#include "pa_host.h"
+
+namespace pa {
+namespace {
+
+constexpr int kIslandMaxN = 4096;
+constexpr int kIslandMaxC = 16;
+constexpr int kKmThreads = 1024;
+
+// ---------------------------------------------------------------- K-means
+//
+// LDS: centroids [C][LK] bytes | labels [N] | nearest distances [N] | small
+// scratch.  The population stays in global memory (each chromosome read once
+// per assignment pass by its thread, each gene column once per update pass).
+struct PopKmArgs {
+  const uint8_t *pop;
+  const float *fit;
+  int N, LK, C, max_iters;
+  int32_t *labels;  // out [N]
+  int32_t *iters;   // out [1] (may be null)
+};
+
+// squared distance of chromosome row (global, 4-byte aligned when LK % 4 == 0)
+// to centroid cent (LDS)
+__device__ __forceinline__ int32_t km_dist(const uint8_t *row, const uint8_t *cent, int LK) {
+  int32_t d = 0;
+  if ((LK & 3) == 0) {
+    const gptr<const uint32_t> r = gp(reinterpret_cast<const uint32_t *>(row));
+    const uint32_t *c = reinterpret_cast<const uint32_t *>(cent);
+    for (int w = 0; w < (LK >> 2); ++w) {
+      const uint32_t a = r[w], b = c[w];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int32_t t = (int32_t)((a >> (8 * k)) & 0xFFu) - (int32_t)((b >> (8 * k)) & 0xFFu);
+        d += t * t;
+      }
+    }
+  } else {
+    for (int i = 0; i < LK; ++i) {
+      const int32_t t = (int32_t)gp(row)[i] - (int32_t)cent[i];
+      d += t * t;
+    }
+  }
+  return d;
+}
+
+// Block-wide arg-max of a 64-bit key over threads (lowest index wins through
+// the key's low half); returns it in every thread.
+__device__ __forceinline__ uint64_t block_max_u64(uint64_t k, uint64_t *sRed) {
+  k = wave_max_u64(k);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  __syncthreads();
+  if (lane == 0) sRed[wave] = k;
+  __syncthreads();
+  uint64_t m = 0;
+  const int nw = (int)blockDim.x / kWave;
+  for (int w = 0; w < nw; ++w) m = sRed[w] > m ? sRed[w] : m;
+  return m;
+}
+
+__global__ __launch_bounds__(kKmThreads) void k_pop_kmeans(PopKmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int N = a.N, LK = a.LK, C = a.C;
+  const int cent_bytes = (C * LK + 15) / 16 * 16;
+  uint8_t *sCent = smem;
+  int32_t *sLab = reinterpret_cast<int32_t *>(smem + cent_bytes);
+  int32_t *sDmin = sLab + N;
+  uint64_t *sRed = reinterpret_cast<uint64_t *>(sDmin + N);  // 8 N bytes after sLab: aligned
+  int32_t *sFlag = reinterpret_cast<int32_t *>(sRed + kKmThreads / kWave);
+  int32_t *sCnt = sFlag + 2;
+  const int tid = threadIdx.x, T = blockDim.x;
+  // centroid 0: the best-ranked chromosome (fitness descending, lower index
+  // first, NaN last: the rank key)
+  uint64_t bk = 0;
+  for (int n = tid; n < N; n += T) {
+    const uint64_t k = full_key(gp(a.fit)[n], (uint32_t)n);
+    bk = k > bk ? k : bk;
+  }
+  int pick = (int)key_index(block_max_u64(bk, sRed));
+  for (int m = 0; m < C; ++m) {
+    for (int i = tid; i < LK; i += T) sCent[m * LK + i] = gp(a.pop)[(size_t)pick * LK + i];
+    __syncthreads();
+    if (m + 1 == C) break;
+    // nearest-centroid distance of every chromosome, updated with centroid m;
+    // the next centroid is the farthest (ties to the lowest index)
+    uint64_t fk = 0;
+    for (int n = tid; n < N; n += T) {
+      const int32_t d = km_dist(a.pop + (size_t)n * LK, sCent + m * LK, LK);
+      const int32_t dm = m == 0 ? d : min(sDmin[n], d);
+      sDmin[n] = dm;
+      const uint64_t k = ((uint64_t)(uint32_t)dm << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)n);
+      fk = k > fk ? k : fk;
+    }
+    pick = (int)key_index(block_max_u64(fk, sRed));
+  }
+  for (int n = tid; n < N; n += T) sLab[n] = -1;
+  int it = 0;
+  for (; it < a.max_iters; ++it) {
+    if (tid == 0) sFlag[0] = 0;
+    __syncthreads();
+    // assignment: nearest centroid, ties to the lowest cluster
+    for (int n = tid; n < N; n += T) {
+      int best = 0;
+      int32_t bd = 0x7FFFFFFF;
+      for (int c = 0; c < C; ++c) {
+        const int32_t d = km_dist(a.pop + (size_t)n * LK, sCent + c * LK, LK);
+        if (d < bd) {
+          bd = d;
+          best = c;
+        }
+      }
+      if (sLab[n] != best) {
+        sLab[n] = best;
+        sFlag[0] = 1;
+      }
+    }
+    __syncthreads();
+    if (sFlag[0] == 0) break;
+    // update: per gene, the member sums of every cluster (then counts)
+    if (tid < C) sCnt[tid] = 0;
+    __syncthreads();
+    for (int n = tid; n < N; n += T) atomicAdd(&sCnt[sLab[n]], 1);
+    __syncthreads();
+    for (int i = tid; i < LK; i += T) {
+      int32_t s[kIslandMaxC];
+#pragma unroll
+      for (int c = 0; c < kIslandMaxC; ++c) s[c] = 0;
+      for (int n = 0; n < N; ++n) {
+        const int32_t g = gp(a.pop)[(size_t)n * LK + i];
+        const int lab = sLab[n];
+#pragma unroll
+        for (int c = 0; c < kIslandMaxC; ++c) s[c] += lab == c ? g : 0;
+      }
+#pragma unroll
+      for (int c = 0; c < kIslandMaxC; ++c) {
+        if (c < C && sCnt[c] > 0)
+          sCent[c * LK + i] = (uint8_t)((2 * s[c] + sCnt[c]) / (2 * sCnt[c]));
+      }
+    }
+    __syncthreads();
+  }
+  for (int n = tid; n < N; n += T) gp(a.labels)[n] = sLab[n];
+  if (tid == 0 && a.iters) *gp(a.iters) = it;
+}
+
+// ---------------------------------------------------------------- island step
+struct IslandArgs {
+  const uint8_t *pin;
+  const float *fin;
+  uint8_t *pout;
+  const int32_t *labels;
+  int N, E, L, K;
+  uint32_t gen;
+  DevGa ga;
+};
+
+constexpr int kIslandThreads = 256;
+
+__global__ __launch_bounds__(kIslandThreads) void k_island_step(IslandArgs a) {
+  __shared__ int32_t sM[kIslandMaxN];
+  __shared__ uint64_t sRed[kIslandThreads / kWave];
+  __shared__ int32_t sCount[kIslandThreads / kWave + 1];
+  const int c = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
+  const int N = a.N, L = a.L, K = a.K, LK = L * K;
+  // members of island c, in increasing position: a block prefix over the labels
+  int base = 0;
+  for (int n0 = 0; n0 < N; n0 += T) {
+    const int n = n0 + tid;
+    const bool mine = n < N && gp(a.labels)[n] == c;
+    const uint64_t ballot = __ballot(mine);
+    const int wave = tid / kWave, lane = tid % kWave;
+    const int before = __popcll(ballot & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (lane == 0) sCount[wave] = __popcll(ballot);
+    __syncthreads();
+    int off = base;
+    for (int w = 0; w < wave; ++w) off += sCount[w];
+    if (mine) sM[off + before] = n;
+    int total = 0;
+    for (int w = 0; w < T / kWave; ++w) total += sCount[w];
+    __syncthreads();
+    base += total;
+  }
+  const int n = base;
+  if (n == 0) return;
+  const uint32_t boff = (uint32_t)c << 16;
+  int Ec = 0;
+  if (a.E > 0) {
+    Ec = (int)((2 * (int64_t)a.E * n + N) / (2 * (int64_t)N));
+    Ec = Ec < 1 ? 1 : (Ec > n ? n : Ec);
+  }
+  // elites: the island's Ec best in rank order (repeated arg-max over keys
+  // below the previous maximum; keys embed the position, so they are unique)
+  uint64_t prev = ~0ull;
+  for (int e = 0; e < Ec; ++e) {
+    uint64_t best = 0;
+    for (int t = tid; t < n; t += T) {
+      const int m = sM[t];
+      const uint64_t k = full_key(gp(a.fin)[m], (uint32_t)m);
+      if (k < prev && k > best) best = k;
+    }
+    best = block_max_u64(best, sRed);
+    prev = best;
+    __syncthreads();
+    const int src = (int)key_index(best), dst = sM[e];
+    for (int i = tid; i < LK; i += T)
+      gp(a.pout)[(size_t)dst * LK + i] = gp(a.pin)[(size_t)src * LK + i];
+  }
+  // children, one thread each: pair (first, first + 1) of island positions
+  // t >= Ec; selection words keyed by the pair's first slot
+  const bool mutate = K >= 2 && a.ga.thr_mut != 0;
+  for (int t = Ec + tid; t < n; t += T) {
+    const int first = Ec + ((t - Ec) & ~1);
+    const bool second = ((t - Ec) & 1) != 0;
+    const uint32_t slot_a = (uint32_t)sM[first];
+    const Stream st{a.ga.seed_lo, a.ga.seed_hi, slot_a, a.gen, a.ga.instance_id, kTagSelect};
+    const Words4 b0 = st.block(boff | 0u), b1 = st.block(boff | 1u);
+    const int u0 = sM[bounded(b0.x, (uint32_t)n)], v0 = sM[bounded(b0.y, (uint32_t)n)];
+    const int u1 = sM[bounded(b0.z, (uint32_t)n)], v1 = sM[bounded(b0.w, (uint32_t)n)];
+    const int p1 = beats(rank_key(gp(a.fin)[v0]), (uint32_t)v0, rank_key(gp(a.fin)[u0]),
+                         (uint32_t)u0)
+                       ? v0
+                       : u0;
+    const int p2 = beats(rank_key(gp(a.fin)[v1]), (uint32_t)v1, rank_key(gp(a.fin)[u1]),
+                         (uint32_t)u1)
+                       ? v1
+                       : u1;
+    const bool cross = L >= 2 && hit(b1.x, a.ga.thr_cross);
+    const int cut = cross ? 1 + (int)bounded(b1.y, (uint32_t)(L - 1)) : L;
+    const int pf = second ? p2 : p1, pr = second ? p1 : p2;
+    const int slot = sM[t];
+    uint8_t *dst = a.pout + (size_t)slot * LK;
+    for (int g = 0; g < LK; ++g)
+      gp(dst)[g] = gp(a.pin)[(size_t)(g < cut * K ? pf : pr) * LK + g];
+    if (mutate) {
+      for (int q = 0; 32 * q < LK; ++q) {
+        uint32_t code[8];
+        group_codes(q, LK, K, a.ga, a.gen, (uint32_t)slot, code, boff);
+        for (int b = 0; b < 32 && 32 * q + b < LK; ++b) {
+          const int cd = (int)((code[b >> 2] >> (8 * (b & 3))) & 0xFFu);
+          if (cd == 0) continue;
+          const int i = 32 * q + b, j = i / K, k = i - j * K;
+          const uint8_t x = gp(dst)[j * K + k];
+          gp(dst)[j * K + k] = gp(dst)[j * K + cd - 1];
+          gp(dst)[j * K + cd - 1] = x;
+        }
+      }
+    }
+  }
+}
+
+__global__ void k_trace_best(const float *fit, int N, float *trace_g) {
+  // best fitness of a population into one trace entry (one wave)
+  uint64_t b = 0;
+  for (int n = threadIdx.x; n < N; n += kWave) {
+    const uint64_t k = full_key(gp(fit)[n], (uint32_t)n);
+    b = k > b ? k : b;
+  }
+  b = wave_max_u64(b);
+  if (threadIdx.x == 0) *gp(trace_g) = gp(fit)[key_index(b)];
+}
+
+hipError_t launch_trace_best(const float *fit, int N, float *trace_g, hipStream_t s) {
+  hipLaunchKernelGGL(k_trace_best, dim3(1), dim3(kWave), 0, s, fit, N, trace_g);
+  return hipGetLastError();
+}
+
+int kmeans_lds(int N, int LK, int C) {
+  return (C * LK + 15) / 16 * 16 + 8 * N + 8 * (kKmThreads / kWave) + 4 * (2 + kIslandMaxC);
+}
+
+hipError_t launch_pop_kmeans(const uint8_t *pop, const float *fit, int N, int LK, int C,
+                             int max_iters, int32_t *labels, int32_t *iters, hipStream_t s) {
+  static LdsAttr attr;
+  const int lds = kmeans_lds(N, LK, C);
+  const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(k_pop_kmeans), kLdsBytes);
+  PopKmArgs a{pop, fit, N, LK, C, max_iters, labels, iters};
+  hipLaunchKernelGGL(k_pop_kmeans, dim3(1), dim3(kKmThreads), lds, s, a);
+  return launch_status(ae);
+}
+
+hipError_t launch_island_step(const DevProblem &p, const DevGa &ga, int C, uint32_t gen,
+                              const int32_t *labels, const uint8_t *pin, const float *fin,
+                              uint8_t *pout, hipStream_t s) {
+  IslandArgs a{pin, fin, pout, labels, ga.N, ga.E, p.L, p.K, gen, ga};
+  hipLaunchKernelGGL(k_island_step, dim3(C), dim3(kIslandThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+pa_status island_check(const pa_instance *in, int N, int C, int max_iters) {
+  if (C < 1 || C > kIslandMaxC) return set_error(PA_EINVAL, "clusters=%d outside [1, %d]", C, kIslandMaxC);
+  if (N > kIslandMaxN) return set_error(PA_EINVAL, "island GA: pop=%d above %d", N, kIslandMaxN);
+  if (C > N) return set_error(PA_EINVAL, "clusters=%d above pop=%d", C, N);
+  if (max_iters < 1) return set_error(PA_EINVAL, "kmeans_iters=%d must be >= 1", max_iters);
+  if (kmeans_lds(N, in->p.L * in->p.K, C) > kLdsBytes)
+    return set_error(PA_EUNSUPPORTED, "population K-means does not fit LDS");
+  return PA_OK;
+}
+
+#define ITRY(call, what)                              \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_error(e_, what); \
+  } while (0)
+
+}  // namespace
+}  // namespace pa
+
+using namespace pa;
+
+extern "C" {
+
+pa_status pa_population_kmeans(pa_instance *in, int32_t clusters, int32_t kmeans_iters,
+                               const uint8_t *d_pop, const float *d_fit, int32_t n,
+                               int32_t *d_labels, void *stream) {
+  if (!in || !d_pop || !d_fit || !d_labels) return set_error(PA_EINVAL, "NULL argument");
+  if (n < 1) return set_error(PA_EINVAL, "n=%d must be >= 1", n);
+  pa_status st = island_check(in, n, clusters, kmeans_iters);
+  if (st != PA_OK) return st;
+  if ((st = use_device(in->ctx)) != PA_OK) return st;
+  ITRY(launch_pop_kmeans(d_pop, d_fit, n, in->p.L * in->p.K, clusters, kmeans_iters, d_labels,
+                         nullptr, (hipStream_t)stream),
+       "pa_population_kmeans");
+  return PA_OK;
+}
+
+pa_status pa_island_step(pa_instance *in, const pa_ga_params *g, int32_t clusters, int32_t gen,
+                         const int32_t *d_labels, const uint8_t *d_pop_in, const float *d_fit_in,
+                         uint8_t *d_pop_out, void *stream) {
+  if (!in || !d_labels || !d_pop_in || !d_fit_in || !d_pop_out)
+    return set_error(PA_EINVAL, "NULL argument");
+  if (d_pop_in == d_pop_out) return set_error(PA_EINVAL, "d_pop_in and d_pop_out must differ");
+  pa_status st = validate_ga(in, g);
+  if (st != PA_OK) return st;
+  if ((st = island_check(in, g->pop, clusters, 1)) != PA_OK) return st;
+  if ((st = use_device(in->ctx)) != PA_OK) return st;
+  ITRY(launch_island_step(in->p, ga_from_params(g), clusters, (uint32_t)gen, d_labels, d_pop_in,
+                          d_fit_in, d_pop_out, (hipStream_t)stream),
+       "pa_island_step");
+  return PA_OK;
+}
+
+pa_status pa_island_solve(pa_instance *in, const pa_ga_params *g, int32_t clusters,
+                          int32_t recluster_every, int32_t kmeans_iters, pa_result *out,
+                          int32_t *labels, void *stream) {
+  if (in && g && g->pop < 1) return set_error(PA_EINVAL, "pop=%d must be >= 1", g->pop);
+  if (!in || !out) return set_error(PA_EINVAL, "instance or result is NULL");
+  pa_status st = validate_ga(in, g);
+  if (st != PA_OK) return st;
+  if ((st = island_check(in, g->pop, clusters, kmeans_iters)) != PA_OK) return st;
+  if (recluster_every < 0) return set_error(PA_EINVAL, "recluster_every=%d < 0", recluster_every);
+  if ((st = use_device(in->ctx)) != PA_OK) return st;
+  const int N = g->pop, G = g->gens, LK = in->p.L * in->p.K;
+  hipStream_t s = (hipStream_t)stream;
+  // work buffers: two populations, two fitness arrays, labels, trace, best
+  uint8_t *pop[2] = {nullptr, nullptr};
+  float *fit[2] = {nullptr, nullptr};
+  int32_t *lab = nullptr, *bidx = nullptr;
+  float *trace = nullptr, *bfit = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto release = [&]() {
+    for (void *p : {(void *)pop[0], (void *)pop[1], (void *)fit[0], (void *)fit[1], (void *)lab,
+                    (void *)bidx, (void *)trace, (void *)bfit})
+      if (p) (void)hipFree(p);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  hipError_t e = hipSuccess;
+  for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+    e = hipMalloc(&pop[b], (size_t)LK * N);
+    if (e == hipSuccess) e = hipMalloc(&fit[b], sizeof(float) * N);
+  }
+  if (e == hipSuccess) e = hipMalloc(&lab, sizeof(int32_t) * N);
+  if (e == hipSuccess) e = hipMalloc(&bidx, sizeof(int32_t));
+  if (e == hipSuccess) e = hipMalloc(&trace, sizeof(float) * (G + 1));
+  if (e == hipSuccess) e = hipMalloc(&bfit, sizeof(float));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = hipMemsetAsync(lab, 0, sizeof(int32_t) * N, s);
+  const DevGa ga = ga_from_params(g);
+  FitShape fs;
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess && ga.n_km > 0) e = launch_kmeans_seed(in->p, s);
+  if (e == hipSuccess) e = launch_init_pop(in->p, ga, pop[0], s);
+  if (e == hipSuccess) e = launch_fitness(in->p, pop[0], N, fit[0], fs, in->ctx->info, s);
+  for (int gen = 0; gen < G && e == hipSuccess; ++gen) {
+    const int a = gen & 1, b = 1 - a;
+    e = launch_trace_best(fit[a], N, trace + gen, s);
+    // Alg. 2: apply K-means (at 0, then every recluster_every generations)
+    if (e == hipSuccess && clusters > 1 &&
+        (gen == 0 || (recluster_every > 0 && gen % recluster_every == 0)))
+      e = launch_pop_kmeans(pop[a], fit[a], N, LK, clusters, kmeans_iters, lab, nullptr, s);
+    if (e == hipSuccess)
+      e = launch_island_step(in->p, ga, clusters, (uint32_t)gen, lab, pop[a], fit[a], pop[b], s);
+    if (e == hipSuccess) e = launch_fitness(in->p, pop[b], N, fit[b], fs, in->ctx->info, s);
+  }
+  const int fin = G & 1;
+  if (e == hipSuccess) e = launch_trace_best(fit[fin], N, trace + G, s);
+  if (e == hipSuccess) e = launch_best(fit[fin], N, bidx, bfit, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  int32_t hidx = 0;
+  float hfit = 0.0f;
+  std::vector<float> htrace(G + 1);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hidx, bidx, sizeof hidx, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hfit, bfit, sizeof hfit, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(htrace.data(), trace, sizeof(float) * (G + 1), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess && out->best)
+    e = hipMemcpy(out->best, pop[fin] + (size_t)hidx * LK, LK, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && labels)
+    e = hipMemcpy(labels, lab, sizeof(int32_t) * N, hipMemcpyDeviceToHost);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  release();
+  if (e != hipSuccess) return hip_error(e, "pa_island_solve");
+  out->best_fit = hfit;
+  out->best_index = hidx;
+  if (out->trace) std::memcpy(out->trace, htrace.data(), sizeof(float) * (G + 1));
+  out->device_ms = ms;
+  return PA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+"""The island GA (PK-means GA, Alg. 2) on the GPU against the oracle.
+
+The population K-means gives the oracle's labels bit for bit, the island step
+the oracle's next population bit for bit (fed the same FP32 fitness), and a
+whole island solve runs in lockstep with the oracle's operators fed the GPU's
+FP32 fitness (re-clustering every three generations, Sec. 6.1); one island
+is pa_solve."""
+import numpy as np
+import pytest
+
+from gpu_util import ctx, flush, need_gpu, rand_pop, to_dev
+from paper_2511_20511_amd import scenario
+
+pytestmark = pytest.mark.gpu
+
+
+def _inst(pa, L, K, seed=1, inst_id=0):
+    d = scenario.make_drop(L, K, seed=seed, instance_id=inst_id)
+    return d, pa.pa_instance_create(ctx(), d.beta, d.user_xy, d.bs_xy, T=196)
+
+
+@pytest.mark.parametrize("L,K,N,C", [(7, 4, 50, 5), (19, 16, 256, 5), (5, 7, 37, 3),
+                                     (37, 32, 1000, 16), (7, 4, 20, 1), (3, 3, 16, 16)])
+def test_population_kmeans_matches_oracle(oracle_mod, L, K, N, C):
+    torch = need_gpu()
+    import paper_2511_20511_amd as pa
+    rng = np.random.default_rng(L * 100 + C)
+    d, inst = _inst(pa, L, K)
+    pop = rand_pop(rng, N, L, K)
+    # a few near-duplicates and equal fitness values (ties)
+    pop[N // 2:N // 2 + 3] = pop[0]
+    fit = rng.normal(size=N).astype(np.float32)
+    fit[1] = fit[2]
+    lab = torch.zeros(N, dtype=torch.int32, device="cuda")
+    for iters in (1, 20):
+        flush(f"population K-means L={L} K={K} N={N} C={C} iters={iters}")
+        pa.pa_population_kmeans(inst, C, to_dev(pop, torch), to_dev(fit, torch), N, lab,
+                                kmeans_iters=iters)
+        torch.cuda.synchronize()
+        want, _, _ = oracle_mod.pop_kmeans(pop, fit.astype(np.float64), C, max_iters=iters)
+        assert np.array_equal(lab.cpu().numpy(), want)
+    inst.close()
+
+
+@pytest.mark.parametrize("L,K,N,C,E", [(7, 4, 50, 5, 2), (19, 16, 256, 5, 8), (5, 7, 41, 3, 3),
+                                       (37, 32, 300, 4, 8), (7, 5, 30, 16, 0)])
+def test_island_step_matches_oracle(oracle_mod, L, K, N, C, E):
+    torch = need_gpu()
+    import paper_2511_20511_amd as pa
+    rng = np.random.default_rng(N + C)
+    d, inst = _inst(pa, L, K)
+    pop = rand_pop(rng, N, L, K)
+    fit = rng.normal(size=N).astype(np.float32)
+    lab = rng.integers(0, C, size=N).astype(np.int32)
+    lab[:C] = np.arange(C)
+    params = pa.GaParams(pop=N, gens=5, elite=E, p_cross=0.8, p_mut=0.05, seed=33, instance_id=2)
+    out = torch.zeros((N, L, K), dtype=torch.uint8, device="cuda")
+    for gen in (0, 3):
+        flush(f"island step L={L} K={K} N={N} C={C} E={E} gen={gen}")
+        pa.pa_island_step(inst, params, C, gen, to_dev(lab, torch), to_dev(pop, torch),
+                          to_dev(fit, torch), out)
+        torch.cuda.synchronize()
+        want = oracle_mod.island_step(pop, fit.astype(np.float64), lab, C, E, 0.8, 0.05, 33, 2,
+                                      gen)
+        assert np.array_equal(out.cpu().numpy(), want)
+    inst.close()
+
+
+@pytest.mark.parametrize("L,K,N,G,E,C,R", [(7, 4, 50, 12, 2, 5, 3), (19, 16, 120, 9, 8, 5, 3),
+                                           (7, 5, 40, 7, 2, 3, 0)])
+def test_island_solve_lockstep(oracle_mod, L, K, N, G, E, C, R):
+    torch = need_gpu()
+    import paper_2511_20511_amd as pa
+    d, inst = _inst(pa, L, K, seed=4, inst_id=1)
+    params = pa.GaParams(pop=N, gens=G, elite=E, p_cross=0.8, p_mut=0.05, kmeans_frac=0.5,
+                         p_init=0.1, seed=12, instance_id=1)
+    flush(f"island solve L={L} K={K} N={N} G={G} C={C} R={R}")
+    res, labels = pa.pa_island_solve(inst, params, C, R)
+    # lockstep: the oracle's K-means and island step fed the GPU's FP32 fitness
+    seed = oracle_mod.kmeans_seed(d.user_xy, d.bs_xy)[0]
+    pop = oracle_mod.init_pop(L, K, N, 0.5, 0.1, 12, 1, seed)
+    d_pop = torch.empty((N, L, K), dtype=torch.uint8, device="cuda")
+    d_fit = torch.empty(N, dtype=torch.float32, device="cuda")
+    lab = np.zeros(N, dtype=np.int32)
+    trace = []
+    for g in range(G + 1):
+        d_pop.copy_(torch.from_numpy(pop))
+        pa.pa_fitness(inst, d_pop, N, d_fit)
+        torch.cuda.synchronize()
+        fit = d_fit.cpu().numpy()
+        want = oracle_mod.fitness(d.beta, pop, T=196)
+        assert np.all(np.abs(fit - want) <= 1e-5 * np.abs(want))
+        trace.append(fit[oracle_mod.rank(fit.astype(np.float64))[0]])
+        if g == G:
+            break
+        if C > 1 and (g == 0 or (R > 0 and g % R == 0)):
+            lab, _, _ = oracle_mod.pop_kmeans(pop, fit.astype(np.float64), C)
+        pop = oracle_mod.island_step(pop, fit.astype(np.float64), lab, C, E, 0.8, 0.05, 12, 1, g)
+    b = oracle_mod.rank(fit.astype(np.float64))[0]
+    assert np.array_equal(res.best, pop[b]) and res.best_index == b
+    assert np.float32(res.best_fit).view(np.uint32) == fit[b].view(np.uint32)
+    assert np.array_equal(res.trace.view(np.uint32), np.array(trace, np.float32).view(np.uint32))
+    assert np.array_equal(labels, lab)
+    assert np.all(np.diff(res.trace) >= 0)
+    inst.close()
+
+
+def test_one_island_is_solve():
+    need_gpu()
+    import paper_2511_20511_amd as pa
+    d, inst = _inst(pa, 19, 16, seed=2)
+    params = pa.GaParams(pop=128, gens=20, elite=8, seed=5, instance_id=0)
+    res, labels = pa.pa_island_solve(inst, params, 1, 3)
+    ref = pa.pa_solve(inst, params)
+    assert np.array_equal(res.best, ref.best) and res.best_index == ref.best_index
+    assert np.float32(res.best_fit).view(np.uint32) == np.float32(ref.best_fit).view(np.uint32)
+    assert np.array_equal(res.trace.view(np.uint32), ref.trace.view(np.uint32))
+    assert np.all(labels == 0)
+    with pytest.raises(pa.PaError):
+        pa.pa_island_solve(inst, pa.GaParams(pop=5000, gens=1), 5, 3)
+    inst.close()
