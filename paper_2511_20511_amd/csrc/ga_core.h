@@ -189,9 +189,10 @@ __device__ __forceinline__ void store_code_word(uint8_t *codes, int LK, int b, u
 // stops drawing Philox blocks once every gene is decided.  The h-th mutating
 // gene takes its partner from word 32q + h of the MUT_PARTNER stream.  boff is
 // or-ed into the block counter (the island streams of the island GA).
-__device__ __forceinline__ void group_codes(int q, int LK, int K, const DevGa &ga, uint32_t gen,
-                                            uint32_t slot, uint32_t (&out)[8],
-                                            uint32_t boff = 0u) {
+// Returns the mask of the group's mutating genes (bit b: gene 32q + b).
+__device__ __forceinline__ uint32_t group_codes(int q, int LK, int K, const DevGa &ga,
+                                                uint32_t gen, uint32_t slot, uint32_t (&out)[8],
+                                                uint32_t boff = 0u) {
 #pragma unroll
   for (int w = 0; w < 8; ++w) out[w] = 0u;
   const int g0 = 32 * q;
@@ -218,7 +219,8 @@ __device__ __forceinline__ void group_codes(int q, int LK, int K, const DevGa &g
       }
     }
   }
-  if (hitm == 0u) return;
+  if (hitm == 0u) return 0u;
+  const uint32_t hits = hitm;
   const Stream par{ga.seed_lo, ga.seed_hi, slot, gen, ga.instance_id, kTagMutPartner};
   Words4 pw{0u, 0u, 0u, 0u};
   int h = 0;
@@ -235,6 +237,17 @@ __device__ __forceinline__ void group_codes(int q, int LK, int K, const DevGa &g
       if ((b >> 2) == w) out[w] |= code << (8 * (b & 3));
     ++h;
   }
+  return hits;
+}
+
+// Byte b (0..31) of a group's codes, selected without dynamic register
+// indexing.
+__device__ __forceinline__ uint32_t code_byte(const uint32_t (&code)[8], int b) {
+  const int w = b >> 2;
+  uint32_t x = code[0];
+#pragma unroll
+  for (int i = 1; i < 8; ++i) x = w == i ? code[i] : x;
+  return (x >> (8 * (b & 3))) & 0xFFu;
 }
 
 // The latency form of group_codes: eight lanes (u = 0..7, consecutive lanes

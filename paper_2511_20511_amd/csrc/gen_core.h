@@ -80,9 +80,12 @@ struct GenPlan {
   static_assert(kTotal <= kLdsBytes, "LDS plan too large");
 };
 
+// A task read with scalar loads (task lists are read-only while a launch
+// runs); t must be wave-uniform.
 __device__ __forceinline__ GenTask load_task(const GenTask *tasks, int t) {
-  const gptr<const GenTask> p = gp(tasks) + t;
-  return GenTask{p->inst, p->kind, p->s0, p->s1};
+  typedef __attribute__((address_space(4))) const int32_t *cwords;
+  const cwords p = (cwords)reinterpret_cast<const int32_t *>(tasks + __builtin_amdgcn_readfirstlane(t));
+  return GenTask{p[0], p[1], p[2], p[3]};
 }
 
 // The children's rows straight from their parents (K % 4 == 0, K <= 32;
@@ -457,7 +460,7 @@ __device__ __forceinline__ void gen_tasks_exact(const GenInst *insts, const GenT
                                                 LdsState &st, const int32_t *gens = nullptr) {
   for (int t = t0; t < t1; ++t) {
     const GenTask task = load_task(tasks, t);
-    const GenInst I = insts[task.inst];
+    const GenInst I = load_inst(insts, task.inst);
     const int g = gens ? gp(gens)[task.inst] : gen;
     run_task<LT, TPT, MODE, BLOCK, PF, KIND>(I, task, g, smem, st, false);
   }
@@ -578,19 +581,18 @@ __device__ __forceinline__ void rows_finish(const GenInst &I, const GenTask &tas
     if (mutate) {
       if (K == 32) {
         uint32_t code[8];
-        group_codes(j, LK, K, I.ga, (uint32_t)gen, (uint32_t)(task.s0 + c), code);
-#pragma unroll
-        for (int w = 0; w < 8; ++w) {
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int cd = (int)((code[w] >> (8 * b)) & 0xFFu);
-            if (cd != 0) {
-              const int k = 4 * w + b;
-              const uint8_t t = rowb[k];
-              rowb[k] = rowb[cd - 1];
-              rowb[cd - 1] = t;
-            }
-          }
+        // the row's swaps in increasing gene order, over this row's hits only
+        // (a loop over all 32 positions runs nearly every one for some lane
+        // of the wave)
+        uint32_t hits =
+            group_codes(j, LK, K, I.ga, (uint32_t)gen, (uint32_t)(task.s0 + c), code);
+        while (hits != 0u) {
+          const int k = __builtin_ctz(hits);
+          hits &= hits - 1u;
+          const int kp = (int)code_byte(code, k) - 1;
+          const uint8_t t = rowb[k];
+          rowb[k] = rowb[kp];
+          rowb[kp] = t;
         }
       } else {
         apply_swaps(rowb, sCode + q * K, q * K, K);
@@ -646,7 +648,7 @@ __device__ __forceinline__ void gen_tasks_tiled(const GenInst *insts, const GenT
   bool ready = false;  // this task's source rows are in sChild (and its codes in sCode)
   GenTask task = t0 < t1 ? load_task(tasks, t0) : GenTask{0, kTaskElite, 0, 0};
   for (int t = t0; t < t1; ++t) {
-    const GenInst I = insts[task.inst];
+    const GenInst I = load_inst(insts, task.inst);
     const int g = gens ? gp(gens)[task.inst] : gen_arg;
     const GenTask next = t + 1 < t1 ? load_task(tasks, t + 1) : GenTask{0, kTaskElite, 0, 0};
     const bool child = task.kind == kTaskChild && g >= 0 && g < I.G && rows_path(I);
@@ -822,7 +824,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_persist(PersistArgs a) {
   const bool fixed = a.chunk == 1 && (int)blockIdx.x < a.ntasks;
   GenTask mt{0, kTaskElite, 0, 0};
   if (fixed) mt = load_task(a.tasks, blockIdx.x);
-  const GenInst mI = a.insts[mt.inst];
+  const GenInst mI = load_inst(a.insts, mt.inst);
   bool prepared = false;  // the child task of `gen` is prepared
   for (int gen = a.g0; gen < a.g1; ++gen) {
     if (gen < 0) {
@@ -836,7 +838,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_persist(PersistArgs a) {
       const int t1 = fixed ? 1 : min(a.ntasks, t0 + a.chunk);
       for (int t = t0; t < t1; ++t) {
         const GenTask task = fixed ? mt : load_task(a.tasks, t);
-        const GenInst I = fixed ? mI : a.insts[task.inst];
+        const GenInst I = fixed ? mI : load_inst(a.insts, task.inst);
         run_task<LT, TPT, MODE, BLOCK, PF>(I, task, gen, smem, st, prepared);
       }
     }
@@ -877,7 +879,7 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
   int loaded = -1;
   for (int t = t0; t < t1; ++t) {
     const GenTask task = load_task(a.tasks, t);
-    const GenInst &I = a.insts[task.inst];
+    const GenInst I = load_inst(a.insts, task.inst);
     const int gen = a.gens ? gp(a.gens)[task.inst] : a.gen;
     if (gen >= I.G) continue;
     const int L = I.L, TP = I.TP, TR = pl.tile_rows;

@@ -261,10 +261,11 @@ __global__ __launch_bounds__(kIslandThreads) void k_island_step(IslandArgs a) {
     if (mutate) {
       for (int q = 0; 32 * q < LK; ++q) {
         uint32_t code[8];
-        group_codes(q, LK, K, a.ga, a.gen, (uint32_t)slot, code, boff);
-        for (int b = 0; b < 32 && 32 * q + b < LK; ++b) {
-          const int cd = (int)((code[b >> 2] >> (8 * (b & 3))) & 0xFFu);
-          if (cd == 0) continue;
+        uint32_t hits = group_codes(q, LK, K, a.ga, a.gen, (uint32_t)slot, code, boff);
+        while (hits != 0u) {
+          const int b = __builtin_ctz(hits);
+          hits &= hits - 1u;
+          const int cd = (int)code_byte(code, b);
           const int i = 32 * q + b, j = i / K, k = i - j * K;
           const uint8_t x = gp(dst)[j * K + k];
           gp(dst)[j * K + k] = gp(dst)[j * K + cd - 1];

@@ -107,6 +107,20 @@ struct GenInst {
 };
 
 
+// A descriptor read with scalar loads (the constant address space: nothing
+// writes descriptors while a kernel that reads them runs), so that its fields
+// live in scalar registers; i must be wave-uniform.
+__device__ __forceinline__ GenInst load_inst(const GenInst *insts, int i) {
+  static_assert(sizeof(GenInst) % 4 == 0, "descriptor of whole words");
+  typedef __attribute__((address_space(4))) const uint32_t *cwords;
+  const cwords src = (cwords)reinterpret_cast<const uint32_t *>(insts + __builtin_amdgcn_readfirstlane(i));
+  GenInst I;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(&I);
+#pragma unroll
+  for (int w = 0; w < (int)(sizeof(GenInst) / 4); ++w) dst[w] = src[w];
+  return I;
+}
+
 // Buffer b of an instance, by selection (no dynamic index, so a descriptor
 // copied into registers stays in registers).
 __device__ __forceinline__ uint8_t *pop_buf(const GenInst &I, int b) {
