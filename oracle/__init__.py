@@ -125,8 +125,9 @@ def threshold(p):
 
 
 def fitness(beta, pop, T=0, se_mode=SE_ASYMPTOTIC, M=1, rho=1.0, objective=0):
-    """Sum SE (Eq. 5-7) x pre-log (Sec. 3) of each chromosome, or with objective 1
-    the smallest per-user SINR (max-min SIR); beta [L][L][K], pop [n][L][K]."""
+    """Sum SE (Eq. 5-7) x pre-log (Sec. 3) of each chromosome, with objective 1
+    the smallest per-user SINR (max-min SIR), with objective 2 minus the
+    inter-cluster interference of Eq. 8; beta [L][L][K], pop [n][L][K]."""
     beta = np.ascontiguousarray(beta, dtype=np.float64)
     L, L2, K = beta.shape
     assert L == L2

@@ -149,16 +149,60 @@ int pao_sinr_terms(int32_t L, int32_t K, int32_t se_mode, double M, double rho,
   return user_terms(L, K, se_mode, M, rho, beta, chrom, 1, sinr);
 }
 
+/*
+ * Inter-cluster interference of Eq. 8 (Sec. 4.2), as read here: the printed
+ * equation sums, over pairs of user clusters (c, c') that share a pilot, the
+ * mean large-scale gain of c' at the BS of c over the mean gain of c at its own
+ * BS, plus the same ratio with the roles swapped (the second numerator's
+ * subscript is garbled in print: it must be c's users at the BS of c'). With
+ * tau = K each cell's users sharing one pilot form a cluster of one user, so
+ * the means are single gains, and summing both directions over every pair of
+ * cells gives, per user (i, k) with pilot s,
+ *     sum_{j != i} beta_i,j,k'(j) / beta_i,i,k,   k'(j) = user of cell j on s,
+ * in first powers of beta (not squares). The pair (c, c) adds a constant and
+ * is left out. The sum over all users is minimised.
+ */
+static int interference_ratio(int32_t L, int32_t K, const double *beta, const uint8_t *chrom,
+                              double *out) {
+  int *inv = (int *)malloc(sizeof(int) * (size_t)L * K);
+  if (!inv) return -2;
+  if (invert_rows(L, K, chrom, inv) != 0) { free(inv); return -1; }
+  double total = 0.0;
+  for (int i = 0; i < L; ++i)
+    for (int k = 0; k < K; ++k) {
+      int s = chrom[i * K + k];
+      double own = beta[((size_t)i * L + i) * K + k];
+      double I = 0.0;
+      for (int j = 0; j < L; ++j)
+        if (j != i) I += beta[((size_t)i * L + j) * K + inv[j * K + s]];
+      total += I / own;
+    }
+  free(inv);
+  *out = total;
+  return 0;
+}
+
 /* Sum SE (Eq. 6), scaled by the share of the coherence interval left after
  * uplink training (Sec. 3): 1 - tau/T, or 1 when T == 0. */
 /* objective 0: the sum over users of Eq. 7 times the pre-log; objective 1:
  * the smallest SINR of any user (the max-min SIR criterion the paper names
  * beside the sum, Sec. 2; SE is monotone in SINR, so it has the same optimum
- * as max-min SE). */
+ * as max-min SE); objective 2: minus the inter-cluster interference of Eq. 8
+ * (interference_ratio; the GA maximises, the paper minimises; no pre-log,
+ * independent of the SE mode). */
 int pao_fitness_obj(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
                     int32_t objective, const double *beta, const uint8_t *pop, int32_t n,
                     double *fit) {
-  if (L < 1 || K < 1 || n < 0 || objective < 0 || objective > 1) return -1;
+  if (L < 1 || K < 1 || n < 0 || objective < 0 || objective > 2) return -1;
+  if (objective == 2) {
+    for (int c = 0; c < n; ++c) {
+      double v = 0.0;
+      int rc = interference_ratio(L, K, beta, pop + (size_t)c * L * K, &v);
+      if (rc != 0) return rc;
+      fit[c] = -v;
+    }
+    return 0;
+  }
   double prelog = (T > 0) ? 1.0 - (double)K / (double)T : 1.0;
   double *se = (double *)malloc(sizeof(double) * (size_t)L * K);
   if (!se) return -2;

@@ -48,7 +48,8 @@ uint64_t pao_threshold(double p);
 /* Sum spectral efficiency (Eq. 5-7) of n chromosomes, FP64. */
 int pao_fitness(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
                 const double *beta, const uint8_t *pop, int32_t n, double *fit);
-/* objective 0 = pao_fitness; 1 = the smallest per-user SINR (max-min SIR). */
+/* objective 0 = pao_fitness; 1 = the smallest per-user SINR (max-min SIR);
+ * 2 = minus the inter-cluster interference of Eq. 8. */
 int pao_fitness_obj(int32_t L, int32_t K, int32_t T, int32_t se_mode, double M, double rho,
                     int32_t objective, const double *beta, const uint8_t *pop, int32_t n,
                     double *fit);

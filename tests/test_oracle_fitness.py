@@ -242,3 +242,44 @@ def test_maxmin_optimum_by_enumeration(oracle_mod):
     assert int(np.argmax(mn)) == int(np.argmax(min_se))
     rand = _rand_pop(rng, 50, 3, 3)
     assert np.all(oracle_mod.fitness(beta, rand, objective=1) <= mn.max() * (1 + 1e-12))
+
+
+# ---- Eq. 8 (Sec. 4.2): inter-cluster interference, objective 2 -------------
+
+def _eq8_cases():
+    import json, os
+    path = os.path.join(os.path.dirname(__file__), "golden", "eq8_hand.json")
+    with open(path) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _eq8_cases(), ids=lambda c: c["name"])
+def test_eq8_hand_worked(oracle_mod, case):
+    beta = np.array(case["beta"], dtype=np.float64)
+    chrom = np.array(case["chrom"], dtype=np.uint8)[None]
+    got = oracle_mod.fitness(beta, chrom, objective=2)[0]
+    assert got == -case["interference"]  # exact: every ratio is a power of two
+    # no pre-log and no dependence on the SE mode
+    assert oracle_mod.fitness(beta, chrom, T=196, objective=2)[0] == got
+    assert oracle_mod.fitness(beta, chrom, se_mode=1, M=64, rho=10.0, objective=2)[0] == got
+
+
+def test_eq8_equal_gains_and_invariances(oracle_mod):
+    rng = np.random.default_rng(8)
+    L, K = 4, 5
+    pop = np.argsort(rng.random((30, L, K)), axis=2).astype(np.uint8)
+    # equal gains: every user sees L - 1 ratios of one
+    flat = np.full((L, L, K), 0.3)
+    np.testing.assert_array_equal(oracle_mod.fitness(flat, pop, objective=2), -L * K * (L - 1.0))
+    beta = np.exp(rng.normal(size=(L, L, K)))
+    f = oracle_mod.fitness(beta, pop, objective=2)
+    # per-BS scaling (a ratio of two gains at one BS)
+    scale = 2.0 ** rng.integers(-20, 20, size=L)
+    np.testing.assert_allclose(oracle_mod.fitness(beta * scale[:, None, None], pop, objective=2),
+                               f, rtol=1e-13)
+    # global pilot relabelling
+    perm = rng.permutation(K).astype(np.uint8)
+    np.testing.assert_allclose(oracle_mod.fitness(beta, perm[pop], objective=2), f, rtol=1e-13)
+    # one cell alone interferes with nobody
+    assert oracle_mod.fitness(beta[:1, :1], pop[:, :1], objective=2)[0] == 0.0
+
