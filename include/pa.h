@@ -78,8 +78,13 @@ enum { PA_SE_ASYMPTOTIC = 0, PA_SE_FINITE_M = 1 };
  * PA_OBJ_MIN_SINR: the smallest SINR of any user (SIR in asymptotic mode):
  *   the max-min SIR criterion the paper names beside the sum (Sec. 2).  SE is
  *   monotone in SINR, so this is also the max-min SE assignment; the SINR
- *   keeps FP32 precision where log2(1 + SINR) of a weak user would not. */
-enum { PA_OBJ_SUM_SE = 0, PA_OBJ_MIN_SINR = 1 };
+ *   keeps FP32 precision where log2(1 + SINR) of a weak user would not.
+ * PA_OBJ_INTERCLUSTER: minus the inter-cluster interference of Eq. 8
+ *   (Sec. 4.2), read with tau = K as clusters of one user per (cell, pilot):
+ *   -sum over users (i, k) of sum_{j != i} beta_ijk' / beta_iik, first powers
+ *   of beta, k' the user of cell j on the pilot of (i, k); no pre-log;
+ *   asymptotic mode only (PA_EINVAL with PA_SE_FINITE_M). */
+enum { PA_OBJ_SUM_SE = 0, PA_OBJ_MIN_SINR = 1, PA_OBJ_INTERCLUSTER = 2 };
 
 typedef struct pa_context pa_context;
 typedef struct pa_instance pa_instance;
@@ -95,7 +100,7 @@ typedef struct pa_server pa_server;
  *   M        BS antennas (finite-M mode), >= 1
  *   rho      transmit SNR (finite-M mode), > 0
  *   se_mode  PA_SE_ASYMPTOTIC or PA_SE_FINITE_M
- *   objective  PA_OBJ_SUM_SE (0) or PA_OBJ_MIN_SINR
+ *   objective  PA_OBJ_SUM_SE (0), PA_OBJ_MIN_SINR (1) or PA_OBJ_INTERCLUSTER (2)
  *   beta     HOST [L][L][K] FP64, finite; > 0 in asymptotic mode, >= 0 in
  *            finite-M mode; per BS l the ratio max/min over the nonzero
  *            entries must not exceed 2^60 (FP32 range after normalisation)

@@ -38,6 +38,7 @@ SE_ASYMPTOTIC = 0
 SE_FINITE_M = 1
 OBJ_SUM_SE = 0
 OBJ_MIN_SINR = 1
+OBJ_INTERCLUSTER = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libpa_amd.so")

@@ -58,8 +58,11 @@ pa_status validate_problem(const pa_problem *pr) {
   if (pr->T < 0) return fail(PA_EINVAL, "T=%d is negative", pr->T);
   if (pr->se_mode != PA_SE_ASYMPTOTIC && pr->se_mode != PA_SE_FINITE_M)
     return fail(PA_EINVAL, "unknown se_mode %d", pr->se_mode);
-  if (pr->objective != PA_OBJ_SUM_SE && pr->objective != PA_OBJ_MIN_SINR)
+  if (pr->objective != PA_OBJ_SUM_SE && pr->objective != PA_OBJ_MIN_SINR &&
+      pr->objective != PA_OBJ_INTERCLUSTER)
     return fail(PA_EINVAL, "unknown objective %d", pr->objective);
+  if (pr->objective == PA_OBJ_INTERCLUSTER && pr->se_mode != PA_SE_ASYMPTOTIC)
+    return fail(PA_EINVAL, "the Eq. 8 objective has no finite-M form (se_mode must be asymptotic)");
   const bool asym = pr->se_mode == PA_SE_ASYMPTOTIC;
   if (asym && pr->L < 2)
     return fail(PA_EINVAL, "asymptotic SE needs L >= 2 (one cell has no interference)");

@@ -26,26 +26,30 @@
 
 namespace pa {
 
-// Objective: the sum of the SE terms (Eq. 7), or with mn the minimum of the
+// Objective `mn`: 0 the sum of the SE terms (Eq. 7); 1 the minimum of the
 // users' SINR (max-min SIR; the SINR is b2 * rcp(den), about 1e-7 relative,
-// where log2(1 + x) in FP32 would lose the small terms).  Both reductions are
-// taken in the canonical order.
-__device__ __forceinline__ float obj_init(bool mn) { return mn ? __builtin_inff() : 0.0f; }
-__device__ __forceinline__ float obj_add(float acc, float se, bool mn) {
-  return mn ? __builtin_fminf(acc, se) : acc + se;
+// where log2(1 + x) in FP32 would lose the small terms); 2 the sum of minus
+// the users' interference-to-signal ratios of Eq. 8 (tables of first-power
+// gains: b2 is the own gain, I the sum of the interferers').  The reductions
+// are taken in the canonical order; only objective 0 is scaled by the pre-log.
+__device__ __forceinline__ float obj_init(int mn) { return mn == 1 ? __builtin_inff() : 0.0f; }
+__device__ __forceinline__ float obj_add(float acc, float se, int mn) {
+  return mn == 1 ? __builtin_fminf(acc, se) : acc + se;
 }
 
-__device__ __forceinline__ float se_asym(float b2, float I, bool mn = false) {
+__device__ __forceinline__ float se_asym(float b2, float I, int mn = 0) {
+  if (mn == 2) return -(I * __builtin_amdgcn_rcpf(b2));
   const float r = __builtin_amdgcn_rcpf(I);
-  return mn ? b2 * r : __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
+  return mn == 1 ? b2 * r : __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
 }
 
+// (objective 2 takes no finite-M form: the host rejects that combination)
 __device__ __forceinline__ float se_finite(float b2, float I, float S, float a, float c2,
-                                           bool mn = false) {
+                                           int mn = 0) {
   const float t = __builtin_fmaf(a, S, 1.0f);
   const float den = __builtin_fmaf(c2, t, I);
   const float r = __builtin_amdgcn_rcpf(den);
-  return mn ? b2 * r : __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
+  return mn == 1 ? b2 * r : __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
 }
 
 // Inverse rows of the chromosomes of a round, stored pilot-major:
@@ -85,7 +89,7 @@ __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int
 template <int LT, int MODE>
 __device__ __forceinline__ float row_term_exact(const char *lds, const uint32_t (&A)[LT],
                                                 uint32_t off, uint32_t t1_bytes, int l,
-                                                float a_l, float c2_l, bool mn = false) {
+                                                float a_l, float c2_l, int mn = 0) {
   float I = 0.0f, b2 = 0.0f;
 #pragma unroll
   for (int j = 0; j < LT; ++j) {
@@ -110,7 +114,7 @@ __device__ __forceinline__ float row_term_exact(const char *lds, const uint32_t 
 template <int LMAX, int MODE>
 __device__ __forceinline__ float row_term_generic(const char *lds, const uint32_t (&A)[LMAX],
                                                   uint32_t off, uint32_t t1_bytes, int L, int l,
-                                                  float a_l, float c2_l, bool mn = false) {
+                                                  float a_l, float c2_l, int mn = 0) {
   float I = 0.0f, b2 = 0.0f, S = 0.0f;
 #pragma unroll
   for (int j = 0; j < LMAX; ++j) {
@@ -193,7 +197,7 @@ template <int LT, int TPT, int MODE, int TR, int NT>
 __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, float *sT,
                                                 const float *__restrict__ T2,
                                                 const float *__restrict__ T1,
-                                                const float *__restrict__ lconst, bool mn = false) {
+                                                const float *__restrict__ lconst, int mn = 0) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);  // bytes per (cell, BS row)
   constexpr int CELLB = TR * ROWB;                      // bytes per cell in the tile
   const char *lds = reinterpret_cast<const char *>(sT);
@@ -297,7 +301,7 @@ __device__ __forceinline__ void load_quad(const float *__restrict__ T2, int L, i
 // increasing l.  Same arithmetic, same order, same bits as lane_sum_exact.
 template <int LT, int TPT>
 __device__ __forceinline__ float lane_sum_quad(const uint8_t *ip, bool active, const float *sQ,
-                                               bool mn = false) {
+                                               int mn = 0) {
   constexpr int LP = quad_rows<LT>();
   constexpr int CELLB = TPT * LP * 4;  // bytes per cell
   typedef float f4 __attribute__((ext_vector_type(4)));
@@ -352,7 +356,7 @@ template <int LT, int TPT, int MODE>
 __device__ __forceinline__ float lane_sum_split(const uint8_t *sInv, int ql, bool active, int rg,
                                                 int RS, const float *sT, float *sSe,
                                                 const float *__restrict__ lconst,
-                                                bool mn = false) {
+                                                int mn = 0) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   constexpr int CELLB = LT * ROWB;
   const char *lds = reinterpret_cast<const char *>(sT);
@@ -405,7 +409,7 @@ __device__ __forceinline__ float lane_sum_split(const uint8_t *sInv, int ql, boo
 template <int LT, int TPT>
 __device__ __forceinline__ float lane_sum_split_quad(const uint8_t *sInv, int ql, bool active,
                                                      int rg, int RS, const float *sQ, float *sSe,
-                                                     bool mn = false) {
+                                                     int mn = 0) {
   constexpr int LP = quad_rows<LT>();
   constexpr int CELLB = TPT * LP * 4;
   typedef float f4 __attribute__((ext_vector_type(4)));
@@ -472,7 +476,7 @@ template <int LT, int TPT, int MODE>
 __device__ __forceinline__ float tiled_row_se(const uint32_t (&A)[LT], const uint8_t *ip,
                                               bool active, const char *lds, const float *sOwn,
                                               const float *__restrict__ lconst, int l, int lr,
-                                              bool mn) {
+                                              int mn) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   const uint32_t ownr = ip[l];  // in bounds for inactive lanes too
   const uint32_t own = active ? ownr : 0u;
@@ -498,7 +502,7 @@ template <int LT, int TPT, int MODE, int TR>
 __device__ __forceinline__ float tiled_rows(uint32_t (&A)[LT], const uint8_t *ip, bool active,
                                             const float *sT, const float *sOwn,
                                             const float *__restrict__ lconst, int t, float acc,
-                                            bool mn = false) {
+                                            int mn = 0) {
   const char *lds = reinterpret_cast<const char *>(sT);
   const int rows = (t + 1) * TR <= LT ? TR : LT - t * TR;
   // Branch-free over the tile's rows (a row past the last BS row of a short
@@ -528,7 +532,7 @@ template <int LT, int TPT, int MODE, int TR, int T>
 __device__ __forceinline__ void tiled_terms(uint32_t (&A)[LT], const uint8_t *ip, bool active,
                                             const float *sT, const float *sOwn,
                                             const float *__restrict__ lconst,
-                                            float (&hold)[LT - TR], bool mn) {
+                                            float (&hold)[LT - TR], int mn) {
   static_assert(T >= 1 && T * TR < LT, "tile T holds BS rows past tile 0");
   constexpr int rows = (T + 1) * TR <= LT ? TR : LT - T * TR;
   const char *lds = reinterpret_cast<const char *>(sT);
@@ -550,7 +554,7 @@ template <int LT, int TPT, int MODE, int TR, int T>
 __device__ __forceinline__ void tiled_visit(int t, uint32_t (&A)[LT], const uint8_t *ip,
                                             bool active, const float *sT, const float *sOwn,
                                             const float *__restrict__ lconst, float &acc,
-                                            float (&hold)[LT - TR], bool mn) {
+                                            float (&hold)[LT - TR], int mn) {
   constexpr int NT = (LT + TR - 1) / TR;
   if (t == T) {
     if constexpr (T == 0)
@@ -574,7 +578,7 @@ __device__ __forceinline__ float lane_sum_tiled(const uint8_t *ip, bool active, 
                                                 const float *sOwn, const float *__restrict__ T2z,
                                                 const float *__restrict__ T1,
                                                 const float *__restrict__ lconst, int &held,
-                                                bool mn = false) {
+                                                int mn = 0) {
   constexpr int NT = (LT + TR - 1) / TR;
   static_assert(NT >= 2, "tiled sums hold more than one tile");
   uint32_t A[LT];
@@ -655,7 +659,7 @@ __device__ __forceinline__ float lane_sum_tiled_hook(const uint8_t *ip, bool act
                                                      const float *__restrict__ T2z,
                                                      const float *__restrict__ T1,
                                                      const float *__restrict__ lconst, int &held,
-                                                     bool mn, Hook &hook) {
+                                                     int mn, Hook &hook) {
   constexpr int NT = (LT + TR - 1) / TR;
   static_assert(NT >= 2, "tiled sums hold more than one tile");
   uint32_t A[LT];
@@ -701,7 +705,7 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
                                                   const float *__restrict__ T2,
                                                   const float *__restrict__ T1,
                                                   const float *__restrict__ lconst,
-                                                  bool mn = false) {
+                                                  int mn = 0) {
   const int NT = (L + TR - 1) / TR;
   const int ROWB = TP * 4 * (MODE == 1 ? 2 : 1);
   const int CELLB = TR * ROWB;
@@ -742,14 +746,14 @@ __device__ __forceinline__ float lane_sum_generic(const uint8_t *ip, bool active
 // Per-chromosome pairwise tree over pilots of the lanes' sums, then * prelog:
 // fit_out[c] for c < nc.  Called by every thread; ends with a barrier.
 template <int S>
-__device__ __forceinline__ float add_from_lane_plus(float v, bool mn) {
+__device__ __forceinline__ float add_from_lane_plus(float v, int mn) {
   // v (+ or min) the value of lane + S in the same row of 16 lanes; DPP row_shl:S
   const int o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + S, 0xF, 0xF, false);
   return obj_add(v, __int_as_float(o), mn);
 }
 
 __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, int nc, int K,
-                                             float prelog, float *fit_out, bool mn = false) {
+                                             float prelog, float *fit_out, int mn = 0) {
   // pairwise tree over the K pilot sums of a chromosome, one lane per pilot:
   // for s = P/2, P/4, .., 1 (P = K rounded up to a power of two) lane p < s
   // adds lane p + s when p + s < K; the result is in lane 0.
@@ -769,7 +773,7 @@ __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, 
     if (K >= 8) v = add_from_lane_plus<4>(v, mn);
     if (K >= 4) v = add_from_lane_plus<2>(v, mn);
     if (K >= 2) v = add_from_lane_plus<1>(v, mn);
-    if (active && p == 0 && c < nc) gp(fit_out)[c] = mn ? v : prelog * v;
+    if (active && p == 0 && c < nc) gp(fit_out)[c] = mn ? v : prelog * v;  // pre-log: objective 0
     __syncthreads();  // the caller's next LDS writes follow every lane's reads
     return;
   }

@@ -387,7 +387,7 @@ __device__ __forceinline__ void run_task(const GenInst &I, const GenTask &task_i
   const int out = gen < 0 ? 0 : 1 - (gen & 1);
   float *const fit_out = fit_buf(I, out) + task.s0;
   const float prelog = I.prelog;
-  const bool mn = I.objective != 0;
+  const int mn = I.objective;
   if (task.kind != kTaskElite && task.inst != st.inst) {
     // every thread passed a barrier since the tables were last read
     if constexpr (P::kQuad)
@@ -687,7 +687,7 @@ __device__ __forceinline__ void gen_tasks_tiled(const GenInst *insts, const GenT
       const SelRegs r = sel_issue(I, next, g);
       PrepHook hook{&I, &next, g, &r, sSel, sChild};
       acc = lane_sum_tiled_hook<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z,
-                                                   I.T1, I.lconst, st.tile, I.objective != 0,
+                                                   I.T1, I.lconst, st.tile, I.objective,
                                                    hook);
       if (mutate && I.K != 32)
         mutation_codes_block(sCode, next.s1 - next.s0, I.L * I.K, I.K, I.ga, (uint32_t)g,
@@ -695,11 +695,11 @@ __device__ __forceinline__ void gen_tasks_tiled(const GenInst *insts, const GenT
     } else {
       NoTileHook hook;
       acc = lane_sum_tiled_hook<LT, TPT, MODE, TR>(sInv + q * LT, active, sT, sOwn, I.T2z,
-                                                   I.T1, I.lconst, st.tile, I.objective != 0,
+                                                   I.T1, I.lconst, st.tile, I.objective,
                                                    hook);
     }
     float *const fit_out = fit_buf(I, 1 - (g & 1)) + task.s0;
-    reduce_round(sE, acc, active, nc, I.K, I.prelog, fit_out, I.objective != 0);
+    reduce_round(sE, acc, active, nc, I.K, I.prelog, fit_out, I.objective);
     ready = pipe;
     task = next;
   }
@@ -895,9 +895,9 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
     const bool active = q / K < nc;
     const float acc =
         lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, I.T2, I.T1, I.lconst,
-                                     I.objective != 0);
+                                     I.objective);
     const int out = gen < 0 ? 0 : 1 - (gen & 1);
-    reduce_round(sE, acc, active, nc, K, I.prelog, fit_buf(I, out) + task.s0, I.objective != 0);
+    reduce_round(sE, acc, active, nc, K, I.prelog, fit_buf(I, out) + task.s0, I.objective);
   }
 }
 

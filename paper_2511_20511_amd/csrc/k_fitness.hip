@@ -26,7 +26,7 @@ struct FitArgs {
   float *fit;
   int n, L, K, TP;
   float prelog;
-  int objective;  // 0: sum of the SE terms, 1: their minimum
+  int objective;  // 0: sum of the SE terms, 1: their minimum, 2: minus the Eq. 8 ratios
   int tile_rows;  // generic variant: BS rows per LDS tile
   int inv_off;    // LDS byte offset of the inverse rows
   int e_off;      // LDS byte offset of the per-(c, p) sums
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   const int CPR = BLOCK / K;
   const int q = threadIdx.x;
   const int rounds = (a.n + CPR - 1) / CPR;
-  const bool mn = a.objective != 0;
+  const int mn = a.objective;
 
   if constexpr (NT > 1) {
     // Tiled table: tiles outermost.  The workgroup's rounds are taken in
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(1024) void k_fitness_generic(FitArgs a) {
     build_inverse(sStage, nc * L, L, K, sInv);
     __syncthreads();
     const bool active = q / K < nc;
-    const bool mn = a.objective != 0;
+    const int mn = a.objective;
     const float acc = lane_sum_generic<LMAX, MODE>(sInv + q * L, active, L, TP, TR, sT, a.T2,
                                                    a.T1, a.lconst, mn);
     reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn);

@@ -6,7 +6,9 @@
 // everything one BS hears by the same power of two leaves the asymptotic SINR
 // of Eq. 5 unchanged and is exact in FP64; the squares then fit FP32.  For the
 // finite-M bound the SNR is rescaled by the inverse power (rho_l = rho 2^e_l)
-// so every product rho*beta is unchanged.
+// so every product rho*beta is unchanged.  For the inter-cluster interference
+// of Eq. 8 (objective 2) the tables hold the scaled gains themselves, not their
+// squares (its ratios are of first powers, and are unchanged by the scaling).
 #include "pa_dev.h"
 #include "pa_internal.h"
 
@@ -15,7 +17,8 @@ namespace pa {
 constexpr int kPrepBlock = 256;
 
 __global__ __launch_bounds__(kPrepBlock) void k_prep(const double *__restrict__ beta, int L, int K,
-                                                      int TP, int finite_m, double rho, int M,
+                                                      int TP, int finite_m, int first_power,
+                                                      double rho, int M,
                                                       float *__restrict__ T2,
                                                       float *__restrict__ T1,
                                                       float *__restrict__ T2z,
@@ -42,7 +45,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(const double *__restrict__ 
     double b = 0.0;
     if (p < K) b = ldexp(row[j * K + p], -e);
     const size_t dst = ((size_t)j * L + l) * TP + p;
-    const float sq = (float)(b * b);
+    const float sq = first_power ? (float)b : (float)(b * b);
     T2[dst] = sq;
     T2z[dst] = j == l ? 0.0f : sq;
     if (j == l) Town[l * TP + p] = sq;
@@ -60,8 +63,9 @@ __global__ __launch_bounds__(kPrepBlock) void k_prep(const double *__restrict__ 
 
 hipError_t launch_prep(const DevProblem &p, int M, double rho, hipStream_t s) {
   const int finite_m = p.se_mode == 1;
+  const int first_power = p.objective == 2;
   hipLaunchKernelGGL(k_prep, dim3(p.L), dim3(kPrepBlock), 0, s, p.beta, p.L, p.K, p.TP, finite_m,
-                     rho, M, p.T2, p.T1, p.T2z, p.Town, p.lconst);
+                     first_power, rho, M, p.T2, p.T1, p.T2z, p.Town, p.lconst);
   return hipGetLastError();
 }
 

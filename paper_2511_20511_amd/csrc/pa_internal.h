@@ -50,7 +50,7 @@ inline int pad_pilots(int K) {
 struct DevProblem {
   int L = 0, K = 0, TP = 0;  // cells, users (= pilots), padded pilot stride
   int se_mode = 0;
-  int objective = 0;         // 0: sum of the SE terms, 1: their minimum
+  int objective = 0;         // 0: sum of the SE terms, 1: their minimum, 2: Eq. 8
   float prelog = 1.0f;       // 1 - tau/T, or 1
   double *beta = nullptr;    // [L][L][K] FP64 as given
   float *T2 = nullptr;       // [L(cell j)][L(BS l)][TP] normalised beta squared (FP32)

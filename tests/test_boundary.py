@@ -129,6 +129,10 @@ def test_objective_is_validated():
     import paper_2511_20511_amd as pa
     from paper_2511_20511_amd import scenario
     d = scenario.make_drop(7, 4, seed=1, instance_id=0)
-    for obj, want in ((0, 0), (1, 0), (2, -1), (-1, -1)):
+    for obj, want in ((0, 0), (1, 0), (2, 0), (3, -1), (-1, -1)):
         h = pa._Host(d.beta, d.user_xy, d.bs_xy, 196, 1, 1.0, 0, obj)
+        assert pa.lib().pa_problem_check(ctypes.byref(h.c)) == want
+    # the Eq. 8 objective has no finite-M form
+    for mode, want in ((0, 0), (1, -1)):
+        h = pa._Host(d.beta, d.user_xy, d.bs_xy, 196, 64, 10.0, mode, 2)
         assert pa.lib().pa_problem_check(ctypes.byref(h.c)) == want
