@@ -538,7 +538,7 @@ def main():
     from paper_2511_20511_amd import scenario
     w = dict(scenario.WORKLOADS[args.workload])
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.experiment and not args.calibrate_copy:
         procs = min(usable_cores(), 16)
         log(f"cpu baseline: oracle sample on 1 core, then {procs} processes ...")
         cpu = cpu_baseline(w, args.cpu_sample_gens, procs)
