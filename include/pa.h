@@ -212,15 +212,18 @@ pa_status pa_ga_step(pa_instance *inst, const pa_ga_params *params, int32_t gen,
  * assignment).  Children are built, written and evaluated in LDS by one
  * fused generation kernel.  The first call with given parameters builds a
  * plan: when every task of a generation fits on the device at once (small
- * instances) all generations run in one cooperative launch separated by
- * grid barriers, with the tasks' size autotuned on the instance itself;
- * otherwise the whole solve (one launch per generation) is captured into a
- * hipGraph.  Later calls with the same parameters replay the plan.  The
- * form and the shape never change a result bit.  The environment variable
+ * instances) all generations run in one launch, either separated by grid
+ * barriers (persistent form) or, when the population and the table fit one
+ * CU's LDS, in one workgroup that keeps them there (one-workgroup form), the
+ * form and the tasks' size autotuned on the instance itself; otherwise the
+ * whole solve (one launch per generation) is captured into a hipGraph.
+ * Later calls with the same parameters replay the plan.  The form and the
+ * shape never change a result bit.  The environment variable
  * PA_PERSIST_BLOCK=256 or 512, read when a plan is built, restricts the
  * autotuner to that workgroup size (for reproducible profiles; unset, both
- * are tried).  PA_EINTERNAL if a grid barrier wait times out (the results
- * are then invalid).  Blocking. */
+ * are tried); PA_SMALL_FORM=persistent or workgroup keeps only that form.
+ * PA_EINTERNAL if a grid barrier wait times out (the results are then
+ * invalid).  Blocking. */
 pa_status pa_solve(pa_instance *inst, const pa_ga_params *params, pa_result *out, void *stream);
 
 /* Many independent solves in one: n instances of the same context, each with
@@ -238,8 +241,8 @@ pa_status pa_solve_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
  * loops until an unspecified termination condition holds); same kernels and
  * bits as pa_solve.
  *   pa_solve_begin  seeding, initial population and its fitness.  Async.
- *   pa_solve_next   ngens more generations (one cooperative launch for the
- *                   persistent form, else one fused launch each); at most
+ *   pa_solve_next   ngens more generations (one launch in the persistent
+ *                   and one-workgroup forms, else one fused launch each); at most
  *                   params->gens in total since the last begin.  Async.
  *   pa_solve_state  best chromosome and fitness of the current population,
  *                   trace[0..gens_done]; *gens_done = generations run so far.
@@ -312,10 +315,12 @@ pa_status pa_fitness_shaped(pa_instance *inst, const uint8_t *d_pop, int32_t n, 
 
 /* Execution form of the current solve plan of `inst` (inst != NULL, after
  * pa_solve or pa_solve_begin) or of the context's batch plan (inst == NULL,
- * after pa_solve_batch): *persistent = 1 for the single cooperative launch,
- * 0 for the captured graph; threads per workgroup, children per task (of the
- * first class, for its first instance's K) and workgroups per launch.  Any
- * output pointer may be NULL.  PA_EINVAL when there is no plan. */
+ * after pa_solve_batch): *persistent = 1 for the persistent form (one launch,
+ * grid barriers), 2 for the one-workgroup form (one workgroup per instance,
+ * population in LDS), 0 for the captured graph; threads per workgroup,
+ * children per task (of the first class, for its first instance's K; all
+ * children in the one-workgroup form) and workgroups per launch.  Any output
+ * pointer may be NULL.  PA_EINVAL when there is no plan. */
 pa_status pa_solve_shape(pa_context *ctx, pa_instance *inst, int32_t *persistent, int32_t *block,
                          int32_t *children_per_task, int32_t *workgroups);
 

@@ -24,7 +24,7 @@ LIB = os.path.join(HERE, "libpa_amd.so")
 SOURCES = [(f, f, []) for f in ("api.cpp", "k_prep.hip", "k_fitness.hip", "k_ga.hip",
                                 "k_kmeans.hip", "k_gen.hip", "solve.cpp", "server.cpp",
                                 "k_exhaustive.hip", "k_peak.hip", "k_noalloc.hip",
-                                "k_island.hip")]
+                                "k_island.hip", "k_gen_wg.hip")]
 # the unrolled generation kernels: one object per (cells, SE mode, form), so
 # that they compile in parallel
 SOURCES += [("k_gen_unrolled.hip", f"k_gen_L{L}_m{m}_{form}.hip",

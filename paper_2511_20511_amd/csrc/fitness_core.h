@@ -752,8 +752,11 @@ __device__ __forceinline__ float add_from_lane_plus(float v, int mn) {
   return obj_add(v, __int_as_float(o), mn);
 }
 
-__device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, int nc, int K,
-                                             float prelog, float *fit_out, int mn = 0) {
+// reduce_round writing each chromosome's value through out(c, v) (LDS or
+// global); same tree, same bits.
+template <class Out>
+__device__ __forceinline__ void reduce_round_to(float *sE, float acc, bool active, int nc, int K,
+                                                float prelog, Out &&out, int mn = 0) {
   // pairwise tree over the K pilot sums of a chromosome, one lane per pilot:
   // for s = P/2, P/4, .., 1 (P = K rounded up to a power of two) lane p < s
   // adds lane p + s when p + s < K; the result is in lane 0.
@@ -773,7 +776,7 @@ __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, 
     if (K >= 8) v = add_from_lane_plus<4>(v, mn);
     if (K >= 4) v = add_from_lane_plus<2>(v, mn);
     if (K >= 2) v = add_from_lane_plus<1>(v, mn);
-    if (active && p == 0 && c < nc) gp(fit_out)[c] = mn ? v : prelog * v;  // pre-log: objective 0
+    if (active && p == 0 && c < nc) out(c, mn ? v : prelog * v);  // pre-log: objective 0
     __syncthreads();  // the caller's next LDS writes follow every lane's reads
     return;
   }
@@ -788,8 +791,14 @@ __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, 
       sE[q] = v;
     }
   }
-  if (active && p == 0 && c < nc) gp(fit_out)[c] = mn ? v : prelog * v;
+  if (active && p == 0 && c < nc) out(c, mn ? v : prelog * v);
   __syncthreads();
+}
+
+__device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, int nc, int K,
+                                             float prelog, float *fit_out, int mn = 0) {
+  reduce_round_to(sE, acc, active, nc, K, prelog, [fit_out](int c, float v) { gp(fit_out)[c] = v; },
+                  mn);
 }
 
 }  // namespace pa

@@ -318,24 +318,34 @@ __device__ __forceinline__ uint32_t group_codes_x8(bool act, int q, int u, int L
 }
 
 // Mutation codes of the children of slots [s0, s0 + nc) into `codes` (child c
-// at byte c*LK) with the whole workgroup: one thread per (child, group of 32
-// genes) when there are more groups than an eighth of the workgroup (the
-// early-stopping group_codes), else eight lanes per group (group_codes_x8).
-// No barrier: the caller's next one publishes the codes.
+// at byte c*LK) with the workgroup's threads from `base` (a multiple of the
+// wave size) on: eight lanes per group of 32 genes (group_codes_x8: all eight
+// decision blocks at once, short dependence chains) when the groups fit
+// those threads in at most x8_passes passes, else one thread per (child,
+// group) (the early-stopping group_codes: fewer Philox blocks, longer
+// chains).  Threads below base return at once.  No barrier: the caller's next
+// one publishes the codes.
 __device__ __forceinline__ void mutation_codes_block(uint8_t *codes, int nc, int LK, int K,
                                                      const DevGa &ga, uint32_t gen, int s0,
-                                                     int block) {
+                                                     int block, int base = 0,
+                                                     int x8_passes = 1) {
+  const int t0 = (int)threadIdx.x - base, avail = block - base;
+  if (t0 < 0) return;
   const int ng = (LK + 31) >> 5;
   const int total = nc * ng;
-  if (8 * total <= block) {
-    const int t = (int)threadIdx.x >> 3, u = (int)threadIdx.x & 7;
-    const bool act = t < total;
-    const int c = act ? t / ng : 0, q = act ? t - c * ng : 0;
-    const uint32_t v = group_codes_x8(act, q, u, LK, K, ga, gen, (uint32_t)(s0 + c));
-    if (act && 32 * q + 4 * u < LK) store_code_word(codes + (size_t)c * LK, LK, 8 * q + u, v);
+  if (8 * total <= avail * x8_passes) {
+    // every lane of a participating wave runs every pass (the eight lanes of
+    // a group shuffle with each other)
+    for (int p0 = 0; p0 < total; p0 += avail >> 3) {
+      const int t = p0 + (t0 >> 3), u = t0 & 7;
+      const bool act = t < total;
+      const int c = act ? t / ng : 0, q = act ? t - c * ng : 0;
+      const uint32_t v = group_codes_x8(act, q, u, LK, K, ga, gen, (uint32_t)(s0 + c));
+      if (act && 32 * q + 4 * u < LK) store_code_word(codes + (size_t)c * LK, LK, 8 * q + u, v);
+    }
     return;
   }
-  for (int t = threadIdx.x; t < total; t += block) {
+  for (int t = t0; t < total; t += avail) {
     const int c = t / ng, q = t - c * ng;
     uint32_t out[8];
     group_codes(q, LK, K, ga, gen, (uint32_t)(s0 + c), out);

@@ -720,7 +720,7 @@ __global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
   gen_tasks_exact<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, st, a.gens);
 }
 
-// ---- persistent form: generations [g0, g1) in one cooperative launch -------
+// ---- persistent form: generations [g0, g1) in one launch, grid barriers ------
 //
 // Every workgroup keeps the same chunk of tasks in every generation (so the
 // table of its instance stays in LDS) and the generations are separated by a

@@ -183,8 +183,8 @@ hipError_t launch_init_batch(const GenInst *insts, int ninst, int maxN, hipStrea
 // gen = -1: fitness of the initial populations (the class's eval tasks).
 hipError_t launch_gen(const GenInst *insts, const GenClass &c, int gen, const DeviceInfo &dev,
                       hipStream_t s);
-// Persistent form: generations [g0, g1) of a class in one cooperative launch
-// of `grid` workgroups separated by grid barriers on the counter `bar`
+// Persistent form: generations [g0, g1) of a class in one launch of `grid`
+// co-resident workgroups separated by grid barriers on the counter `bar`
 // (zeroed before the launch); a barrier wait that times out sets *err.  With
 // best != 0 it ends with the best of each of the first `ninst` instances.
 struct PersistLaunch {
@@ -196,6 +196,17 @@ struct PersistLaunch {
 // persistent kernel (0 when the class has none) and launches nothing.
 hipError_t launch_gen_persist(const GenInst *insts, const GenClass &c, const PersistLaunch &pl,
                               const DeviceInfo &dev, int *capacity, hipStream_t s);
+// One-workgroup form: generations [g0, g1) of ninst instances of one class
+// (L, TP, mode), one workgroup of `block` threads each, with the population,
+// its fitness and the table in LDS (g0 = -1: from the initial population; with
+// best, the result at each instance's last generation).  lds_out != null: only
+// the LDS bytes for the largest instance (maxN, maxK) into *lds_out, or
+// hipErrorInvalidValue when no such kernel variant exists.
+hipError_t launch_gen_wg(const GenInst *d_insts, int ninst, int L, int TP, int mode, int block,
+                         int g0, int g1, bool best, int maxN, int maxK, int *lds_out,
+                         hipStream_t s);
+// Most elites the one-workgroup form ranks (one wave).
+int wg_max_elites();
 // Best of each instance's population after generation `gen` (or after its
 // last generation when gen < 0); closes the trace at that generation.
 hipError_t launch_best_batch(const GenInst *insts, int ninst, int gen, hipStream_t s,

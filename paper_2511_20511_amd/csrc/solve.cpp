@@ -6,9 +6,13 @@
 //    last population) is captured once into a hipGraph and replayed;
 //  - persistent: when the plan has one class whose tasks all fit on the
 //    device at once (small instances: the generation kernel would be a few
-//    microseconds of latency), every generation runs inside one cooperative
-//    launch separated by grid barriers, so the table stays in LDS and no
-//    per-generation launch is paid.
+//    microseconds of latency), every generation runs inside one launch of
+//    co-resident workgroups separated by grid barriers, so the table stays
+//    in LDS and no per-generation launch is paid;
+//  - one-workgroup: when an instance's population and table fit one CU's
+//    LDS, one workgroup per instance runs every generation with the
+//    population resident in LDS (no grid barrier, no global round trip).
+//    The autotuner times it beside the persistent shapes.
 // Either way a solve ends with one copy of the results.
 #include <algorithm>
 #include <array>
@@ -49,6 +53,8 @@ struct SolvePlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool persist = false;          // persistent form (one class, co-resident tasks)
+  int wg_block = 0;              // one-workgroup form: its threads (0: not this form)
+  int wg_maxN = 0, wg_maxK = 0;  // its largest instance
   int pgrid = 0;                 // its workgroups
   uint32_t *d_sync = nullptr;    // [0]: grid-barrier counter, [1]: barrier time-out flag
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -161,52 +167,81 @@ pa_status make_class(SolvePlan *pl, const ClassKey &key, const std::vector<int> 
 hipError_t launch_start(SolvePlan *pl, hipStream_t s);
 hipError_t launch_persist(SolvePlan *pl, const DeviceInfo &dev, int g0, int g1, bool best,
                           hipStream_t s);
+hipError_t launch_wg(SolvePlan *pl, int block, int g0, int g1, bool best, hipStream_t s);
 
-// Autotuning of the persistent form: every candidate shape (block size from
-// `blocks`, each with its co-residency cap; children per task = block / K /
-// div for div = 1, 2, 4, ..., all tasks co-resident) runs
-// the start and the first 8 and 40 generations of the plan's own instances;
-// the shape whose cost extrapolated to the plan's generation count is
-// smallest is kept (within 3%, the larger workgroup).  Shapes change the
-// schedule, never a result bit.
+// Autotuning of the small-instance forms: every persistent shape (block size
+// from `blocks`, each with its co-residency cap; children per task = block /
+// K / div for div = 1, 2, 4, ..., all tasks co-resident) and every
+// one-workgroup shape (`wg_blocks`) runs the start and the first 8 and 40
+// generations of the plan's own instances; the shape whose cost extrapolated
+// to the plan's generation count is smallest is kept (within 3%: the
+// one-workgroup form, which leaves the other CUs free, then the larger
+// workgroup).  PA_SMALL_FORM=persistent or workgroup keeps only that form's
+// shapes.  Shapes and forms change the schedule, never a result bit.
 pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
                           const std::vector<int> &members, const std::vector<GenInst> &hi,
-                          const std::vector<std::pair<int, int>> &blocks) {
+                          const std::vector<std::pair<int, int>> &blocks,
+                          const std::vector<int> &wg_blocks) {
   int maxK = 0;
   for (int i : members) maxK = std::max(maxK, hi[i].K);
+  const char *form_env = std::getenv("PA_SMALL_FORM");
+  const std::string form = form_env ? form_env : "";
   std::vector<PlanClass> cands;
-  for (const auto &bc : blocks) {
-    const int block = bc.first, cap = bc.second;
-    int last_tasks = -1;
-    for (int div = 1; div <= std::max(1, block / maxK); div *= 2) {
-      const int nt = count_tasks(members, pl->insts, pl->params, block, div);
-      if (nt > cap) break;
-      if (nt == last_tasks) continue;
-      last_tasks = nt;
-      PlanClass pc;
-      pa_status st = make_class(pl, key, members, hi, Shape{block, div}, ctx->info.cus, &pc);
-      if (st != PA_OK) return st;
-      cands.push_back(pc);
+  if (form != "workgroup") {
+    for (const auto &bc : blocks) {
+      const int block = bc.first, cap = bc.second;
+      int last_tasks = -1;
+      for (int div = 1; div <= std::max(1, block / maxK); div *= 2) {
+        const int nt = count_tasks(members, pl->insts, pl->params, block, div);
+        if (nt > cap) break;
+        if (nt == last_tasks) continue;
+        last_tasks = nt;
+        PlanClass pc;
+        pa_status st = make_class(pl, key, members, hi, Shape{block, div}, ctx->info.cus, &pc);
+        if (st != PA_OK) return st;
+        cands.push_back(pc);
+      }
     }
   }
-  if (cands.empty()) return set_error(PA_EINTERNAL, "no persistent shape");
-  pl->persist = true;
+  // candidates: persistent shapes (wg = 0, index into cands), then
+  // one-workgroup shapes (wg = threads)
+  struct Cand {
+    size_t pc;
+    int wg;
+  };
+  std::vector<Cand> all;
+  for (size_t c = 0; c < cands.size(); ++c) all.push_back({c, 0});
+  if (form != "persistent")
+    for (int b : wg_blocks) all.push_back({0, b});
+  if (all.empty()) return set_error(PA_EINTERNAL, "no persistent or one-workgroup shape");
+  auto select = [&](const Cand &cd) {
+    pl->persist = cd.wg == 0;
+    pl->wg_block = cd.wg;
+    if (cd.wg == 0) {
+      pl->classes.assign(1, cands[cd.pc]);
+      pl->pgrid = cands[cd.pc].c.ntasks;
+    } else {
+      pl->classes.clear();
+    }
+  };
   size_t best = 0;
-  if (cands.size() > 1) {
+  if (all.size() > 1) {
     // each shape's start-up and per-generation cost from a short and a long
     // run (best of two each), extrapolated to the plan's generation count
     hipStream_t cs = ctx->stream;
     const int gs = std::min(pl->Gmax, 8), gl = std::min(pl->Gmax, 40);
-    std::vector<float> ests(cands.size(), 0.0f);
-    for (size_t c = 0; c < cands.size(); ++c) {
-      pl->classes.assign(1, cands[c]);
-      pl->pgrid = cands[c].c.ntasks;
+    std::vector<float> ests(all.size(), 0.0f);
+    for (size_t c = 0; c < all.size(); ++c) {
+      select(all[c]);
       float t[2] = {0.0f, 0.0f};
       for (int k = 0; k < (gl > gs ? 2 : 1); ++k) {
         for (int rep = 0; rep < 2; ++rep) {
           PTRY(launch_start(pl, cs), "tuning");
           PTRY(hipEventRecord(pl->ev0, cs), "hipEventRecord");
-          PTRY(launch_persist(pl, ctx->info, -1, k == 0 ? gs : gl, false, cs), "tuning");
+          if (all[c].wg)
+            PTRY(launch_wg(pl, all[c].wg, -1, k == 0 ? gs : gl, false, cs), "tuning");
+          else
+            PTRY(launch_persist(pl, ctx->info, -1, k == 0 ? gs : gl, false, cs), "tuning");
           PTRY(hipEventRecord(pl->ev1, cs), "hipEventRecord");
           PTRY(hipEventSynchronize(pl->ev1), "hipEventSynchronize");
           float ms = 0.0f;
@@ -222,17 +257,20 @@ pa_status tune_persistent(SolvePlan *pl, pa_context *ctx, const ClassKey &key,
       ests[c] = est;
     }
     // estimates within 3% of the best count as equal (run-to-run noise is of
-    // that order); among them the larger workgroup, then the cheaper, wins
+    // that order); among them the one-workgroup form, then the larger
+    // workgroup, then the cheaper, wins
+    auto block_of = [&](const Cand &cd) { return cd.wg ? cd.wg : cands[cd.pc].c.block; };
     const float lo = *std::min_element(ests.begin(), ests.end());
-    for (size_t c = 0; c < cands.size(); ++c) {
+    for (size_t c = 0; c < all.size(); ++c) {
       if (ests[c] > lo * 1.03f) continue;
-      if (ests[best] > lo * 1.03f || cands[c].c.block > cands[best].c.block ||
-          (cands[c].c.block == cands[best].c.block && ests[c] < ests[best]))
+      const bool bwg = all[best].wg != 0, cwg = all[c].wg != 0;
+      if (ests[best] > lo * 1.03f || (cwg && !bwg) ||
+          (cwg == bwg && (block_of(all[c]) > block_of(all[best]) ||
+                          (block_of(all[c]) == block_of(all[best]) && ests[c] < ests[best]))))
         best = c;
     }
   }
-  pl->classes.assign(1, cands[best]);
-  pl->pgrid = cands[best].c.ntasks;
+  select(all[best]);
   return PA_OK;
 }
 
@@ -518,12 +556,37 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
         pblocks.push_back({block, cap});
     }
   }
+  // one-workgroup form: the same class, when the largest instance's
+  // population, fitness, inverse rows, codes and table fit one CU's LDS and
+  // its elites one wave's ranking
+  std::vector<int> wgblocks;
+  if (!pblocks.empty()) {
+    const ClassKey &key = groups[0].first;
+    int maxN = 0, maxK = 0, maxE = 0;
+    for (int i : groups[0].second) {
+      maxN = std::max(maxN, hi[i].N);
+      maxK = std::max(maxK, hi[i].K);
+      maxE = std::max(maxE, hi[i].E);
+    }
+    pl->wg_maxN = maxN;
+    pl->wg_maxK = maxK;
+    for (int block : {256, 512}) {
+      if (only != 0 && block != only) continue;
+      int lds = 0;
+      if (maxE <= wg_max_elites() &&
+          launch_gen_wg(nullptr, 0, key.L, key.TP, key.mode, block, 0, 0, false, maxN, maxK, &lds,
+                        nullptr) == hipSuccess &&
+          lds <= 160 * 1024)
+        wgblocks.push_back(block);
+    }
+  }
   PTRY(alloc(pl, &pl->d_sync, 2), "hipMalloc(plan)");
   PTRY(hipMemset(pl->d_sync, 0, 2 * sizeof(uint32_t)), "hipMemset");
   PTRY(hipEventCreate(&pl->ev0), "hipEventCreate");
   PTRY(hipEventCreate(&pl->ev1), "hipEventCreate");
   if (!pblocks.empty()) {
-    pa_status st = tune_persistent(pl, ctx, groups[0].first, groups[0].second, hi, pblocks);
+    pa_status st =
+        tune_persistent(pl, ctx, groups[0].first, groups[0].second, hi, pblocks, wgblocks);
     if (st != PA_OK) return st;
   } else {
     for (auto &grp : groups) {
@@ -541,7 +604,7 @@ pa_status build_plan(pa_context *ctx, int n, pa_instance *const *insts,
   pl->h_fit.resize(n);
   pl->h_trace.resize((size_t)n * TG);
   pl->h_best.resize(best_total);
-  if (pl->persist) {
+  if (pl->persist || pl->wg_block) {
     *out = guard.release();
     return PA_OK;
   }
@@ -632,6 +695,13 @@ hipError_t launch_persist(SolvePlan *pl, const DeviceInfo &dev, int g0, int g1, 
   return launch_gen_persist(pl->d_insts, pl->classes[0].c, L, dev, nullptr, s);
 }
 
+// One-workgroup launch of generations [g0, g1) of every instance of the plan.
+hipError_t launch_wg(SolvePlan *pl, int block, int g0, int g1, bool best, hipStream_t s) {
+  const GenInst &I0 = pl->h_inst[0];
+  return launch_gen_wg(pl->d_insts, (int)pl->insts.size(), I0.L, I0.TP, I0.se_mode, block, g0, g1,
+                       best, pl->wg_maxN, pl->wg_maxK, nullptr, s);
+}
+
 // Seeding, initial population and (persistent form) the time-out flag.
 hipError_t launch_start(SolvePlan *pl, hipStream_t s) {
   hipError_t e = launch_kmeans_batch(pl->d_insts, pl->d_which, pl->nwhich, s);
@@ -642,7 +712,10 @@ hipError_t launch_start(SolvePlan *pl, hipStream_t s) {
 
 pa_status run_plan(SolvePlan *pl, const DeviceInfo &dev, hipStream_t s, pa_result *results) {
   PTRY(hipEventRecord(pl->ev0, s), "hipEventRecord");
-  if (pl->persist) {
+  if (pl->wg_block) {
+    PTRY(launch_start(pl, s), "launching the solve");
+    PTRY(launch_wg(pl, pl->wg_block, -1, pl->Gmax, true, s), "one-workgroup solve kernel");
+  } else if (pl->persist) {
     PTRY(launch_start(pl, s), "launching the solve");
     PTRY(launch_persist(pl, dev, -1, pl->Gmax, true, s), "persistent generation kernel");
   } else {
@@ -721,8 +794,10 @@ pa_status check_batch(pa_context *ctx, int32_t n, pa_instance *const *insts,
 // generations (next), best of the current populations (state).
 pa_status plan_begin(SolvePlan *pl, const DeviceInfo &dev, hipStream_t s) {
   hipError_t e = launch_start(pl, s);
+  if (e == hipSuccess && pl->wg_block) e = launch_wg(pl, pl->wg_block, -1, 0, false, s);
   if (e == hipSuccess && pl->persist) e = launch_persist(pl, dev, -1, 0, false, s);
-  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess && !pl->persist; ++c)
+  for (size_t c = 0; c < pl->classes.size() && e == hipSuccess && !pl->persist && !pl->wg_block;
+       ++c)
     e = launch_gen(pl->d_insts, pl->classes[c].c, -1, dev, s);
   if (e != hipSuccess) return hip_error(e, "solve begin");
   pl->cur_gen = 0;
@@ -735,9 +810,11 @@ pa_status plan_next(SolvePlan *pl, const DeviceInfo &dev, int ngens, hipStream_t
   if (ngens < 0 || pl->cur_gen + ngens > pl->Gmax)
     return set_error(PA_EINVAL, "%d more generations exceed gens=%d (done %d)", ngens, pl->Gmax,
                      pl->cur_gen);
-  if (pl->persist) {
+  if (pl->persist || pl->wg_block) {
     if (ngens == 0) return PA_OK;
-    hipError_t e = launch_persist(pl, dev, pl->cur_gen, pl->cur_gen + ngens, false, s);
+    hipError_t e = pl->wg_block
+                       ? launch_wg(pl, pl->wg_block, pl->cur_gen, pl->cur_gen + ngens, false, s)
+                       : launch_persist(pl, dev, pl->cur_gen, pl->cur_gen + ngens, false, s);
     if (e != hipSuccess) return hip_error(e, "solve next");
     pl->cur_gen += ngens;
     pl->done_gen = pl->cur_gen;
@@ -914,6 +991,13 @@ pa_status pa_solve_shape(pa_context *ctx, pa_instance *in, int32_t *persistent, 
                          int32_t *children_per_task, int32_t *workgroups) {
   const SolvePlan *pl = in ? in->plan : (ctx ? ctx->batch_plan : nullptr);
   if (!pl) return set_error(PA_EINVAL, "no solve plan (solve first)");
+  if (pl->wg_block) {
+    if (persistent) *persistent = 2;
+    if (block) *block = pl->wg_block;
+    if (children_per_task) *children_per_task = pl->params[0].pop - pl->params[0].elite;
+    if (workgroups) *workgroups = (int32_t)pl->insts.size();
+    return PA_OK;
+  }
   const PlanClass &pc = pl->classes[0];
   const int K = pl->insts[0]->p.K;
   if (persistent) *persistent = pl->persist ? 1 : 0;
