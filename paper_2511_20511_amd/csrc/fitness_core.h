@@ -37,10 +37,14 @@ __device__ __forceinline__ float obj_add(float acc, float se, int mn) {
   return mn == 1 ? __builtin_fminf(acc, se) : acc + se;
 }
 
+// Branch-free in the objective: marked unpredictable, the final choice stays a
+// select; as a uniform branch around the log it would split each BS row into
+// blocks of its own and keep adjacent rows' LDS reads from pairing (ds_read2).
 __device__ __forceinline__ float se_asym(float b2, float I, int mn = 0) {
-  if (mn == 2) return -(I * __builtin_amdgcn_rcpf(b2));
-  const float r = __builtin_amdgcn_rcpf(I);
-  return mn == 1 ? b2 * r : __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
+  const float r = __builtin_amdgcn_rcpf(mn == 2 ? b2 : I);
+  const float se = __builtin_amdgcn_logf(__builtin_fmaf(b2, r, 1.0f));
+  const float q = (mn == 2 ? -I : b2) * r;
+  return __builtin_unpredictable(mn == 0) ? se : q;
 }
 
 // (objective 2 takes no finite-M form: the host rejects that combination)
