@@ -349,8 +349,9 @@ pa_status pa_population_kmeans(pa_instance *inst, int32_t clusters, int32_t kmea
  * from binary tournaments among its members, cell-axis crossover and swap
  * mutation as in pa_ga_step.  The random streams are pa_ga_step's with the
  * island index in bits 16..23 of the block counter: with every label 0 the
- * result is pa_ga_step's, bit for bit.  pop <= 4096, 1 <= clusters <= 16.
- * Async. */
+ * result is pa_ga_step's, bit for bit.  A position whose label lies outside
+ * [0, clusters) is copied unchanged.  pop <= 4096, 1 <= clusters <= 16.
+ * Async (device scratch of 16 pop bytes, stream-ordered). */
 pa_status pa_island_step(pa_instance *inst, const pa_ga_params *params, int32_t clusters,
                          int32_t gen, const int32_t *d_labels, const uint8_t *d_pop_in,
                          const float *d_fit_in, uint8_t *d_pop_out, void *stream);

@@ -17,8 +17,9 @@
 //     among its members, crossover and mutation as in the panmictic step;
 //   - the random streams are those of the panmictic step with the island
 //     index in bits 16..23 of the block counter, so C = 1 is the panmictic GA.
-// Kernels: k_pop_kmeans (one workgroup per population) and k_island_step (one
-// workgroup per island, the processing unit of an island in Sec. 5).
+// Kernels: k_pop_kmeans (one workgroup per population), k_island_plan (one
+// workgroup per island, the processing unit of an island in Sec. 5) and
+// k_island_build (the positions of all islands in chunks).
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -171,6 +172,13 @@ __global__ __launch_bounds__(kKmThreads) void k_pop_kmeans(PopKmArgs a) {
 }
 
 // ---------------------------------------------------------------- island step
+//
+// Two kernels: k_island_plan (one workgroup per island) finds the island's
+// members, its elites and each child's tournaments and cut, and writes one
+// record per position; k_island_build (positions in chunks, many workgroups)
+// builds every position from its record: rows from the parents (word
+// gathers), mutation codes drawn per (child, group of 32 genes) with the
+// island's block offset, swaps per row.
 struct IslandArgs {
   const uint8_t *pin;
   const float *fin;
@@ -181,9 +189,16 @@ struct IslandArgs {
   DevGa ga;
 };
 
+// What position s of the next generation is built from: rows [0, cutg / K)
+// from `first`, the others from `rest` (packed first | rest << 16); `island`
+// its island; elite != 0: a copy of `first`, no mutation.
+struct IslandRec {
+  int32_t parents, cutg, island, elite;
+};
+
 constexpr int kIslandThreads = 256;
 
-__global__ __launch_bounds__(kIslandThreads) void k_island_step(IslandArgs a) {
+__global__ __launch_bounds__(kIslandThreads) void k_island_plan(IslandArgs a, IslandRec *rec) {
   __shared__ int32_t sM[kIslandMaxN];
   __shared__ uint64_t sRed[kIslandThreads / kWave];
   __shared__ int32_t sCount[kIslandThreads / kWave + 1];
@@ -209,7 +224,6 @@ __global__ __launch_bounds__(kIslandThreads) void k_island_step(IslandArgs a) {
   }
   const int n = base;
   if (n == 0) return;
-  const uint32_t boff = (uint32_t)c << 16;
   int Ec = 0;
   if (a.E > 0) {
     Ec = (int)((2 * (int64_t)a.E * n + N) / (2 * (int64_t)N));
@@ -227,14 +241,14 @@ __global__ __launch_bounds__(kIslandThreads) void k_island_step(IslandArgs a) {
     }
     best = block_max_u64(best, sRed);
     prev = best;
-    __syncthreads();
-    const int src = (int)key_index(best), dst = sM[e];
-    for (int i = tid; i < LK; i += T)
-      gp(a.pout)[(size_t)dst * LK + i] = gp(a.pin)[(size_t)src * LK + i];
+    if (tid == 0) {
+      const int src = (int)key_index(best);
+      rec[sM[e]] = IslandRec{src | (src << 16), LK, c, 1};
+    }
   }
   // children, one thread each: pair (first, first + 1) of island positions
   // t >= Ec; selection words keyed by the pair's first slot
-  const bool mutate = K >= 2 && a.ga.thr_mut != 0;
+  const uint32_t boff = (uint32_t)c << 16;
   for (int t = Ec + tid; t < n; t += T) {
     const int first = Ec + ((t - Ec) & ~1);
     const bool second = ((t - Ec) & 1) != 0;
@@ -254,26 +268,86 @@ __global__ __launch_bounds__(kIslandThreads) void k_island_step(IslandArgs a) {
     const bool cross = L >= 2 && hit(b1.x, a.ga.thr_cross);
     const int cut = cross ? 1 + (int)bounded(b1.y, (uint32_t)(L - 1)) : L;
     const int pf = second ? p2 : p1, pr = second ? p1 : p2;
-    const int slot = sM[t];
-    uint8_t *dst = a.pout + (size_t)slot * LK;
-    for (int g = 0; g < LK; ++g)
-      gp(dst)[g] = gp(a.pin)[(size_t)(g < cut * K ? pf : pr) * LK + g];
-    if (mutate) {
-      for (int q = 0; 32 * q < LK; ++q) {
-        uint32_t code[8];
-        uint32_t hits = group_codes(q, LK, K, a.ga, a.gen, (uint32_t)slot, code, boff);
-        while (hits != 0u) {
-          const int b = __builtin_ctz(hits);
-          hits &= hits - 1u;
-          const int cd = (int)code_byte(code, b);
-          const int i = 32 * q + b, j = i / K, k = i - j * K;
-          const uint8_t x = gp(dst)[j * K + k];
-          gp(dst)[j * K + k] = gp(dst)[j * K + cd - 1];
-          gp(dst)[j * K + cd - 1] = x;
-        }
-      }
+    rec[sM[t]] = IslandRec{pf | (pr << 16), cut * K, c, 0};
+  }
+}
+
+// Every record a copy of its own position (what a position whose label names
+// no island receives).
+__global__ void k_island_fill(IslandRec *rec, int N, int LK) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < N) rec[i] = IslandRec{i | (i << 16), LK, 0, 1};
+}
+
+// Positions per build workgroup for chromosomes of LK genes (two LK-byte
+// buffers of them in LDS).
+int island_chunk(int LK) { return std::max(1, std::min(64, 16384 / LK)); }
+
+__global__ __launch_bounds__(kIslandThreads) void k_island_build(IslandArgs a,
+                                                                 const IslandRec *rec,
+                                                                 int cpw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int L = a.L, K = a.K, LK = L * K, tid = threadIdx.x, block = blockDim.x;
+  const int s0 = blockIdx.x * cpw, nc = min(cpw, a.N - s0);
+  const int cb = (cpw * LK + 15) / 16 * 16;
+  uint8_t *child = smem;
+  uint8_t *codes = smem + cb;
+  int32_t *sSel = reinterpret_cast<int32_t *>(smem + 2 * cb);  // parents, cutg per position
+  int32_t *sIsl = sSel + 2 * cpw;                                // island, or -1 for an elite
+  if (tid < nc) {
+    const IslandRec r = rec[s0 + tid];
+    sSel[2 * tid] = r.parents;
+    sSel[2 * tid + 1] = r.cutg;
+    sIsl[tid] = r.elite ? -1 : r.island;
+  }
+  __syncthreads();
+  const bool mutate = K >= 2 && a.ga.thr_mut != 0;
+  // mutation codes of the children (not of the elites), one thread per
+  // (position, group of 32 genes), the island index in the block counter
+  if (mutate) {
+    const int ng = (LK + 31) >> 5;
+    for (int t = tid; t < nc * ng; t += block) {
+      const int cpos = t / ng, q = t - cpos * ng;
+      const int isl = sIsl[cpos];
+      if (isl < 0) continue;
+      uint32_t out[8];
+      group_codes(q, LK, K, a.ga, a.gen, (uint32_t)(s0 + cpos), out, (uint32_t)isl << 16);
+      uint8_t *dst = codes + (size_t)cpos * LK;
+#pragma unroll
+      for (int w = 0; w < 8; ++w)
+        if (32 * q + 4 * w < LK) store_code_word(dst, LK, 8 * q + w, out[w]);
     }
   }
+  // rows [0, cut) from the first parent and [cut, L) from the other: two
+  // byte ranges per position, a team of threads per range
+  {
+    const int nr = 2 * nc;
+    int lg = 0;
+    while ((2 << lg) * nr <= block) ++lg;
+    const int tpr = 1 << lg;
+    const int sub = tid & (tpr - 1);
+    for (int r0 = tid >> lg; r0 < nr; r0 += block >> lg) {
+      const int cpos = r0 >> 1;
+      const uint32_t pr = (uint32_t)sSel[2 * cpos];
+      const int cutg = sSel[2 * cpos + 1];
+      if ((r0 & 1) == 0)
+        gather_range(ByteRange{a.pin + (size_t)(pr & 0xFFFFu) * LK, cutg}, child, cpos * LK, sub,
+                     tpr);
+      else
+        gather_range(ByteRange{a.pin + (size_t)(pr >> 16) * LK + cutg, LK - cutg}, child,
+                     cpos * LK + cutg, sub, tpr);
+    }
+  }
+  __syncthreads();
+  if (mutate) {
+    for (int r = tid; r < nc * L; r += block) {
+      if (sIsl[r / L] < 0) continue;
+      const int off = r * K;
+      apply_swaps(child + off, codes + off, off, K);
+    }
+    __syncthreads();
+  }
+  store_bytes(a.pout + (size_t)s0 * LK, child, nc * LK);
 }
 
 __global__ void k_trace_best(const float *fit, int N, float *trace_g) {
@@ -306,11 +380,23 @@ hipError_t launch_pop_kmeans(const uint8_t *pop, const float *fit, int N, int LK
   return launch_status(ae);
 }
 
+// One generation of every island: records (each a copy of its position),
+// plan (one workgroup per island), build (positions in chunks).  rec: N
+// records of device scratch.
 hipError_t launch_island_step(const DevProblem &p, const DevGa &ga, int C, uint32_t gen,
                               const int32_t *labels, const uint8_t *pin, const float *fin,
-                              uint8_t *pout, hipStream_t s) {
+                              uint8_t *pout, IslandRec *rec, hipStream_t s) {
   IslandArgs a{pin, fin, pout, labels, ga.N, ga.E, p.L, p.K, gen, ga};
-  hipLaunchKernelGGL(k_island_step, dim3(C), dim3(kIslandThreads), 0, s, a);
+  hipLaunchKernelGGL(k_island_fill, dim3((ga.N + 255) / 256), dim3(256), 0, s, rec, ga.N,
+                     p.L * p.K);
+  hipLaunchKernelGGL(k_island_plan, dim3(C), dim3(kIslandThreads), 0, s, a, rec);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int LK = p.L * p.K, cpw = island_chunk(LK);
+  const int cb = (cpw * LK + 15) / 16 * 16;
+  const size_t lds = 2 * (size_t)cb + 3 * sizeof(int32_t) * cpw;
+  hipLaunchKernelGGL(k_island_build, dim3((ga.N + cpw - 1) / cpw), dim3(kIslandThreads), lds, s,
+                     a, rec, cpw);
   return hipGetLastError();
 }
 
@@ -361,9 +447,15 @@ pa_status pa_island_step(pa_instance *in, const pa_ga_params *g, int32_t cluster
   if (st != PA_OK) return st;
   if ((st = island_check(in, g->pop, clusters, 1)) != PA_OK) return st;
   if ((st = use_device(in->ctx)) != PA_OK) return st;
-  ITRY(launch_island_step(in->p, ga_from_params(g), clusters, (uint32_t)gen, d_labels, d_pop_in,
-                          d_fit_in, d_pop_out, (hipStream_t)stream),
-       "pa_island_step");
+  hipStream_t s = (hipStream_t)stream;
+  IslandRec *rec = nullptr;
+  ITRY(hipMallocAsync(reinterpret_cast<void **>(&rec), sizeof(IslandRec) * g->pop, s),
+       "pa_island_step scratch");
+  const hipError_t e = launch_island_step(in->p, ga_from_params(g), clusters, (uint32_t)gen,
+                                          d_labels, d_pop_in, d_fit_in, d_pop_out, rec, s);
+  const hipError_t ef = hipFreeAsync(rec, s);
+  ITRY(e, "pa_island_step");
+  ITRY(ef, "pa_island_step scratch");
   return PA_OK;
 }
 
@@ -384,10 +476,11 @@ pa_status pa_island_solve(pa_instance *in, const pa_ga_params *g, int32_t cluste
   float *fit[2] = {nullptr, nullptr};
   int32_t *lab = nullptr, *bidx = nullptr;
   float *trace = nullptr, *bfit = nullptr;
+  IslandRec *rec = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto release = [&]() {
     for (void *p : {(void *)pop[0], (void *)pop[1], (void *)fit[0], (void *)fit[1], (void *)lab,
-                    (void *)bidx, (void *)trace, (void *)bfit})
+                    (void *)bidx, (void *)trace, (void *)bfit, (void *)rec})
       if (p) (void)hipFree(p);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
@@ -401,6 +494,7 @@ pa_status pa_island_solve(pa_instance *in, const pa_ga_params *g, int32_t cluste
   if (e == hipSuccess) e = hipMalloc(&bidx, sizeof(int32_t));
   if (e == hipSuccess) e = hipMalloc(&trace, sizeof(float) * (G + 1));
   if (e == hipSuccess) e = hipMalloc(&bfit, sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&rec, sizeof(IslandRec) * N);
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) e = hipMemsetAsync(lab, 0, sizeof(int32_t) * N, s);
@@ -418,7 +512,8 @@ pa_status pa_island_solve(pa_instance *in, const pa_ga_params *g, int32_t cluste
         (gen == 0 || (recluster_every > 0 && gen % recluster_every == 0)))
       e = launch_pop_kmeans(pop[a], fit[a], N, LK, clusters, kmeans_iters, lab, nullptr, s);
     if (e == hipSuccess)
-      e = launch_island_step(in->p, ga, clusters, (uint32_t)gen, lab, pop[a], fit[a], pop[b], s);
+      e = launch_island_step(in->p, ga, clusters, (uint32_t)gen, lab, pop[a], fit[a], pop[b], rec,
+                             s);
     if (e == hipSuccess) e = launch_fitness(in->p, pop[b], N, fit[b], fs, in->ctx->info, s);
   }
   const int fin = G & 1;

@@ -119,3 +119,32 @@ def test_one_island_is_solve():
     with pytest.raises(pa.PaError):
         pa.pa_island_solve(inst, pa.GaParams(pop=5000, gens=1), 5, 3)
     inst.close()
+
+
+def test_island_step_labels_outside_the_islands():
+    """Positions labelled outside [0, clusters) are copied unchanged; the
+    islands' children still come from their own members."""
+    torch = need_gpu()
+    import paper_2511_20511_amd as pa
+    rng = np.random.default_rng(77)
+    L, K, N, C = 7, 4, 60, 3
+    d, inst = _inst(pa, L, K)
+    pop = rand_pop(rng, N, L, K)
+    fit = rng.normal(size=N).astype(np.float32)
+    lab = rng.integers(0, C, size=N).astype(np.int32)
+    lab[:C] = np.arange(C)
+    stray = np.array([5, 17, 40])
+    lab[stray] = [C, -1, 99]
+    params = pa.GaParams(pop=N, gens=3, elite=2, p_cross=1.0, p_mut=0.0, seed=4, instance_id=0)
+    out = torch.zeros((N, L, K), dtype=torch.uint8, device="cuda")
+    flush("island step with stray labels")
+    pa.pa_island_step(inst, params, C, 1, to_dev(lab, torch), to_dev(pop, torch),
+                      to_dev(fit, torch), out)
+    got = out.cpu().numpy()
+    assert np.array_equal(got[stray], pop[stray])
+    for c in range(C):
+        members = np.flatnonzero(lab == c)
+        for s in members:  # without mutation every row is a member's row
+            for j in range(L):
+                assert any(np.array_equal(got[s, j], pop[m, j]) for m in members)
+    inst.close()
