@@ -326,6 +326,78 @@ def run_fitness(pa, scenario, torch, peaks):
     return out
 
 
+def run_objectives(pa, scenario, torch, oracle_mod):
+    """pa_fitness of one resident population (L=19, K=16, n=65536) under each
+    objective: sum SE (Eq. 7), max-min SIR, Eq. 8; FP32 against FP64 on a sample."""
+    import numpy as np
+    out = []
+    stream = torch.cuda.current_stream()
+    L, K, n = 19, 16, 65536
+    d = scenario.make_drop(L, K, seed=1, instance_id=0)
+    ctx = pa.pa_context_create(0)
+    for obj, name in ((pa.OBJ_SUM_SE, "sum_se"), (pa.OBJ_MIN_SINR, "min_sinr"),
+                      (pa.OBJ_INTERCLUSTER, "eq8_intercluster")):
+        inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=196, objective=obj)
+        pop = torch.empty((n, L, K), dtype=torch.uint8, device="cuda")
+        pa.pa_kmeans_init(inst, pa.GaParams(pop=n, kmeans_frac=0.0, seed=3), pop)
+        fit = torch.empty(n, dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            pa.pa_fitness(inst, pop, n, fit)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(20):
+            pa.pa_fitness(inst, pop, n, fit)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        got = fit[:256].cpu().numpy().astype(np.float64)
+        want = oracle_mod.fitness(d.beta, pop[:256].cpu().numpy(), T=196, objective=obj)
+        out.append({"objective": name, "L": L, "K": K, "n": n, "avg_launch_us": ms * 1e3,
+                    "evals_per_s": n / (ms * 1e-3),
+                    "fp32_vs_fp64_rel_err_max": float(np.max(np.abs(got - want) / np.abs(want)))})
+        log(f"objective {name}: {ms * 1e3:.1f} us per launch of {n}")
+        inst.close()
+    ctx.close()
+    return out
+
+
+def run_island(pa, scenario, torch, oracle_mod, name="single_L19_K16", clusters=5, every=3,
+               reps=5):
+    """The PK-means GA (Alg. 2; C = 5 islands re-clustered every 3 generations,
+    Sec. 6.1) on one instance beside the panmictic solve of the same parameters."""
+    import numpy as np
+    w = dict(scenario.WORKLOADS[name])
+    L, K, N, G, E = w["L"], w["K"], w["N"], w["gens"], w["E"]
+    ctx = pa.pa_context_create(0)
+    d = scenario.make_drop(L, K, seed=w["seed"], instance_id=0)
+    inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=w["T"], M=w["M"],
+                                 rho=scenario.snr_to_rho(w["snr_db"]))
+    p = pa.GaParams(pop=N, gens=G, elite=E, p_cross=w["p_cross"], p_mut=w["p_mut"],
+                    kmeans_frac=w["kmeans_frac"], p_init=w["p_init"], seed=w["seed"],
+                    instance_id=0)
+    res, _ = pa.pa_island_solve(inst, p, clusters, every)
+    torch.cuda.synchronize()
+    lat, dev = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res, labels = pa.pa_island_solve(inst, p, clusters, every)
+        lat.append(time.perf_counter() - t0)
+        dev.append(res.device_ms)
+    pan = pa.pa_solve(inst, p)
+    want = float(oracle_mod.fitness(d.beta, res.best[None], T=w["T"])[0])
+    counts = np.bincount(labels, minlength=clusters)
+    out = {"workload": name, "clusters": clusters, "recluster_every": every,
+           "solve_ms_median": float(np.median(lat) * 1e3), "solve_device_ms": float(np.median(dev)),
+           "best_fit": float(res.best_fit), "panmictic_best_fit": float(pan.best_fit),
+           "best_fp32_vs_fp64_rel_err": abs(res.best_fit - want) / abs(want),
+           "last_island_sizes": [int(x) for x in counts]}
+    log(f"island GA {name} C={clusters} R={every}: {out['solve_ms_median']:.2f} ms per solve, "
+        f"best {res.best_fit:.2f} (panmictic {pan.best_fit:.2f})")
+    inst.close()
+    ctx.close()
+    return out
+
+
 def run_serve(pa, scenario, torch, name, warm_s, seconds, plain_s):
     """Poisson arrivals of uneven solves through the continuous-batching server
     (warm-up, then the measured window): solves/s and p50/p99 latency
@@ -517,6 +589,8 @@ def main():
     ap.add_argument("--plain-seconds", type=float, default=3.0,
                     help="the plain path runs on this prefix of the arrival trace")
     ap.add_argument("--no-fitness", action="store_true", help="skip the pa_fitness roofline lines")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the objectives and island GA lines")
     ap.add_argument("--experiment", default="", choices=["", "convergence"],
                     help="only run this experiment and print its JSON line")
     ap.add_argument("--drops", type=int, default=256)
@@ -627,6 +701,9 @@ def main():
                           for s in args.single.split(",") if s]
     if not args.no_fitness:
         line["fitness"] = run_fitness(pa, scenario, torch, peaks)
+    if not args.no_next:
+        line["objectives"] = run_objectives(pa, scenario, torch, oracle)
+        line["island"] = run_island(pa, scenario, torch, oracle)
     if args.batch:
         line["batch"] = [run_batch_extra(pa, scenario, torch, oracle, b)
                          for b in args.batch.split(",") if b]
