@@ -17,7 +17,8 @@
 //     among its members, crossover and mutation as in the panmictic step;
 //   - the random streams are those of the panmictic step with the island
 //     index in bits 16..23 of the block counter, so C = 1 is the panmictic GA.
-// Kernels: k_pop_kmeans (one workgroup per population), k_island_plan (one
+// Kernels: k_pop_kmeans / k_pop_kmeans_lds (one workgroup per population; the
+// second with the population resident in LDS), k_island_plan (one
 // workgroup per island, the processing unit of an island in Sec. 5) and
 // k_island_build (the positions of all islands in chunks).
 #include <algorithm>
@@ -171,6 +172,261 @@ __global__ __launch_bounds__(kKmThreads) void k_pop_kmeans(PopKmArgs a) {
   if (tid == 0 && a.iters) *gp(a.iters) = it;
 }
 
+// The same clustering with the population resident in LDS (rows padded with
+// zero genes to LKP bytes, a multiple of 16), for populations that fit.  Gene
+// values are below 64, so the squared distance is |a|^2 + |b|^2 - 2 a.b with
+// a.b by v_dot4_u32_u8, four genes per instruction, exact in 32 bits; a
+// chromosome's nearest centroid minimises |c|^2 - 2 a.c.  Assignment: one
+// thread per chromosome, its row read 16 bytes at a time and matched against
+// every centroid (the centroid reads are the same address in every lane, an
+// LDS broadcast).  Update: the members of each cluster listed by a counting
+// sort, then one thread per (cluster, 4-gene word) sums its members' genes in
+// two packed 16-bit accumulators (flushed every 256 members).
+constexpr int kKmPad = 16;
+
+__device__ __forceinline__ int km_lkp(int LK) { return (LK + kKmPad - 1) / kKmPad * kKmPad; }
+
+struct KmLds {
+  uint8_t *pop, *cent;
+  int32_t *a2, *lab, *dmin, *mem, *b2, *cnt, *off, *pos, *flag;
+  uint64_t *red;
+};
+
+__device__ __forceinline__ KmLds km_lds_layout(unsigned char *smem, int N, int LKP, int C) {
+  KmLds m;
+  m.pop = smem;
+  m.cent = smem + (size_t)N * LKP;
+  int32_t *w = reinterpret_cast<int32_t *>(m.cent + (size_t)C * LKP);
+  m.a2 = w;
+  m.lab = w + N;
+  m.dmin = w + 2 * N;
+  m.mem = w + 3 * N;
+  m.b2 = w + 4 * N;
+  m.cnt = m.b2 + kIslandMaxC;
+  m.off = m.cnt + kIslandMaxC;
+  m.pos = m.off + kIslandMaxC;
+  m.flag = m.pos + kIslandMaxC;
+  m.red = reinterpret_cast<uint64_t *>(m.flag + 4);  // 16-byte aligned: N, LKP multiples of 4
+  return m;
+}
+
+int kmeans_lds_resident(int N, int LK, int C) {
+  const int LKP = (LK + kKmPad - 1) / kKmPad * kKmPad;
+  return N * LKP + C * LKP + 16 * N + 4 * (4 * kIslandMaxC + 4) +
+         8 * (kKmThreads / kWave);
+}
+
+// Lanes per chromosome in the distance passes: the largest power of two (at
+// most 16) with N x S within the workgroup, so small populations still fill
+// it; a chromosome's S lanes are consecutive and each takes every S-th
+// 16-byte chunk of the row.
+__device__ __forceinline__ int km_split(int N, int T) {
+  int S = 1;
+  while (S < 16 && N * (2 * S) <= T) S <<= 1;
+  return S;
+}
+
+// a.b over chunks q, q + S, .. of a row and a centroid (LDS)
+__device__ __forceinline__ uint32_t km_dot_part(const uint8_t *x, const uint8_t *y, int LKP, int q,
+                                                int S) {
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  uint32_t d = 0u;
+  for (int o = 16 * q; o < LKP; o += 16 * S) {
+    const u4 a = *reinterpret_cast<const u4 *>(x + o), b = *reinterpret_cast<const u4 *>(y + o);
+    d = __builtin_amdgcn_udot4(a.x, b.x, d, false);
+    d = __builtin_amdgcn_udot4(a.y, b.y, d, false);
+    d = __builtin_amdgcn_udot4(a.z, b.z, d, false);
+    d = __builtin_amdgcn_udot4(a.w, b.w, d, false);
+  }
+  return d;
+}
+
+// sum over the S consecutive lanes of a group (every lane of the wave calls it)
+__device__ __forceinline__ uint32_t km_group_sum(uint32_t v, int S) {
+  for (int m = 1; m < S; m <<= 1) v += (uint32_t)__shfl_xor((int)v, m);
+  return v;
+}
+
+__global__ __launch_bounds__(kKmThreads) void k_pop_kmeans_lds(PopKmArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+  const int N = a.N, LK = a.LK, C = a.C, LKP = km_lkp(LK), W = LKP / 4;
+  const KmLds m = km_lds_layout(smem, N, LKP, C);
+  const int tid = threadIdx.x, T = blockDim.x;
+  const int wave = tid / kWave, lane = tid % kWave, nw = T / kWave;
+  // the population into LDS, zero genes past LK: rows of whole 16-byte
+  // chunks as one flat copy (four chunks in flight per thread), others one
+  // wave per row
+  if (LK == LKP && (reinterpret_cast<uintptr_t>(a.pop) & 15) == 0) {
+    const gptr<const u4> src = gp(reinterpret_cast<const u4 *>(a.pop));
+    u4 *dst = reinterpret_cast<u4 *>(m.pop);
+    const int total = N * (LKP / 16);
+#pragma unroll 4
+    for (int i = tid; i < total; i += T) dst[i] = src[i];
+  } else {
+    for (int n = wave; n < N; n += nw) {
+      uint32_t *dst = reinterpret_cast<uint32_t *>(m.pop + (size_t)n * LKP);
+      if ((LK & 3) == 0) {
+        const gptr<const uint32_t> src =
+            gp(reinterpret_cast<const uint32_t *>(a.pop + (size_t)n * LK));
+        for (int w = lane; w < W; w += kWave) dst[w] = w < (LK >> 2) ? src[w] : 0u;
+      } else {
+        for (int i = lane; i < LKP; i += kWave)
+          m.pop[(size_t)n * LKP + i] = i < LK ? gp(a.pop)[(size_t)n * LK + i] : (uint8_t)0;
+      }
+    }
+  }
+  __syncthreads();
+  const int S = km_split(N, T);
+  // |row|^2 of every chromosome; centroid 0 the best-ranked chromosome
+  uint64_t bk = 0;
+  for (int n = tid; n < N; n += T) {
+    const uint64_t k = full_key(gp(a.fit)[n], (uint32_t)n);
+    bk = k > bk ? k : bk;
+  }
+  for (int b0 = 0; b0 < N * S; b0 += T) {
+    const int n = (b0 + tid) / S, q = (b0 + tid) % S;
+    const uint8_t *row = m.pop + (size_t)min(n, N - 1) * LKP;
+    const uint32_t d = km_group_sum(n < N ? km_dot_part(row, row, LKP, q, S) : 0u, S);
+    if (n < N && q == 0) m.a2[n] = (int32_t)d;
+  }
+  int pick = (int)key_index(block_max_u64(bk, m.red));  // (its barriers publish a2)
+  for (int c = 0; c < C; ++c) {
+    const u4 *src = reinterpret_cast<const u4 *>(m.pop + (size_t)pick * LKP);
+    u4 *dst = reinterpret_cast<u4 *>(m.cent + (size_t)c * LKP);
+    for (int i = tid; i < LKP / 16; i += T) dst[i] = src[i];
+    if (tid == 0) m.b2[c] = m.a2[pick];
+    __syncthreads();
+    if (c + 1 == C) break;
+    // nearest-centroid distance of every chromosome, updated with centroid c;
+    // the next centroid is the farthest (ties to the lowest index)
+    uint64_t fk = 0;
+    const int32_t bc = m.b2[c];
+    for (int b0 = 0; b0 < N * S; b0 += T) {
+      const int n = (b0 + tid) / S, q = (b0 + tid) % S;
+      const uint8_t *row = m.pop + (size_t)min(n, N - 1) * LKP;
+      const uint32_t dot =
+          km_group_sum(n < N ? km_dot_part(row, m.cent + (size_t)c * LKP, LKP, q, S) : 0u, S);
+      if (n < N && q == 0) {
+        const int32_t d = m.a2[n] + bc - 2 * (int32_t)dot;
+        const int32_t dm = c == 0 ? d : min(m.dmin[n], d);
+        m.dmin[n] = dm;
+        const uint64_t k = ((uint64_t)(uint32_t)dm << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)n);
+        fk = k > fk ? k : fk;
+      }
+    }
+    pick = (int)key_index(block_max_u64(fk, m.red));
+  }
+  for (int n = tid; n < N; n += T) m.lab[n] = -1;
+  int it = 0;
+  for (; it < a.max_iters; ++it) {
+    if (tid == 0) m.flag[0] = 0;
+    __syncthreads();
+    // assignment: the centroid minimising |c|^2 - 2 a.c, ties to the lowest
+    for (int b0 = 0; b0 < N * S; b0 += T) {
+      const int n = (b0 + tid) / S, q = (b0 + tid) % S;
+      uint32_t acc[kIslandMaxC];
+#pragma unroll
+      for (int c = 0; c < kIslandMaxC; ++c) acc[c] = 0u;
+      const uint8_t *row = m.pop + (size_t)n * LKP;
+      for (int o = 16 * q; n < N && o < LKP; o += 16 * S) {
+        const u4 r = *reinterpret_cast<const u4 *>(row + o);
+#pragma unroll
+        for (int c = 0; c < kIslandMaxC; ++c) {
+          if (c < C) {
+            const u4 q = *reinterpret_cast<const u4 *>(m.cent + (size_t)c * LKP + o);
+            uint32_t d = __builtin_amdgcn_udot4(r.x, q.x, acc[c], false);
+            d = __builtin_amdgcn_udot4(r.y, q.y, d, false);
+            d = __builtin_amdgcn_udot4(r.z, q.z, d, false);
+            acc[c] = __builtin_amdgcn_udot4(r.w, q.w, d, false);
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kIslandMaxC; ++c)
+        if (c < C) acc[c] = km_group_sum(acc[c], S);
+      if (n >= N || q != 0) continue;
+      int best = 0;
+      int32_t bd = m.b2[0] - 2 * (int32_t)acc[0];
+#pragma unroll
+      for (int c = 1; c < kIslandMaxC; ++c) {
+        if (c < C) {
+          const int32_t d = m.b2[c] - 2 * (int32_t)acc[c];
+          if (d < bd) {
+            bd = d;
+            best = c;
+          }
+        }
+      }
+      if (m.lab[n] != best) {
+        m.lab[n] = best;
+        m.flag[0] = 1;
+      }
+    }
+    if (tid < kIslandMaxC) m.cnt[tid] = 0;
+    __syncthreads();
+    if (m.flag[0] == 0) break;
+    // members of each cluster, listed by a counting sort (the order inside
+    // a cluster is free: the sums are exact)
+    for (int n = tid; n < N; n += T) atomicAdd(&m.cnt[m.lab[n]], 1);
+    __syncthreads();
+    if (tid == 0) {
+      int o = 0;
+      for (int c = 0; c < C; ++c) {
+        m.off[c] = o;
+        m.pos[c] = o;
+        o += m.cnt[c];
+      }
+    }
+    if (tid < C && m.cnt[tid] > 0) m.b2[tid] = 0;  // recomputed below with the new centroid
+    __syncthreads();
+    for (int n = tid; n < N; n += T) m.mem[atomicAdd(&m.pos[m.lab[n]], 1)] = n;
+    __syncthreads();
+    // new centroids, one thread per (cluster, word of 4 genes)
+    for (int t = tid; t < C * W; t += T) {
+      const int c = t / W, w = t - c * W;
+      const int cnt = m.cnt[c];
+      if (cnt == 0) continue;
+      uint32_t s[4] = {0u, 0u, 0u, 0u};
+      const int32_t *mem = m.mem + m.off[c];
+      const uint32_t *pw = reinterpret_cast<const uint32_t *>(m.pop) + w;
+      for (int k0 = 0; k0 < cnt; k0 += 256) {
+        uint32_t ev = 0u, od = 0u;  // genes 0, 2 and 1, 3 of the word in 16-bit halves
+        const int k1 = min(cnt, k0 + 256);
+        int k = k0;
+        for (; k + 8 <= k1; k += 8) {  // eight members' loads in flight
+          uint32_t x[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) x[j] = pw[(size_t)mem[k + j] * W];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            ev += x[j] & 0x00FF00FFu;
+            od += (x[j] >> 8) & 0x00FF00FFu;
+          }
+        }
+        for (; k < k1; ++k) {
+          const uint32_t x = pw[(size_t)mem[k] * W];
+          ev += x & 0x00FF00FFu;
+          od += (x >> 8) & 0x00FF00FFu;
+        }
+        s[0] += ev & 0xFFFFu;
+        s[1] += od & 0xFFFFu;
+        s[2] += ev >> 16;
+        s[3] += od >> 16;
+      }
+      uint32_t word = 0u;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        word |= ((2u * s[b] + (uint32_t)cnt) / (2u * (uint32_t)cnt)) << (8 * b);
+      reinterpret_cast<uint32_t *>(m.cent + (size_t)c * LKP)[w] = word;
+      atomicAdd(&m.b2[c], (int32_t)__builtin_amdgcn_udot4(word, word, 0u, false));
+    }
+    __syncthreads();
+  }
+  for (int n = tid; n < N; n += T) gp(a.labels)[n] = m.lab[n];
+  if (tid == 0 && a.iters) *gp(a.iters) = it;
+}
+
 // ---------------------------------------------------------------- island step
 //
 // Two kernels: k_island_plan (one workgroup per island) finds the island's
@@ -184,9 +440,10 @@ struct IslandArgs {
   const float *fin;
   uint8_t *pout;
   const int32_t *labels;
-  int N, E, L, K;
+  int N, E, L, K, C;
   uint32_t gen;
   DevGa ga;
+  float *trace_g;  // null, or the trace entry that receives the best of fin
 };
 
 // What position s of the next generation is built from: rows [0, cutg / K)
@@ -204,6 +461,23 @@ __global__ __launch_bounds__(kIslandThreads) void k_island_plan(IslandArgs a, Is
   __shared__ int32_t sCount[kIslandThreads / kWave + 1];
   const int c = blockIdx.x, tid = threadIdx.x, T = blockDim.x;
   const int N = a.N, L = a.L, K = a.K, LK = L * K;
+  if (c == a.C) {
+    // the extra workgroup: a position whose label names no island is a copy
+    // of itself (no island writes its record), and the best of the input
+    // population goes to the trace
+    uint64_t bk = 0;
+    for (int n = tid; n < N; n += T) {
+      const int lab = gp(a.labels)[n];
+      if (lab < 0 || lab >= a.C) rec[n] = IslandRec{n | (n << 16), LK, 0, 1};
+      const uint64_t k = full_key(gp(a.fin)[n], (uint32_t)n);
+      bk = k > bk ? k : bk;
+    }
+    if (a.trace_g) {
+      bk = block_max_u64(bk, sRed);
+      if (tid == 0) *gp(a.trace_g) = gp(a.fin)[key_index(bk)];
+    }
+    return;
+  }
   // members of island c, in increasing position: a block prefix over the labels
   int base = 0;
   for (int n0 = 0; n0 < N; n0 += T) {
@@ -272,16 +546,12 @@ __global__ __launch_bounds__(kIslandThreads) void k_island_plan(IslandArgs a, Is
   }
 }
 
-// Every record a copy of its own position (what a position whose label names
-// no island receives).
-__global__ void k_island_fill(IslandRec *rec, int N, int LK) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i < N) rec[i] = IslandRec{i | (i << 16), LK, 0, 1};
+// Positions per build workgroup for N chromosomes of LK genes: enough
+// workgroups for the population to spread over 128 of them, at most 64
+// positions and two 16 KB buffers of them in LDS.
+int island_chunk(int LK, int N) {
+  return std::max(1, std::min({64, 16384 / LK, (N + 127) / 128}));
 }
-
-// Positions per build workgroup for chromosomes of LK genes (two LK-byte
-// buffers of them in LDS).
-int island_chunk(int LK) { return std::max(1, std::min(64, 16384 / LK)); }
 
 __global__ __launch_bounds__(kIslandThreads) void k_island_build(IslandArgs a,
                                                                  const IslandRec *rec,
@@ -372,27 +642,34 @@ int kmeans_lds(int N, int LK, int C) {
 
 hipError_t launch_pop_kmeans(const uint8_t *pop, const float *fit, int N, int LK, int C,
                              int max_iters, int32_t *labels, int32_t *iters, hipStream_t s) {
+  PopKmArgs a{pop, fit, N, LK, C, max_iters, labels, iters};
+  const int resident = kmeans_lds_resident(N, LK, C);
+  if (resident <= kLdsBytes) {
+    static LdsAttr attr_r;
+    const hipError_t ae =
+        allow_lds_once(attr_r, reinterpret_cast<const void *>(k_pop_kmeans_lds), kLdsBytes);
+    hipLaunchKernelGGL(k_pop_kmeans_lds, dim3(1), dim3(kKmThreads), resident, s, a);
+    return launch_status(ae);
+  }
   static LdsAttr attr;
   const int lds = kmeans_lds(N, LK, C);
   const hipError_t ae = allow_lds_once(attr, reinterpret_cast<const void *>(k_pop_kmeans), kLdsBytes);
-  PopKmArgs a{pop, fit, N, LK, C, max_iters, labels, iters};
   hipLaunchKernelGGL(k_pop_kmeans, dim3(1), dim3(kKmThreads), lds, s, a);
   return launch_status(ae);
 }
 
-// One generation of every island: records (each a copy of its position),
-// plan (one workgroup per island), build (positions in chunks).  rec: N
-// records of device scratch.
+// One generation of every island: plan (one workgroup per island, and one
+// for the positions of no island and, with trace_g, the trace entry), then
+// build (positions in chunks).  rec: N records of device scratch.
 hipError_t launch_island_step(const DevProblem &p, const DevGa &ga, int C, uint32_t gen,
                               const int32_t *labels, const uint8_t *pin, const float *fin,
-                              uint8_t *pout, IslandRec *rec, hipStream_t s) {
-  IslandArgs a{pin, fin, pout, labels, ga.N, ga.E, p.L, p.K, gen, ga};
-  hipLaunchKernelGGL(k_island_fill, dim3((ga.N + 255) / 256), dim3(256), 0, s, rec, ga.N,
-                     p.L * p.K);
-  hipLaunchKernelGGL(k_island_plan, dim3(C), dim3(kIslandThreads), 0, s, a, rec);
+                              uint8_t *pout, IslandRec *rec, hipStream_t s,
+                              float *trace_g = nullptr) {
+  IslandArgs a{pin, fin, pout, labels, ga.N, ga.E, p.L, p.K, C, gen, ga, trace_g};
+  hipLaunchKernelGGL(k_island_plan, dim3(C + 1), dim3(kIslandThreads), 0, s, a, rec);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int LK = p.L * p.K, cpw = island_chunk(LK);
+  const int LK = p.L * p.K, cpw = island_chunk(LK, ga.N);
   const int cb = (cpw * LK + 15) / 16 * 16;
   const size_t lds = 2 * (size_t)cb + 3 * sizeof(int32_t) * cpw;
   hipLaunchKernelGGL(k_island_build, dim3((ga.N + cpw - 1) / cpw), dim3(kIslandThreads), lds, s,
@@ -506,14 +783,13 @@ pa_status pa_island_solve(pa_instance *in, const pa_ga_params *g, int32_t cluste
   if (e == hipSuccess) e = launch_fitness(in->p, pop[0], N, fit[0], fs, in->ctx->info, s);
   for (int gen = 0; gen < G && e == hipSuccess; ++gen) {
     const int a = gen & 1, b = 1 - a;
-    e = launch_trace_best(fit[a], N, trace + gen, s);
     // Alg. 2: apply K-means (at 0, then every recluster_every generations)
-    if (e == hipSuccess && clusters > 1 &&
+    if (clusters > 1 &&
         (gen == 0 || (recluster_every > 0 && gen % recluster_every == 0)))
       e = launch_pop_kmeans(pop[a], fit[a], N, LK, clusters, kmeans_iters, lab, nullptr, s);
     if (e == hipSuccess)
       e = launch_island_step(in->p, ga, clusters, (uint32_t)gen, lab, pop[a], fit[a], pop[b], rec,
-                             s);
+                             s, trace + gen);
     if (e == hipSuccess) e = launch_fitness(in->p, pop[b], N, fit[b], fs, in->ctx->info, s);
   }
   const int fin = G & 1;

@@ -20,7 +20,8 @@ def _inst(pa, L, K, seed=1, inst_id=0):
 
 
 @pytest.mark.parametrize("L,K,N,C", [(7, 4, 50, 5), (19, 16, 256, 5), (5, 7, 37, 3),
-                                     (37, 32, 1000, 16), (7, 4, 20, 1), (3, 3, 16, 16)])
+                                     (37, 32, 1000, 16), (7, 4, 20, 1), (3, 3, 16, 16),
+                                     (8, 32, 512, 7)])
 def test_population_kmeans_matches_oracle(oracle_mod, L, K, N, C):
     torch = need_gpu()
     import paper_2511_20511_amd as pa
