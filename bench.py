@@ -291,11 +291,12 @@ def run_single(pa, scenario, torch, name, steps, peaks):
 
 
 def run_fitness(pa, scenario, torch, peaks):
-    """pa_fitness alone on a resident population: evals/s and LDS roofline
-    against the measured peak of the instruction each layout issues."""
+    """pa_fitness alone on a resident population of 65,536 chromosomes (the
+    64 x 1024 a generation of the L=37 batch evaluates): evals/s and LDS
+    roofline against the measured peak of the instruction each layout issues."""
     out = []
     stream = torch.cuda.current_stream()
-    for (L, K, n, instr) in ((37, 32, 16384, "lds_b32"), (19, 16, 65536, "lds_b128")):
+    for (L, K, n, instr) in ((37, 32, 65536, "lds_b32"), (19, 16, 65536, "lds_b128")):
         d = scenario.make_drop(L, K, seed=1, instance_id=0)
         ctx = pa.pa_context_create(0)
         inst = pa.pa_instance_create(ctx, d.beta, d.user_xy, d.bs_xy, T=196)
