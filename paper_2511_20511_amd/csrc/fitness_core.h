@@ -83,6 +83,33 @@ __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int
   }
 }
 
+// The inverse row of lane q = (c, p) of a round (chromosome c = q / K, pilot
+// p = q % K; inv[j] = the user of cell j on pilot p) into sInv + q * LT,
+// straight from the round's chromosome bytes in LDS (row-major [c][j][k]):
+// lane (c, x) reads the pilot s of user x of cell j and sends x to lane
+// (c, s) with ds_permute, so each lane writes only its own row and no
+// workgroup pass or barrier is needed.  K must divide 64 (a chromosome's
+// lanes lie in one wave) and every lane of the wave calls it.  Rows must be
+// permutations: lanes past the round's last chromosome read stale bytes and
+// send inside their own group.  The same inverse rows as build_inverse.
+template <int LT>
+__device__ __forceinline__ void inverse_rows_permute(const uint8_t *stage, int K, uint8_t *sInv) {
+  const int q = (int)threadIdx.x;
+  const int x = q & (K - 1);
+  const int base = (q & 63) - x;
+  const uint8_t *row = stage + (q - x) * LT + x;  // user x of cell 0 of chromosome q / K
+  uint8_t *dst = sInv + q * LT;
+  // all reads, then all permutes, then all writes (interleaved, each write
+  // could alias a later read and the three would wait on each other per cell)
+  int v[LT];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) v[j] = row[j * K];
+#pragma unroll
+  for (int j = 0; j < LT; ++j) v[j] = __builtin_amdgcn_ds_permute((base + (v[j] & (K - 1))) << 2, x);
+#pragma unroll
+  for (int j = 0; j < LT; ++j) dst[j] = (uint8_t)v[j];
+}
+
 // LDS tile layout: cell-major, T[j][lr][p] (asymptotic) or T[j][lr][2][p]
 // (finite-M: the T2 row then the T1 row), lr the BS row inside the tile.  A
 // lane's base register A[j] = byte address of T[j][0][u_j(p)]; the BS row is a

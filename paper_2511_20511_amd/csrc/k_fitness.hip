@@ -87,6 +87,8 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   const int q = threadIdx.x;
   const int rounds = (a.n + CPR - 1) / CPR;
   const int mn = a.objective;
+  // a chromosome's lanes in one wave: inverse rows by lane permutes
+  const bool perm = (64 % K) == 0;
 
   if constexpr (NT > 1) {
     // Tiled table: tiles outermost.  The workgroup's rounds are taken in
@@ -114,11 +116,19 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
           const int r = (int)blockIdx.x + (i0 + g) * (int)gridDim.x;
           const int c0 = r * CPR;
           const int nc = min(CPR, a.n - c0);
+          // (with the permute form, a round of a tile before the last ends
+          // without a barrier: every lane's reads of sStage come before this
+          // round's staging)
+          if (perm && g > 0 && t + 1 < NT) __syncthreads();
           prefetch_store(range(g), pf, sStage);
           if (g + 1 < ng) prefetch_issue(range(g + 1), pf);
           __syncthreads();
-          build_inverse(sStage, nc * LT, LT, K, sInv);
-          __syncthreads();
+          if (perm) {
+            inverse_rows_permute<LT>(sStage, K, sInv);
+          } else {
+            build_inverse(sStage, nc * LT, LT, K, sInv);
+            __syncthreads();
+          }
           const bool active = q / K < nc;
           const uint8_t *ip = sInv + q * LT;
           uint32_t A[LT];
@@ -156,8 +166,14 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
     prefetch_store(range(r), pf, sStage);
     prefetch_issue(range(r + gridDim.x), pf);
     __syncthreads();
-    build_inverse(sStage, nc * LT, LT, K, sInv);
-    __syncthreads();
+    // (reduce_round's closing barrier keeps the next round's staging after
+    // every lane's reads of sStage)
+    if (perm) {
+      inverse_rows_permute<LT>(sStage, K, sInv);
+    } else {
+      build_inverse(sStage, nc * LT, LT, K, sInv);
+      __syncthreads();
+    }
     const bool active = q / K < nc;
     float acc;
     if constexpr (P::kQuad)
