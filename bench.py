@@ -270,7 +270,8 @@ def run_single(pa, scenario, torch, name, steps, peaks):
     if shape["persistent"]:
         stream = torch.cuda.current_stream()
         TP = max(4, 1 << (K - 1).bit_length())
-        kname = f"k_gen_persist<{L},{TP},0,{shape['block']}>"
+        form = "k_gen_wg" if shape["persistent"] == 2 else "k_gen_persist"
+        kname = f"{form}<{L},{TP},0,{shape['block']}>"
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         pa.pa_solve_begin(inst, p)
         e0.record(stream)
