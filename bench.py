@@ -133,6 +133,41 @@ def cpu_baseline(w, sample_gens, procs):
                                     f"same sample each, {wall:.1f} s wall"}}
 
 
+def oracle_full_and_service(scenario, procs, n_requests=16):
+    """The oracle on the two small single instances in full (one core each), and
+    its service time on the first n_requests of the serving mix (G = 50), one
+    single-threaded process per request, `procs` at a time: the distribution,
+    and the cores that the serving rate would need at that mean."""
+    def run(L, K, N, G, E, seed, inst, T):
+        return [sys.executable, os.path.abspath(__file__), "--oracle-sample",
+                ",".join(str(x) for x in (L, K, N, G, E, seed, inst, T))]
+    full = {}
+    for name in ("single_L7_K4", "single_L19_K16"):
+        w = scenario.WORKLOADS[name]
+        o = json.loads(subprocess.run(run(w["L"], w["K"], w["N"], w["gens"], w["E"], w["seed"], 0,
+                                          w["T"]), capture_output=True, text=True,
+                                      check=True).stdout)
+        full[name] = {"solve_s": o["seconds"], "evals": o["evals"],
+                      "evals_per_s": o["evals"] / o["seconds"], "cores": 1}
+    w = scenario.WORKLOADS["serve_mix_2000rps"]
+    sizes = scenario.size_mix(w["pool"], w["seed"])[:n_requests]
+    secs = []
+    for i0 in range(0, len(sizes), procs):
+        ps = [subprocess.Popen(run(L, K, N, w["gens"], w["E"], w["seed"], i0 + j, w["T"]),
+                               stdout=subprocess.PIPE, text=True)
+              for j, (L, K, N) in enumerate(sizes[i0:i0 + procs])]
+        secs += [json.loads(p.communicate()[0])["seconds"] for p in ps]
+    a = sorted(secs)
+    mean = sum(a) / len(a)
+    q = lambda f: a[min(len(a) - 1, int(f * len(a)))]
+    service = {"requests": len(a), "gens": w["gens"], "mean_s": mean, "p50_s": q(0.5),
+               "p90_s": q(0.9), "max_s": a[-1], "rate_per_s": w["rate"],
+               "cores_for_rate": w["rate"] * mean,
+               "sample": (f"the first {len(a)} drops of the serving pool (size mix), one "
+                          f"single-threaded oracle process per request, {procs} at a time")}
+    return full, service
+
+
 # ---- GPU measurements ---------------------------------------------------------
 
 def make_batch(pa, scenario, ctx, w, sizes):
@@ -620,6 +655,12 @@ def main():
         cpu = cpu_baseline(w, args.cpu_sample_gens, procs)
         log(f"oracle: {cpu['value']:.0f} evals/s on one core, "
             f"{cpu['multicore']['value']:.0f} evals/s on {procs}")
+        cpu["full_solves"], cpu["serve_service_time"] = oracle_full_and_service(scenario, procs)
+        sv = cpu["serve_service_time"]
+        log(f"oracle full solves: " + ", ".join(f"{k} {v['solve_s']:.2f} s"
+                                              for k, v in cpu["full_solves"].items())
+            + f"; serving mix service time mean {sv['mean_s']:.2f} s, p90 {sv['p90_s']:.2f} s "
+            f"({sv['cores_for_rate']:.0f} cores for {sv['rate_per_s']:.0f} req/s)")
 
     import numpy as np
     import torch
