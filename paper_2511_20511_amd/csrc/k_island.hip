@@ -188,8 +188,9 @@ __device__ __forceinline__ int km_lkp(int LK) { return (LK + kKmPad - 1) / kKmPa
 
 struct KmLds {
   uint8_t *pop, *cent;
-  int32_t *a2, *lab, *dmin, *mem, *b2, *cnt, *off, *pos, *flag;
-  uint64_t *red;
+  int32_t *a2, *lab, *dmin, *mem, *b2, *cnt, *off, *pos, *flag, *pk;
+  uint64_t *red, *far;
+  uint32_t *part;  // [kKmThreads][4] partial member sums of the update
 };
 
 __device__ __forceinline__ KmLds km_lds_layout(unsigned char *smem, int N, int LKP, int C) {
@@ -202,18 +203,21 @@ __device__ __forceinline__ KmLds km_lds_layout(unsigned char *smem, int N, int L
   m.dmin = w + 2 * N;
   m.mem = w + 3 * N;
   m.b2 = w + 4 * N;
-  m.cnt = m.b2 + kIslandMaxC;
-  m.off = m.cnt + kIslandMaxC;
+  m.cnt = m.b2 + kIslandMaxC;      // two sets, by pass parity
+  m.off = m.cnt + 2 * kIslandMaxC;
   m.pos = m.off + kIslandMaxC;
-  m.flag = m.pos + kIslandMaxC;
-  m.red = reinterpret_cast<uint64_t *>(m.flag + 4);  // 16-byte aligned: N, LKP multiples of 4
+  m.flag = m.pos + kIslandMaxC;    // two, by pass parity (+ 2 unused)
+  m.pk = m.flag + 4;               // the farthest-point picks
+  m.red = reinterpret_cast<uint64_t *>(m.pk + kIslandMaxC);  // 8-byte aligned: N, LKP multiples of 4
+  m.far = m.red + kKmThreads / kWave;                         // three rotating maxima
+  m.part = reinterpret_cast<uint32_t *>(m.far + 4);           // 16-byte aligned
   return m;
 }
 
 int kmeans_lds_resident(int N, int LK, int C) {
   const int LKP = (LK + kKmPad - 1) / kKmPad * kKmPad;
-  return N * LKP + C * LKP + 16 * N + 4 * (4 * kIslandMaxC + 4) +
-         8 * (kKmThreads / kWave);
+  return N * LKP + C * LKP + 16 * N + 4 * (6 * kIslandMaxC + 4) +
+         8 * (kKmThreads / kWave + 4) + 16 * kKmThreads;
 }
 
 // Lanes per chromosome in the distance passes: the largest power of two (at
@@ -245,6 +249,34 @@ __device__ __forceinline__ uint32_t km_dot_part(const uint8_t *x, const uint8_t 
 __device__ __forceinline__ uint32_t km_group_sum(uint32_t v, int S) {
   for (int m = 1; m < S; m <<= 1) v += (uint32_t)__shfl_xor((int)v, m);
   return v;
+}
+
+typedef int km_v4i __attribute__((ext_vector_type(4)));
+
+// The products a.c of the 16 chromosomes of tile t (rows 16 t .. 16 t + 15 of
+// the population in LDS) with 16 centroid rows (column j: row cent + j *
+// cstride, zero for j >= ncent), as an int8 matrix product in steps of 64
+// genes (gene values are below 64, so the int8 operands are exact and the
+// int32 sums too).  Lane l gives row l % 16 and column l % 16 the same 16
+// genes of each step (bytes 16 (l / 16) of it; zeros past the padded row
+// end), so the order of the product's k slots does not matter.  Lane l
+// receives rows 4 (l / 16) + r, column l % 16 in element r.  Every lane of the
+// wave calls it.
+__device__ __forceinline__ km_v4i km_tile_dots(const uint8_t *pop, int N, int LKP, int t,
+                                               const uint8_t *cent, int ncent, int cstride) {
+  const int lane = (int)(threadIdx.x & 63), i = lane & 15, g = lane >> 4;
+  const int n = 16 * t + i;
+  const uint8_t *ra = pop + (size_t)n * LKP;
+  const uint8_t *rb = cent + (size_t)i * cstride;
+  km_v4i d = {0, 0, 0, 0};
+  for (int o = 16 * g; o - 16 * g < LKP; o += 64) {
+    const bool in = o < LKP;
+    const km_v4i zero = {0, 0, 0, 0};
+    const km_v4i x = (in && n < N) ? *reinterpret_cast<const km_v4i *>(ra + o) : zero;
+    const km_v4i y = (in && i < ncent) ? *reinterpret_cast<const km_v4i *>(rb + o) : zero;
+    d = __builtin_amdgcn_mfma_i32_16x16x64_i8(x, y, d, 0, 0, 0);
+  }
+  return d;
 }
 
 __global__ __launch_bounds__(kKmThreads) void k_pop_kmeans_lds(PopKmArgs a) {
@@ -290,109 +322,128 @@ __global__ __launch_bounds__(kKmThreads) void k_pop_kmeans_lds(PopKmArgs a) {
     const uint32_t d = km_group_sum(n < N ? km_dot_part(row, row, LKP, q, S) : 0u, S);
     if (n < N && q == 0) m.a2[n] = (int32_t)d;
   }
+  if (tid < 3) m.far[tid] = 0;  // (published by the barriers of the next reduction)
   int pick = (int)key_index(block_max_u64(bk, m.red));  // (its barriers publish a2)
-  for (int c = 0; c < C; ++c) {
-    const u4 *src = reinterpret_cast<const u4 *>(m.pop + (size_t)pick * LKP);
-    u4 *dst = reinterpret_cast<u4 *>(m.cent + (size_t)c * LKP);
-    for (int i = tid; i < LKP / 16; i += T) dst[i] = src[i];
-    if (tid == 0) m.b2[c] = m.a2[pick];
-    __syncthreads();
-    if (c + 1 == C) break;
-    // nearest-centroid distance of every chromosome, updated with centroid c;
-    // the next centroid is the farthest (ties to the lowest index)
+  // farthest-point start: centroid c is population row pk[c] (compared in
+  // place); each pass updates every chromosome's nearest distance and takes
+  // the farthest through an LDS maximum (three slots in rotation, each reset
+  // a pass before its next use)
+  for (int c = 0; c + 1 < C; ++c) {
+    if (tid == 0) {
+      m.pk[c] = pick;
+      m.far[(c + 1) % 3] = 0;
+    }
+    const uint8_t *cr = m.pop + (size_t)pick * LKP;
+    const int32_t bc = m.a2[pick];
     uint64_t fk = 0;
-    const int32_t bc = m.b2[c];
-    for (int b0 = 0; b0 < N * S; b0 += T) {
-      const int n = (b0 + tid) / S, q = (b0 + tid) % S;
-      const uint8_t *row = m.pop + (size_t)min(n, N - 1) * LKP;
-      const uint32_t dot =
-          km_group_sum(n < N ? km_dot_part(row, m.cent + (size_t)c * LKP, LKP, q, S) : 0u, S);
-      if (n < N && q == 0) {
-        const int32_t d = m.a2[n] + bc - 2 * (int32_t)dot;
-        const int32_t dm = c == 0 ? d : min(m.dmin[n], d);
-        m.dmin[n] = dm;
-        const uint64_t k = ((uint64_t)(uint32_t)dm << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)n);
-        fk = k > fk ? k : fk;
+    for (int t = wave; 16 * t < N; t += nw) {
+      // the picked row in every column; lanes of column 0 take the results
+      const km_v4i dot = km_tile_dots(m.pop, N, LKP, t, cr, 16, 0);
+      if ((lane & 15) == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int n = 16 * t + 4 * (lane >> 4) + r;
+          if (n < N) {
+            const int32_t d = m.a2[n] + bc - 2 * dot[r];
+            const int32_t dm = c == 0 ? d : min(m.dmin[n], d);
+            m.dmin[n] = dm;
+            const uint64_t k =
+                ((uint64_t)(uint32_t)dm << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)n);
+            fk = k > fk ? k : fk;
+          }
+        }
       }
     }
-    pick = (int)key_index(block_max_u64(fk, m.red));
+    fk = wave_max_u64(fk);
+    if (lane == 0) atomicMax(reinterpret_cast<unsigned long long *>(&m.far[c % 3]),
+                             (unsigned long long)fk);
+    __syncthreads();
+    pick = (int)key_index(m.far[c % 3]);
   }
+  if (tid == 0) {
+    m.pk[C - 1] = pick;
+    m.flag[0] = 0;
+  }
+  if (tid < kIslandMaxC) m.cnt[tid] = 0;
+  __syncthreads();
+  // the centroids: copies of the picked rows
+  for (int i = tid; i < C * (LKP / 16); i += T) {
+    const int c = i / (LKP / 16), o = i - c * (LKP / 16);
+    reinterpret_cast<u4 *>(m.cent + (size_t)c * LKP)[o] =
+        reinterpret_cast<const u4 *>(m.pop + (size_t)m.pk[c] * LKP)[o];
+  }
+  if (tid < C) m.b2[tid] = m.a2[m.pk[tid]];
   for (int n = tid; n < N; n += T) m.lab[n] = -1;
+  __syncthreads();
+  const int CW = C * W;
+  const int S2 = max(1, T / CW);  // threads per (cluster, word) in the update
   int it = 0;
   for (; it < a.max_iters; ++it) {
-    if (tid == 0) m.flag[0] = 0;
-    __syncthreads();
-    // assignment: the centroid minimising |c|^2 - 2 a.c, ties to the lowest
-    for (int b0 = 0; b0 < N * S; b0 += T) {
-      const int n = (b0 + tid) / S, q = (b0 + tid) % S;
-      uint32_t acc[kIslandMaxC];
+    // counts and the change flag alternate by pass parity: this pass clears
+    // the other set, last read before the previous pass's final barrier
+    const int par = it & 1;
+    int32_t *cnt = m.cnt + par * kIslandMaxC;
+    if (tid == 0) m.flag[par ^ 1] = 0;
+    if (tid < kIslandMaxC) m.cnt[(par ^ 1) * kIslandMaxC + tid] = 0;
+    // assignment: the centroid minimising |c|^2 - 2 a.c, ties to the lowest,
+    // by tiles of 16 chromosomes x 16 centroids; each cluster's members counted
+    for (int t = wave; 16 * t < N; t += nw) {
+      const km_v4i dot = km_tile_dots(m.pop, N, LKP, t, m.cent, C, LKP);
+      const int j = lane & 15;
+      const int32_t bj = j < C ? m.b2[j] : 0;
 #pragma unroll
-      for (int c = 0; c < kIslandMaxC; ++c) acc[c] = 0u;
-      const uint8_t *row = m.pop + (size_t)n * LKP;
-      for (int o = 16 * q; n < N && o < LKP; o += 16 * S) {
-        const u4 r = *reinterpret_cast<const u4 *>(row + o);
+      for (int r = 0; r < 4; ++r) {
+        // key (|c|^2 - 2 a.c + 2^25) << 5 | c: |c|^2 and a.c stay below 4096 x 63^2
+        // < 2^24, so the offset distance fits 26 bits and the minimum key is the
+        // nearest centroid, the lowest on ties
+        uint32_t key = j < C ? ((uint32_t)(bj - 2 * dot[r] + (1 << 25)) << 5) | (uint32_t)j
+                             : 0xFFFFFFFFu;
 #pragma unroll
-        for (int c = 0; c < kIslandMaxC; ++c) {
-          if (c < C) {
-            const u4 q = *reinterpret_cast<const u4 *>(m.cent + (size_t)c * LKP + o);
-            uint32_t d = __builtin_amdgcn_udot4(r.x, q.x, acc[c], false);
-            d = __builtin_amdgcn_udot4(r.y, q.y, d, false);
-            d = __builtin_amdgcn_udot4(r.z, q.z, d, false);
-            acc[c] = __builtin_amdgcn_udot4(r.w, q.w, d, false);
-          }
+        for (int x = 1; x < 16; x <<= 1) {
+          const uint32_t o = (uint32_t)__shfl_xor((int)key, x);
+          key = o < key ? o : key;
         }
-      }
-#pragma unroll
-      for (int c = 0; c < kIslandMaxC; ++c)
-        if (c < C) acc[c] = km_group_sum(acc[c], S);
-      if (n >= N || q != 0) continue;
-      int best = 0;
-      int32_t bd = m.b2[0] - 2 * (int32_t)acc[0];
-#pragma unroll
-      for (int c = 1; c < kIslandMaxC; ++c) {
-        if (c < C) {
-          const int32_t d = m.b2[c] - 2 * (int32_t)acc[c];
-          if (d < bd) {
-            bd = d;
-            best = c;
+        const int n = 16 * t + 4 * (lane >> 4) + r;
+        if (j == 0 && n < N) {
+          const int best = (int)(key & 31u);
+          if (m.lab[n] != best) {
+            m.lab[n] = best;
+            m.flag[par] = 1;
           }
+          atomicAdd(&cnt[best], 1);
         }
-      }
-      if (m.lab[n] != best) {
-        m.lab[n] = best;
-        m.flag[0] = 1;
       }
     }
-    if (tid < kIslandMaxC) m.cnt[tid] = 0;
     __syncthreads();
-    if (m.flag[0] == 0) break;
+    if (m.flag[par] == 0) break;
     // members of each cluster, listed by a counting sort (the order inside
     // a cluster is free: the sums are exact)
-    for (int n = tid; n < N; n += T) atomicAdd(&m.cnt[m.lab[n]], 1);
-    __syncthreads();
     if (tid == 0) {
       int o = 0;
       for (int c = 0; c < C; ++c) {
         m.off[c] = o;
         m.pos[c] = o;
-        o += m.cnt[c];
+        o += cnt[c];
       }
     }
-    if (tid < C && m.cnt[tid] > 0) m.b2[tid] = 0;  // recomputed below with the new centroid
+    if (tid < C && cnt[tid] > 0) m.b2[tid] = 0;  // recomputed below with the new centroid
     __syncthreads();
     for (int n = tid; n < N; n += T) m.mem[atomicAdd(&m.pos[m.lab[n]], 1)] = n;
     __syncthreads();
-    // new centroids, one thread per (cluster, word of 4 genes)
-    for (int t = tid; t < C * W; t += T) {
-      const int c = t / W, w = t - c * W;
-      const int cnt = m.cnt[c];
-      if (cnt == 0) continue;
-      uint32_t s[4] = {0u, 0u, 0u, 0u};
+    // new centroids: the members' gene sums per (cluster, word of 4 genes),
+    // over S2 slices of the member list when threads are left over
+    for (int t = tid; t < CW * S2; t += T) {
+      const int h = t / CW, cw = t - h * CW;
+      const int c = cw / W, w = cw - c * W;
+      const int n_c = cnt[c];
+      if (n_c == 0) continue;
+      uint32_t sum[4] = {0u, 0u, 0u, 0u};
       const int32_t *mem = m.mem + m.off[c];
       const uint32_t *pw = reinterpret_cast<const uint32_t *>(m.pop) + w;
-      for (int k0 = 0; k0 < cnt; k0 += 256) {
+      const int ka = (int)((int64_t)h * n_c / S2), kb = (int)((int64_t)(h + 1) * n_c / S2);
+      for (int k0 = ka; k0 < kb; k0 += 256) {
         uint32_t ev = 0u, od = 0u;  // genes 0, 2 and 1, 3 of the word in 16-bit halves
-        const int k1 = min(cnt, k0 + 256);
+        const int k1 = min(kb, k0 + 256);
         int k = k0;
         for (; k + 8 <= k1; k += 8) {  // eight members' loads in flight
           uint32_t x[8];
@@ -409,17 +460,39 @@ __global__ __launch_bounds__(kKmThreads) void k_pop_kmeans_lds(PopKmArgs a) {
           ev += x & 0x00FF00FFu;
           od += (x >> 8) & 0x00FF00FFu;
         }
-        s[0] += ev & 0xFFFFu;
-        s[1] += od & 0xFFFFu;
-        s[2] += ev >> 16;
-        s[3] += od >> 16;
+        sum[0] += ev & 0xFFFFu;
+        sum[1] += od & 0xFFFFu;
+        sum[2] += ev >> 16;
+        sum[3] += od >> 16;
+      }
+      if (S2 > 1) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) m.part[4 * t + b] = sum[b];
+        continue;
       }
       uint32_t word = 0u;
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        word |= ((2u * s[b] + (uint32_t)cnt) / (2u * (uint32_t)cnt)) << (8 * b);
+        word |= ((2u * sum[b] + (uint32_t)n_c) / (2u * (uint32_t)n_c)) << (8 * b);
       reinterpret_cast<uint32_t *>(m.cent + (size_t)c * LKP)[w] = word;
       atomicAdd(&m.b2[c], (int32_t)__builtin_amdgcn_udot4(word, word, 0u, false));
+    }
+    if (S2 > 1) {
+      __syncthreads();
+      for (int cw = tid; cw < CW; cw += T) {
+        const int c = cw / W, w = cw - c * W;
+        const int n_c = cnt[c];
+        if (n_c == 0) continue;
+        uint32_t word = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          uint32_t sb = 0u;
+          for (int h = 0; h < S2; ++h) sb += m.part[4 * (h * CW + cw) + b];
+          word |= ((2u * sb + (uint32_t)n_c) / (2u * (uint32_t)n_c)) << (8 * b);
+        }
+        reinterpret_cast<uint32_t *>(m.cent + (size_t)c * LKP)[w] = word;
+        atomicAdd(&m.b2[c], (int32_t)__builtin_amdgcn_udot4(word, word, 0u, false));
+      }
     }
     __syncthreads();
   }
