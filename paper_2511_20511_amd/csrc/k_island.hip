@@ -174,14 +174,14 @@ __global__ __launch_bounds__(kKmThreads) void k_pop_kmeans(PopKmArgs a) {
 
 // The same clustering with the population resident in LDS (rows padded with
 // zero genes to LKP bytes, a multiple of 16), for populations that fit.  Gene
-// values are below 64, so the squared distance is |a|^2 + |b|^2 - 2 a.b with
-// a.b by v_dot4_u32_u8, four genes per instruction, exact in 32 bits; a
-// chromosome's nearest centroid minimises |c|^2 - 2 a.c.  Assignment: one
-// thread per chromosome, its row read 16 bytes at a time and matched against
-// every centroid (the centroid reads are the same address in every lane, an
-// LDS broadcast).  Update: the members of each cluster listed by a counting
-// sort, then one thread per (cluster, 4-gene word) sums its members' genes in
-// two packed 16-bit accumulators (flushed every 256 members).
+// values are below 64, so the squared distance is |a|^2 + |b|^2 - 2 a.b,
+// exact in 32 bits; a chromosome's nearest centroid minimises |c|^2 - 2 a.c.
+// The products a.c of the assignment and of the farthest-point passes are
+// int8 matrix products (km_tile_dots: 16 chromosomes x 16 centroids per
+// tile); |a|^2 uses v_dot4_u32_u8.  Update: the members of each cluster
+// listed by a counting sort, then threads per (cluster, 4-gene word) sum
+// their members' genes in two packed 16-bit accumulators (flushed every 256
+// members).
 constexpr int kKmPad = 16;
 
 __device__ __forceinline__ int km_lkp(int LK) { return (LK + kKmPad - 1) / kKmPad * kKmPad; }
