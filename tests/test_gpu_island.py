@@ -149,3 +149,26 @@ def test_island_step_labels_outside_the_islands():
             for j in range(L):
                 assert any(np.array_equal(got[s, j], pop[m, j]) for m in members)
     inst.close()
+
+
+def test_population_kmeans_unaligned_population(oracle_mod):
+    """A population that does not start on a 16-byte boundary (rows of whole
+    words, staged row by row instead of as one flat copy): the oracle's labels."""
+    torch = need_gpu()
+    import paper_2511_20511_amd as pa
+    L, K, N, C = 19, 16, 256, 5
+    rng = np.random.default_rng(5)
+    d, inst = _inst(pa, L, K)
+    pop = rand_pop(rng, N, L, K)
+    fit = rng.normal(size=N).astype(np.float32)
+    buf = torch.zeros(N * L * K + 16, dtype=torch.uint8, device="cuda")
+    view = buf[4:4 + N * L * K]
+    view.copy_(torch.from_numpy(np.ascontiguousarray(pop).reshape(-1)).cuda())
+    assert view.data_ptr() % 16 == 4
+    lab = torch.zeros(N, dtype=torch.int32, device="cuda")
+    flush("population K-means from an unaligned population")
+    pa.pa_population_kmeans(inst, C, view, to_dev(fit, torch), N, lab, kmeans_iters=20)
+    torch.cuda.synchronize()
+    want, _, _ = oracle_mod.pop_kmeans(pop, fit.astype(np.float64), C, max_iters=20)
+    assert np.array_equal(lab.cpu().numpy(), want)
+    inst.close()
