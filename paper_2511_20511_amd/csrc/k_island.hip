@@ -626,10 +626,10 @@ int island_chunk(int LK, int N) {
   return std::max(1, std::min({64, 16384 / LK, (N + 127) / 128}));
 }
 
-__global__ __launch_bounds__(kIslandThreads) void k_island_build(IslandArgs a,
-                                                                 const IslandRec *rec,
-                                                                 int cpw) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+// The positions [blockIdx.x cpw, ..) built from their records into LDS (smem:
+// child rows | codes | selections) and stored; the rows stay in LDS.
+__device__ __forceinline__ void island_build_chunk(const IslandArgs &a, const IslandRec *rec,
+                                                   int cpw, unsigned char *smem) {
   const int L = a.L, K = a.K, LK = L * K, tid = threadIdx.x, block = blockDim.x;
   const int s0 = blockIdx.x * cpw, nc = min(cpw, a.N - s0);
   const int cb = (cpw * LK + 15) / 16 * 16;
@@ -693,6 +693,69 @@ __global__ __launch_bounds__(kIslandThreads) void k_island_build(IslandArgs a,
   store_bytes(a.pout + (size_t)s0 * LK, child, nc * LK);
 }
 
+// LDS bytes of island_build_chunk for cpw positions of LK genes.
+__host__ __device__ inline int island_build_lds(int cpw, int LK) {
+  const int cb = (cpw * LK + 15) / 16 * 16;
+  return 2 * cb + (3 * (int)sizeof(int32_t) * cpw + 15) / 16 * 16;
+}
+
+__global__ __launch_bounds__(kIslandThreads) void k_island_build(IslandArgs a,
+                                                                 const IslandRec *rec,
+                                                                 int cpw) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  island_build_chunk(a, rec, cpw, smem);
+}
+
+// The fitness of the new population, when the build evaluates it too.
+struct IslandFit {
+  const float *T2;  // the instance's table [L][L][TP] (asymptotic SE)
+  float *fit_out;   // [N]
+  float prelog;
+  int objective;
+};
+
+// Build and fitness in one launch for tables that fit LDS in the quad layout
+// (asymptotic SE, L of 7 or 19): the table is staged while the chunk is
+// built, then the chunk's rows (still in LDS) are inverted and evaluated by
+// the fitness kernels' own quad sums and pilot reduction, so every position
+// gets the bits pa_fitness would give it.  cpw * K <= the workgroup size.
+template <int LT, int TPT>
+__global__ __launch_bounds__(kIslandThreads) void k_island_build_fit(IslandArgs a,
+                                                                     const IslandRec *rec,
+                                                                     int cpw, IslandFit f) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  constexpr int LP = quad_rows<LT>();
+  constexpr int kQuadBytes = LT * TPT * LP * 4;
+  float *sQ = reinterpret_cast<float *>(smem);
+  load_quad(f.T2, LT, TPT, 0, LT, LP, sQ);  // published by the build's barriers
+  unsigned char *b = smem + kQuadBytes;
+  island_build_chunk(a, rec, cpw, b);      // ends with the final rows in LDS, after a barrier
+  const int K = a.K, block = (int)blockDim.x, q = (int)threadIdx.x;
+  const int s0 = blockIdx.x * cpw, nc = min(cpw, a.N - s0);
+  const uint8_t *child = b;
+  uint8_t *sInv = b + island_build_lds(cpw, LT * K);
+  float *sE = reinterpret_cast<float *>(sInv + (block * LT + 15) / 16 * 16);
+  build_inverse(child, nc * LT, LT, K, sInv);
+  __syncthreads();
+  const bool active = q / K < nc;
+  const float acc = lane_sum_quad<LT, TPT>(sInv + q * LT, active, sQ, f.objective);
+  reduce_round(sE, acc, active, nc, K, f.prelog, f.fit_out + s0, f.objective);
+}
+
+template <int LT, int TPT>
+hipError_t launch_build_fit(const IslandArgs &a, const IslandRec *rec, int cpw,
+                            const IslandFit &f, hipStream_t s) {
+  const int LK = LT * a.K;
+  const int lds = LT * TPT * quad_rows<LT>() * 4 + island_build_lds(cpw, LK) +
+                  (kIslandThreads * LT + 15) / 16 * 16 + kIslandThreads * 4;
+  static LdsAttr attr;
+  const hipError_t ae =
+      allow_lds_once(attr, reinterpret_cast<const void *>(k_island_build_fit<LT, TPT>), kLdsBytes);
+  hipLaunchKernelGGL((k_island_build_fit<LT, TPT>), dim3((a.N + cpw - 1) / cpw),
+                     dim3(kIslandThreads), lds, s, a, rec, cpw, f);
+  return launch_status(ae);
+}
+
 __global__ void k_trace_best(const float *fit, int N, float *trace_g) {
   // best fitness of a population into one trace entry (one wave)
   uint64_t b = 0;
@@ -733,20 +796,34 @@ hipError_t launch_pop_kmeans(const uint8_t *pop, const float *fit, int N, int LK
 
 // One generation of every island: plan (one workgroup per island, and one
 // for the positions of no island and, with trace_g, the trace entry), then
-// build (positions in chunks).  rec: N records of device scratch.
+// build (positions in chunks).  rec: N records of device scratch.  With
+// fit_out, the build also evaluates the new population when the table fits
+// the fused form (*evaluated set to true; else the caller evaluates it).
 hipError_t launch_island_step(const DevProblem &p, const DevGa &ga, int C, uint32_t gen,
                               const int32_t *labels, const uint8_t *pin, const float *fin,
                               uint8_t *pout, IslandRec *rec, hipStream_t s,
-                              float *trace_g = nullptr) {
+                              float *trace_g = nullptr, float *fit_out = nullptr,
+                              bool *evaluated = nullptr) {
   IslandArgs a{pin, fin, pout, labels, ga.N, ga.E, p.L, p.K, C, gen, ga, trace_g};
+  if (evaluated) *evaluated = false;
   hipLaunchKernelGGL(k_island_plan, dim3(C + 1), dim3(kIslandThreads), 0, s, a, rec);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int LK = p.L * p.K, cpw = island_chunk(LK, ga.N);
-  const int cb = (cpw * LK + 15) / 16 * 16;
-  const size_t lds = 2 * (size_t)cb + 3 * sizeof(int32_t) * cpw;
-  hipLaunchKernelGGL(k_island_build, dim3((ga.N + cpw - 1) / cpw), dim3(kIslandThreads), lds, s,
-                     a, rec, cpw);
+  if (fit_out && p.se_mode == 0 && (p.L == 7 || p.L == 19) && p.TP <= 32) {
+    const int cpf = std::max(1, std::min(cpw, kIslandThreads / p.K));
+    const IslandFit f{p.T2, fit_out, p.prelog, p.objective};
+    hipError_t ef = hipErrorInvalidValue;
+#define PA_BUILD_FIT(LV, TV) \
+  if (p.L == LV && p.TP == TV) ef = launch_build_fit<LV, TV>(a, rec, cpf, f, s);
+    PA_BUILD_FIT(7, 4) PA_BUILD_FIT(7, 8) PA_BUILD_FIT(7, 16) PA_BUILD_FIT(7, 32)
+    PA_BUILD_FIT(19, 4) PA_BUILD_FIT(19, 8) PA_BUILD_FIT(19, 16) PA_BUILD_FIT(19, 32)
+#undef PA_BUILD_FIT
+    if (ef == hipSuccess && evaluated) *evaluated = true;
+    return ef;
+  }
+  hipLaunchKernelGGL(k_island_build, dim3((ga.N + cpw - 1) / cpw), dim3(kIslandThreads),
+                     island_build_lds(cpw, LK), s, a, rec, cpw);
   return hipGetLastError();
 }
 
@@ -860,10 +937,12 @@ pa_status pa_island_solve(pa_instance *in, const pa_ga_params *g, int32_t cluste
     if (clusters > 1 &&
         (gen == 0 || (recluster_every > 0 && gen % recluster_every == 0)))
       e = launch_pop_kmeans(pop[a], fit[a], N, LK, clusters, kmeans_iters, lab, nullptr, s);
+    bool evaluated = false;
     if (e == hipSuccess)
       e = launch_island_step(in->p, ga, clusters, (uint32_t)gen, lab, pop[a], fit[a], pop[b], rec,
-                             s, trace + gen);
-    if (e == hipSuccess) e = launch_fitness(in->p, pop[b], N, fit[b], fs, in->ctx->info, s);
+                             s, trace + gen, fit[b], &evaluated);
+    if (e == hipSuccess && !evaluated)
+      e = launch_fitness(in->p, pop[b], N, fit[b], fs, in->ctx->info, s);
   }
   const int fin = G & 1;
   if (e == hipSuccess) e = launch_trace_best(fit[fin], N, trace + G, s);
