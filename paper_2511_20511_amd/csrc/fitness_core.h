@@ -787,7 +787,8 @@ __device__ __forceinline__ float add_from_lane_plus(float v, int mn) {
 // global); same tree, same bits.
 template <class Out>
 __device__ __forceinline__ void reduce_round_to(float *sE, float acc, bool active, int nc, int K,
-                                                float prelog, Out &&out, int mn = 0) {
+                                                float prelog, Out &&out, int mn = 0,
+                                                bool sync = true) {
   // pairwise tree over the K pilot sums of a chromosome, one lane per pilot:
   // for s = P/2, P/4, .., 1 (P = K rounded up to a power of two) lane p < s
   // adds lane p + s when p + s < K; the result is in lane 0.
@@ -808,7 +809,9 @@ __device__ __forceinline__ void reduce_round_to(float *sE, float acc, bool activ
     if (K >= 4) v = add_from_lane_plus<2>(v, mn);
     if (K >= 2) v = add_from_lane_plus<1>(v, mn);
     if (active && p == 0 && c < nc) out(c, mn ? v : prelog * v);  // pre-log: objective 0
-    __syncthreads();  // the caller's next LDS writes follow every lane's reads
+    // the caller's next LDS writes follow every lane's reads (sync = false: a
+    // caller whose waves share no LDS between rounds)
+    if (sync) __syncthreads();
     return;
   }
   // otherwise through LDS, one barrier per stride
@@ -827,9 +830,10 @@ __device__ __forceinline__ void reduce_round_to(float *sE, float acc, bool activ
 }
 
 __device__ __forceinline__ void reduce_round(float *sE, float acc, bool active, int nc, int K,
-                                             float prelog, float *fit_out, int mn = 0) {
+                                             float prelog, float *fit_out, int mn = 0,
+                                             bool sync = true) {
   reduce_round_to(sE, acc, active, nc, K, prelog, [fit_out](int c, float v) { gp(fit_out)[c] = v; },
-                  mn);
+                  mn, sync);
 }
 
 }  // namespace pa

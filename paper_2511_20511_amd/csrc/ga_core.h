@@ -128,13 +128,6 @@ __device__ __forceinline__ int rank_of(const float *__restrict__ fin, int N, int
   return r;
 }
 
-// Orders this wave's LDS writes before its later LDS reads by other lanes.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Elitism by one wave: slots 0..E-1 of pout receive the E best chromosomes
 // of pin in rank order (and fout their fitness, when given); trace (when
 // given) receives the best fitness at index gen.  idx: 64 ints of LDS.

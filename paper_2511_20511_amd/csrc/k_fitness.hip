@@ -87,8 +87,24 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   const int q = threadIdx.x;
   const int rounds = (a.n + CPR - 1) / CPR;
   const int mn = a.objective;
-  // a chromosome's lanes in one wave: inverse rows by lane permutes
-  const bool perm = (64 % K) == 0;
+  // a chromosome's lanes in one wave: inverse rows by lane permutes; with a
+  // tiled asymptotic-SE table (K a power of two up to 32, so a pilot
+  // reduction in registers) every round is also staged, inverted, summed and
+  // reduced by each wave on its own chromosomes, with no barrier between
+  // rounds (finite-M tiles keep the workgroup staging: their registers would
+  // spill)
+  const bool perm = (64 % K) == 0 && K <= 32;
+  const bool wave_private = perm && NT > 1 && MODE == 0;
+  const int lane = q & (kWave - 1);
+  // the wave's chromosomes of a round: 64 / K of them, from the wave's
+  // first; their bytes are contiguous in the round's and staged at the same
+  // place (wstage = the wave's first chromosome x LK)
+  const int cw0 = __builtin_amdgcn_readfirstlane((q / kWave) * (kWave / K));  // wave-uniform
+  const int wstage = cw0 * LK;
+  auto wave_range = [&](const ByteRange &rr) {
+    const int nb = min(max(rr.n - wstage, 0), (kWave / K) * LK);
+    return ByteRange{rr.src + wstage, nb};
+  };
 
   if constexpr (NT > 1) {
     // Tiled table: tiles outermost.  The workgroup's rounds are taken in
@@ -111,23 +127,39 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
           const int c0 = ((int)blockIdx.x + (i0 + g) * (int)gridDim.x) * CPR;
           return ByteRange{a.pop + (size_t)c0 * LK, min(CPR, a.n - c0) * LK};
         };
-        prefetch_issue(range(0), pf);
+        if (wave_private) {
+          prefetch_issue(wave_range(range(0)), pf, lane, kWave);
+          __syncthreads();  // the tile
+        } else {
+          prefetch_issue(range(0), pf);
+        }
         for (int g = 0; g < ng; ++g) {
           const int r = (int)blockIdx.x + (i0 + g) * (int)gridDim.x;
           const int c0 = r * CPR;
           const int nc = min(CPR, a.n - c0);
-          // (with the permute form, a round of a tile before the last ends
-          // without a barrier: every lane's reads of sStage come before this
-          // round's staging)
-          if (perm && g > 0 && t + 1 < NT) __syncthreads();
-          prefetch_store(range(g), pf, sStage);
-          if (g + 1 < ng) prefetch_issue(range(g + 1), pf);
-          __syncthreads();
-          if (perm) {
+          if (wave_private) {
+            // each wave stages and inverts its own chromosomes: no barrier
+            // until the next tile (wave_sync keeps the previous round's
+            // permute reads of the wave's stage before these writes)
+            wave_sync();
+            prefetch_store(wave_range(range(g)), pf, sStage + wstage, lane, kWave);
+            if (g + 1 < ng) prefetch_issue(wave_range(range(g + 1)), pf, lane, kWave);
+            wave_sync();
             inverse_rows_permute<LT>(sStage, K, sInv);
           } else {
-            build_inverse(sStage, nc * LT, LT, K, sInv);
+            // (with the permute form, a round of a tile before the last ends
+            // without a barrier: every lane's reads of sStage come before
+            // this round's staging)
+            if (perm && g > 0 && t + 1 < NT) __syncthreads();
+            prefetch_store(range(g), pf, sStage);
+            if (g + 1 < ng) prefetch_issue(range(g + 1), pf);
             __syncthreads();
+            if (perm) {
+              inverse_rows_permute<LT>(sStage, K, sInv);
+            } else {
+              build_inverse(sStage, nc * LT, LT, K, sInv);
+              __syncthreads();
+            }
           }
           const bool active = q / K < nc;
           const uint8_t *ip = sInv + q * LT;
@@ -140,7 +172,8 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
             // round's sInv reads before that round's inverse rows)
             sAcc[g * BLOCK + q] = acc;
           } else {
-            reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn);  // ends with a barrier
+            // (ends with a barrier, except in the wave-private form)
+            reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn, !wave_private);
           }
         }
       }

@@ -185,29 +185,39 @@ __device__ __forceinline__ void copy_bytes(const uint8_t *src, int n, uint8_t *d
   }
 }
 
+// Orders this wave's LDS writes before its later LDS reads by other lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Two-step copy of a global byte range [src, src + n) into LDS, so that the
 // loads of one range can fly while the workgroup computes on the previous
 // one: prefetch_issue loads this thread's aligned words (at most PF per
-// thread: the range must satisfy words() <= PF * blockDim.x) into registers,
-// prefetch_store writes them to dst (LDS, any alignment).
+// thread: the range must satisfy words() <= PF * step) into registers,
+// prefetch_store writes them to dst (LDS, any alignment).  The copy is shared
+// by `step` threads, this one being number t (by default the workgroup; one
+// wave: t = lane, step = 64).
 template <int PF>
-__device__ __forceinline__ void prefetch_issue(const ByteRange &r, uint32_t (&v)[PF]) {
+__device__ __forceinline__ void prefetch_issue(const ByteRange &r, uint32_t (&v)[PF],
+                                               int t = (int)threadIdx.x,
+                                               int step = (int)blockDim.x) {
   const int nw = r.n > 0 ? r.words() : 0;
-  const int step = (int)blockDim.x;
 #pragma unroll
   for (int u = 0; u < PF; ++u) {
-    const int w = (int)threadIdx.x + u * step;
+    const int w = t + u * step;
     v[u] = w < nw ? r.load(w) : 0u;
   }
 }
 template <int PF>
 __device__ __forceinline__ void prefetch_store(const ByteRange &r, const uint32_t (&v)[PF],
-                                               uint8_t *dst) {
+                                               uint8_t *dst, int t = (int)threadIdx.x,
+                                               int step = (int)blockDim.x) {
   const int nw = r.n > 0 ? r.words() : 0;
-  const int step = (int)blockDim.x;
 #pragma unroll
   for (int u = 0; u < PF; ++u) {
-    const int w = (int)threadIdx.x + u * step;
+    const int w = t + u * step;
     if (w < nw) {
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
