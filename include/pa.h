@@ -276,6 +276,28 @@ pa_status pa_solve_batch_state(pa_context *ctx, pa_result *results, int32_t *gen
 pa_status pa_solve_population(pa_context *ctx, pa_instance *inst, int32_t index, uint8_t *pop,
                               float *fit, int32_t *gen, void *stream);
 
+/* Resume of a stepwise solve from a saved state (Alg. 1: the loop state is
+ * the population P of generation gen and its fitness; every random word of a
+ * generation is keyed by (seed, instance_id, generation, slot), so the
+ * generations after gen depend on nothing else).  Loads into inst's solve
+ * plan (built for params as pa_solve_begin builds it, without seeding):
+ *   pop    HOST [N][L][K] bytes, N = params->pop: the population of
+ *          generation gen, as pa_solve_population returns it; every row must
+ *          be a permutation of 0..K-1 (checked: PA_EINVAL otherwise)
+ *   fit    HOST [N] FP32, its fitness as this library computed it, or NULL
+ *          to recompute it on the device (the same bits)
+ *   trace  HOST [gen] FP32, the best fitness of generations 0..gen-1 (as
+ *          pa_solve_state returned them), or NULL: those entries read NaN
+ * The caller keeps ownership of the three buffers; they are copied before
+ * the call returns.  Then pa_solve_next(inst, k) runs generations gen ..
+ * gen + k - 1 (gen + k <= params->gens) and pa_solve_state reports as in an
+ * uninterrupted solve: the same populations, best and trace entries from gen
+ * on, bit for bit.  PA_EINVAL for invalid parameters, gen outside
+ * [0, params->gens] or a NULL pop.  Blocking. */
+pa_status pa_solve_resume(pa_instance *inst, const pa_ga_params *params, int32_t gen,
+                          const uint8_t *pop, const float *fit, const float *trace,
+                          void *stream);
+
 /* The same solve as one launch per step (seeding, fitness, then per
  * generation a pa_ga_step launch and a pa_fitness launch), no fusion and no
  * graph: the plain comparator.  Bit-identical results to pa_solve. */

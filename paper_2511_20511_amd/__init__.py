@@ -26,7 +26,7 @@ __all__ = [
     "pa_kmeans_init", "pa_fitness", "pa_fitness_shaped", "pa_ga_step", "pa_solve",
     "pa_solve_plain", "pa_solve_batch", "pa_solve_begin", "pa_solve_next", "pa_solve_state",
     "pa_solve_shape", "pa_solve_batch_begin", "pa_solve_batch_next", "pa_solve_batch_state",
-    "pa_solve_population", "pa_device_peaks", "pa_solve_noalloc", "pa_population_kmeans", "pa_island_step",
+    "pa_solve_population", "pa_solve_resume", "pa_device_peaks", "pa_solve_noalloc", "pa_population_kmeans", "pa_island_step",
     "pa_island_solve", "release_all", "pa_server_create", "pa_server_submit", "pa_server_poll", "pa_server_stats",
     "pa_server_destroy", "pa_server_cancel", "Server", "pa_exhaustive",
     "pa_instance_kmeans_state", "pa_problem_check", "pa_params_check",
@@ -173,6 +173,7 @@ def lib():
         "pa_solve_batch_next": (st, [vp, i32, vp]),
         "pa_solve_batch_state": (st, [vp, ctypes.POINTER(_Result), ctypes.POINTER(i32), vp]),
         "pa_solve_population": (st, [vp, vp, i32, vp, vp, ctypes.POINTER(i32), vp]),
+        "pa_solve_resume": (st, [vp, ctypes.POINTER(_Params), i32, vp, vp, vp, vp]),
         "pa_server_create": (st, [vp, ctypes.POINTER(_ServerCfg), ctypes.POINTER(vp)]),
         "pa_server_submit": (st, [vp, ctypes.POINTER(_Problem), ctypes.POINTER(_Params),
                                   ctypes.POINTER(ctypes.c_uint64)]),
@@ -432,6 +433,31 @@ def pa_solve_population(ctx: Context | None, inst: Instance | None, index: int, 
                                      pop.ctypes.data, fit.ctypes.data, ctypes.byref(gen),
                                      _stream(stream)))
     return pop, fit, int(gen.value)
+
+
+def pa_solve_resume(inst: Instance, params: GaParams, gen: int, pop, fit=None, trace=None,
+                    stream=None):
+    """Continue a stepwise solve from a saved state: pop [N][L][K] uint8 of
+    generation gen (host), its fitness [N] float32 (None: recomputed) and the
+    trace of generations 0..gen-1 (None: NaN).  pa_solve_next and
+    pa_solve_state follow as in an uninterrupted solve."""
+    inst._gens = params.gens
+    pop = np.ascontiguousarray(pop, dtype=np.uint8)
+    if pop.shape != (params.pop, inst.L, inst.K):
+        raise ValueError(f"population shape {pop.shape} != {(params.pop, inst.L, inst.K)}")
+    if fit is not None:
+        fit = np.ascontiguousarray(fit, dtype=np.float32)
+        if fit.shape != (params.pop,):
+            raise ValueError(f"fitness shape {fit.shape} != {(params.pop,)}")
+    if trace is not None:
+        trace = np.ascontiguousarray(trace, dtype=np.float32)
+        if trace.ndim != 1 or trace.shape[0] < gen:
+            raise ValueError(f"trace holds {trace.shape} entries, needs {gen}")
+    p = params.to_c()
+    _check(lib().pa_solve_resume(inst.h, ctypes.byref(p), int(gen), pop.ctypes.data,
+                                 None if fit is None else fit.ctypes.data,
+                                 None if trace is None else trace.ctypes.data,
+                                 _stream(stream)))
 
 
 def pa_solve_noalloc(inst: Instance, params: GaParams, d_best, d_best_fit, d_trace=None,

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <mutex>
 #include <string>
@@ -984,6 +985,57 @@ pa_status pa_solve_population(pa_context *ctx, pa_instance *in, int32_t index, u
          "copy fitness");
   PTRY(hipStreamSynchronize(s), "hipStreamSynchronize");
   if (gen) *gen = G;
+  return PA_OK;
+}
+
+pa_status pa_solve_resume(pa_instance *in, const pa_ga_params *g, int32_t gen, const uint8_t *pop,
+                          const float *fit, const float *trace, void *stream) {
+  if (!in || !pop) return set_error(PA_EINVAL, "instance or population is NULL");
+  pa_status st = validate_ga(in, g);
+  if (st != PA_OK) return st;
+  if (gen < 0 || gen > g->gens)
+    return set_error(PA_EINVAL, "gen=%d outside [0, gens=%d]", gen, g->gens);
+  const int L = in->p.L, K = in->p.K, N = g->pop;
+  // every row of the restored population must be a permutation of the pilots
+  for (int64_t r = 0; r < (int64_t)N * L; ++r) {
+    uint64_t seen = 0;
+    const uint8_t *row = pop + r * K;
+    for (int k = 0; k < K; ++k) {
+      if (row[k] >= K || ((seen >> row[k]) & 1u))
+        return set_error(PA_EINVAL, "chromosome %lld, cell %lld is not a permutation of 0..%d",
+                         (long long)(r / L), (long long)(r % L), K - 1);
+      seen |= uint64_t(1) << row[k];
+    }
+  }
+  if ((st = use_device(in->ctx)) != PA_OK) return st;
+  if (!plan_matches(in->plan, 1, &in, g)) {
+    free_plan(in->plan);
+    in->plan = nullptr;
+    if ((st = build_plan(in->ctx, 1, &in, g, &in->plan)) != PA_OK) return st;
+  }
+  SolvePlan *pl = in->plan;
+  const GenInst &I = pl->h_inst[0];
+  hipStream_t s = (hipStream_t)stream;
+  const size_t LK = (size_t)L * K;
+  // the generation's buffers of the double-buffered population and fitness
+  PTRY(hipMemcpyAsync(I.pop[gen & 1], pop, LK * N, hipMemcpyHostToDevice, s), "copy population");
+  if (fit) {
+    PTRY(hipMemcpyAsync(I.fit[gen & 1], fit, sizeof(float) * N, hipMemcpyHostToDevice, s),
+         "copy fitness");
+  } else {
+    // recomputed: the same bits as the fitness the solve computed
+    if ((st = pa_fitness(in, I.pop[gen & 1], N, I.fit[gen & 1], stream)) != PA_OK) return st;
+  }
+  // trace entries before gen from the caller (NaN without one); entry gen
+  // and later are written by the generations and the state call to come
+  std::vector<float> tr((size_t)pl->Gmax + 1, std::numeric_limits<float>::quiet_NaN());
+  if (trace) std::memcpy(tr.data(), trace, sizeof(float) * gen);
+  PTRY(hipMemcpyAsync(I.trace, tr.data(), sizeof(float) * tr.size(), hipMemcpyHostToDevice, s),
+       "copy trace");
+  if (pl->persist) PTRY(hipMemsetAsync(pl->d_sync, 0, 2 * sizeof(uint32_t), s), "hipMemsetAsync");
+  PTRY(hipStreamSynchronize(s), "hipStreamSynchronize");
+  pl->cur_gen = gen;
+  pl->done_gen = gen;
   return PA_OK;
 }
 
