@@ -66,8 +66,9 @@ __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int
                                               uint8_t *sInv) {
   for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
     const int c = r / L, j = r - c * L;
-    const int off = r * K, mis = off & 3;
-    const uint32_t *w = reinterpret_cast<const uint32_t *>(src + off - mis);
+    const uint8_t *rp = src + r * K;
+    const int mis = (int)((uintptr_t)rp & 3u);
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(rp - mis);
     const int nw = (mis + K + 3) >> 2;
     uint8_t *dst = sInv + c * K * L + j;
 #pragma unroll 4

@@ -44,7 +44,9 @@ struct ExactPlan {
   static constexpr int kInvBytes = ((BLOCK * LT) + 15) / 16 * 16;
   static constexpr int kEBytes = BLOCK * 4;
   static constexpr int kOwnBytes = LT * TPT * 4;  // own-cell squares (tiled tables)
-  static constexpr int kStageBytes = kInvBytes;     // the round's chromosome bytes
+  // the round's chromosome bytes, stored as whole words from 4 bytes past
+  // each wave's part (wave w's part at w * 64 * LT + 4 (w + 1))
+  static constexpr int kStageBytes = ((BLOCK * LT + 4 * (BLOCK / 64 + 1) + 4) + 15) / 16 * 16;
   static constexpr int kBase = kInvBytes + kEBytes + kOwnBytes + kStageBytes;
   static constexpr int kGroup = 8;
   static constexpr int kAccBytes = TilePlan<LT, TPT, MODE, kBase>::kTiles > 1 ? kGroup * BLOCK * 4 : 0;
@@ -99,8 +101,12 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   // the wave's chromosomes of a round: 64 / K of them, from the wave's
   // first; their bytes are contiguous in the round's and staged at the same
   // place (wstage = the wave's first chromosome x LK)
-  const int cw0 = __builtin_amdgcn_readfirstlane((q / kWave) * (kWave / K));  // wave-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(q / kWave);  // wave-uniform
+  const int cw0 = wave * (kWave / K);
   const int wstage = cw0 * LK;
+  // the wave's staged words start 4 (wave + 1) bytes past its part (room
+  // for the bytes before and after its range in its first and last words)
+  uint8_t *const wdst = sStage + wstage + 4 * (wave + 1);
   auto wave_range = [&](const ByteRange &rr) {
     const int nb = min(max(rr.n - wstage, 0), (kWave / K) * LK);
     return ByteRange{rr.src + wstage, nb};
@@ -142,22 +148,25 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
             // until the next tile (wave_sync keeps the previous round's
             // permute reads of the wave's stage before these writes)
             wave_sync();
-            prefetch_store(wave_range(range(g)), pf, sStage + wstage, lane, kWave);
+            const ByteRange wr = wave_range(range(g));
+            prefetch_store(wr, pf, wdst, lane, kWave);
             if (g + 1 < ng) prefetch_issue(wave_range(range(g + 1)), pf, lane, kWave);
             wave_sync();
-            inverse_rows_permute<LT>(sStage, K, sInv);
+            // (chromosome c of the round at base + c * LK)
+            inverse_rows_permute<LT>(sStage + 4 * (wave + 1) + wr.lead(), K, sInv);
           } else {
             // (with the permute form, a round of a tile before the last ends
             // without a barrier: every lane's reads of sStage come before
             // this round's staging)
             if (perm && g > 0 && t + 1 < NT) __syncthreads();
-            prefetch_store(range(g), pf, sStage);
+            const ByteRange rr = range(g);
+            prefetch_store(rr, pf, sStage + 4);
             if (g + 1 < ng) prefetch_issue(range(g + 1), pf);
             __syncthreads();
             if (perm) {
-              inverse_rows_permute<LT>(sStage, K, sInv);
+              inverse_rows_permute<LT>(sStage + 4 + rr.lead(), K, sInv);
             } else {
-              build_inverse(sStage, nc * LT, LT, K, sInv);
+              build_inverse(sStage + 4 + rr.lead(), nc * LT, LT, K, sInv);
               __syncthreads();
             }
           }
@@ -196,15 +205,16 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   for (int r = blockIdx.x; r < rounds; r += gridDim.x) {
     const int c0 = r * CPR;
     const int nc = min(CPR, a.n - c0);
-    prefetch_store(range(r), pf, sStage);
+    const ByteRange rr = range(r);
+    prefetch_store(rr, pf, sStage + 4);
     prefetch_issue(range(r + gridDim.x), pf);
     __syncthreads();
     // (reduce_round's closing barrier keeps the next round's staging after
     // every lane's reads of sStage)
     if (perm) {
-      inverse_rows_permute<LT>(sStage, K, sInv);
+      inverse_rows_permute<LT>(sStage + 4 + rr.lead(), K, sInv);
     } else {
-      build_inverse(sStage, nc * LT, LT, K, sInv);
+      build_inverse(sStage + 4 + rr.lead(), nc * LT, LT, K, sInv);
       __syncthreads();
     }
     const bool active = q / K < nc;

@@ -151,6 +151,8 @@ struct ByteRange {
   __device__ __forceinline__ int words() const {
     return ((int)((uintptr_t)src & 3u) + n + 3) >> 2;
   }
+  // bytes of the first aligned word before the range
+  __device__ __forceinline__ int lead() const { return (int)((uintptr_t)src & 3u); }
   __device__ __forceinline__ uint32_t load(int w) const {
     return gp(reinterpret_cast<const uint32_t *>((uintptr_t)src & ~(uintptr_t)3))[w];
   }
@@ -196,9 +198,12 @@ __device__ __forceinline__ void wave_sync() {
 // loads of one range can fly while the workgroup computes on the previous
 // one: prefetch_issue loads this thread's aligned words (at most PF per
 // thread: the range must satisfy words() <= PF * step) into registers,
-// prefetch_store writes them to dst (LDS, any alignment).  The copy is shared
-// by `step` threads, this one being number t (by default the workgroup; one
-// wave: t = lane, step = 64).
+// prefetch_store writes them whole to dst (LDS, 4-byte aligned): word w at
+// dst + 4w, so byte i of the range lands at dst + lead() + i, and the first
+// and last words carry up to 3 bytes each from outside the range (dst needs
+// 4 * words() <= n + 6 bytes).  The copy is shared by `step` threads, this
+// one being number t (by default the workgroup; one wave: t = lane,
+// step = 64).
 template <int PF>
 __device__ __forceinline__ void prefetch_issue(const ByteRange &r, uint32_t (&v)[PF],
                                                int t = (int)threadIdx.x,
@@ -218,13 +223,7 @@ __device__ __forceinline__ void prefetch_store(const ByteRange &r, const uint32_
 #pragma unroll
   for (int u = 0; u < PF; ++u) {
     const int w = t + u * step;
-    if (w < nw) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int g = r.pos(w, b);
-        if (g >= 0 && g < r.n) dst[g] = (uint8_t)(v[u] >> (8 * b));
-      }
-    }
+    if (w < nw) reinterpret_cast<uint32_t *>(dst)[w] = v[u];
   }
 }
 

@@ -119,3 +119,31 @@ def test_zero_and_invalid_sizes():
         pa.pa_fitness(inst, d_pop, -1, d_fit)
     with pytest.raises(pa.PaError):
         pa.pa_fitness_shaped(inst, d_pop, 1, d_fit, block=96)
+
+
+# the population's bytes may start anywhere: every staging path (tiled with
+# per-wave staging, tiled and untiled with workgroup staging, permutes or byte
+# scatters for the inverse rows, the runtime-L kernel) must give the same
+# bits from a population 1, 2 or 3 bytes past a 4-byte boundary
+@pytest.mark.parametrize("se_mode", [0, 1])
+@pytest.mark.parametrize("L,K,n", [(37, 32, 97), (37, 23, 45), (19, 16, 301), (7, 5, 259),
+                                   (19, 17, 131), (37, 16, 50), (37, 4, 200), (12, 9, 77)])
+def test_fitness_of_unaligned_population(L, K, n, se_mode):
+    torch = need_gpu()
+    import paper_2511_20511_amd as pa
+    flush(f"fitness unaligned population L={L} K={K} n={n} mode={se_mode}")
+    _, inst, _ = _instance(pa, L, K, se_mode)
+    pop = rand_pop(np.random.default_rng(7 * L + K), n, L, K)
+    nb = n * L * K
+    fits = []
+    for off in range(4):
+        buf = torch.zeros(nb + 8, dtype=torch.uint8, device="cuda")
+        d_pop = buf[off:off + nb].view(n, L, K)
+        d_pop.copy_(torch.from_numpy(pop))
+        assert d_pop.data_ptr() % 4 == off % 4
+        d_fit = torch.empty(n, dtype=torch.float32, device="cuda")
+        pa.pa_fitness(inst, d_pop, n, d_fit)
+        torch.cuda.synchronize()
+        fits.append(d_fit.cpu().numpy().view(np.uint32))
+    for f in fits[1:]:
+        assert np.array_equal(f, fits[0])
