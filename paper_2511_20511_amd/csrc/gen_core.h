@@ -88,6 +88,30 @@ __device__ __forceinline__ GenTask load_task(const GenTask *tasks, int t) {
   return GenTask{p[0], p[1], p[2], p[3]};
 }
 
+// A finished child row of K bytes (K % 16 == 0, n16 = K / 16) from LDS
+// (rowb) to the output population (gdst) as whole 16-byte words, and its
+// inverse entries: dst[t * L] = the position of pilot t in the row.  Both
+// rows are 16-byte aligned (LDS rows and population rows of a multiple of 16
+// bytes).
+__device__ __forceinline__ void store_row_inverse16(const uint8_t *rowb, uint8_t *gdst,
+                                                    uint8_t *dst, int n16, int K, int L) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 *row = reinterpret_cast<const u32x4 *>(rowb);
+  gptr<u32x4> gw = gp(reinterpret_cast<u32x4 *>(gdst));
+  for (int h = 0; h < n16; ++h) {
+    const u32x4 x4 = row[h];
+    gw[h] = x4;
+    const uint32_t xs[4] = {x4.x, x4.y, x4.z, x4.w};
+#pragma unroll
+    for (int w = 0; w < 4; ++w)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int t = (int)((xs[w] >> (8 * b)) & 0xFFu);
+        if (t < K) dst[t * L] = (uint8_t)(16 * h + 4 * w + b);
+      }
+  }
+}
+
 // The children's rows straight from their parents (K % 4 == 0, K <= 32;
 // parents and cut in sSel as build_children_block leaves them), one thread
 // per row (c, j), the loads of two rows in flight per thread: the crossover
@@ -123,8 +147,12 @@ __device__ __forceinline__ void rows_from_parents(const uint8_t *__restrict__ pi
         for (int w = 0; w < 8; ++w)
           if (w < nw) row[w] = v[h][w];
         if (mutate) apply_swaps(sChild + q * K, sCode + q * K, q * K, K);
-        gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)q * K));
         uint8_t *dst = sInv + c * K * L + j;
+        if ((K & 15) == 0) {
+          store_row_inverse16(sChild + q * K, pout + (size_t)q * K, dst, K >> 4, K, L);
+          continue;
+        }
+        gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)q * K));
         for (int w = 0; w < nw; ++w) {
           const uint32_t x = row[w];
           gw[w] = x;
@@ -598,9 +626,13 @@ __device__ __forceinline__ void rows_finish(const GenInst &I, const GenTask &tas
         apply_swaps(rowb, sCode + q * K, q * K, K);
       }
     }
+    uint8_t *dst = sInv + c * K * L + j;
+    if (K == 32) {
+      store_row_inverse16(rowb, pout + (size_t)q * K, dst, 2, K, L);
+      continue;
+    }
     const uint32_t *row = reinterpret_cast<const uint32_t *>(rowb);
     gptr<uint32_t> gw = gp(reinterpret_cast<uint32_t *>(pout + (size_t)q * K));
-    uint8_t *dst = sInv + c * K * L + j;
     for (int w = 0; w < nw; ++w) {
       const uint32_t x = row[w];
       gw[w] = x;
