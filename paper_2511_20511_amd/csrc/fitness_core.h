@@ -63,14 +63,15 @@ __device__ __forceinline__ float se_finite(float b2, float I, float S, float a, 
 // aligned 32-bit words; pilots >= K (invalid input) are skipped so the write
 // stays inside the chromosome.
 __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int L, int K,
-                                              uint8_t *sInv) {
+                                              uint8_t *sInv, int stride = 0) {
+  const int ST = stride > 0 ? stride : L;  // inverse row stride (bytes)
   for (int r = threadIdx.x; r < nrows; r += blockDim.x) {
     const int c = r / L, j = r - c * L;
     const uint8_t *rp = src + r * K;
     const int mis = (int)((uintptr_t)rp & 3u);
     const uint32_t *w = reinterpret_cast<const uint32_t *>(rp - mis);
     const int nw = (mis + K + 3) >> 2;
-    uint8_t *dst = sInv + c * K * L + j;
+    uint8_t *dst = sInv + c * K * ST + j;
 #pragma unroll 4
     for (int i = 0; i < nw; ++i) {
       const uint32_t v = w[i];
@@ -78,7 +79,7 @@ __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int
       for (int b = 0; b < 4; ++b) {
         const int k = 4 * i + b - mis;
         const int s = (int)((v >> (8 * b)) & 0xFFu);
-        if (k >= 0 && k < K && s < K) dst[s * L] = (uint8_t)k;
+        if (k >= 0 && k < K && s < K) dst[s * ST] = (uint8_t)k;
       }
     }
   }
@@ -93,13 +94,13 @@ __device__ __forceinline__ void build_inverse(const uint8_t *src, int nrows, int
 // lanes lie in one wave) and every lane of the wave calls it.  Rows must be
 // permutations: lanes past the round's last chromosome read stale bytes and
 // send inside their own group.  The same inverse rows as build_inverse.
-template <int LT>
+template <int LT, int ST = LT>
 __device__ __forceinline__ void inverse_rows_permute(const uint8_t *stage, int K, uint8_t *sInv) {
   const int q = (int)threadIdx.x;
   const int x = q & (K - 1);
   const int base = (q & 63) - x;
   const uint8_t *row = stage + (q - x) * LT + x;  // user x of cell 0 of chromosome q / K
-  uint8_t *dst = sInv + q * LT;
+  uint8_t *dst = sInv + q * ST;
   // all reads, then all permutes, then all writes (interleaved, each write
   // could alias a later read and the three would wait on each other per cell)
   int v[LT];
@@ -107,8 +108,45 @@ __device__ __forceinline__ void inverse_rows_permute(const uint8_t *stage, int K
   for (int j = 0; j < LT; ++j) v[j] = row[j * K];
 #pragma unroll
   for (int j = 0; j < LT; ++j) v[j] = __builtin_amdgcn_ds_permute((base + (v[j] & (K - 1))) << 2, x);
+  if constexpr (ST % 4 == 0) {
+    // a row stride of whole words: the row as 32-bit stores
 #pragma unroll
-  for (int j = 0; j < LT; ++j) dst[j] = (uint8_t)v[j];
+    for (int i = 0; i < ST / 4; ++i) {
+      uint32_t w = 0u;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (4 * i + b < LT) w |= ((uint32_t)v[4 * i + b] & 0xFFu) << (8 * b);
+      reinterpret_cast<uint32_t *>(dst)[i] = w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < LT; ++j) dst[j] = (uint8_t)v[j];
+  }
+}
+
+// Row stride of the population-fitness kernels' inverse rows: L rounded up to
+// whole 32-bit words, so that a lane writes and reads its row by words.
+template <int LT>
+constexpr int inv_stride() {
+  return (LT + 3) & ~3;
+}
+
+// The LT bytes of a lane's inverse row into A: 32-bit reads when the rows'
+// stride ST is a whole number of words (ip then 4-byte aligned), else bytes.
+template <int LT, int ST>
+__device__ __forceinline__ void read_inv_row(const uint8_t *ip, uint32_t (&A)[LT]) {
+  if constexpr (ST % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < (LT + 3) / 4; ++i) {
+      const uint32_t w = reinterpret_cast<const uint32_t *>(ip)[i];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (4 * i + b < LT) A[4 * i + b] = (w >> (8 * b)) & 0xFFu;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < LT; ++j) A[j] = ip[j];
+  }
 }
 
 // LDS tile layout: cell-major, T[j][lr][p] (asymptotic) or T[j][lr][2][p]
@@ -225,7 +263,7 @@ struct TilePlan {
 // Sum over all BS rows of the SE terms of lane (c, p) in the canonical order;
 // `ip` = inv[c][p][0..L).  With more than one tile the tiles are (re)loaded
 // here, so every thread of the workgroup must call this (inactive lanes too).
-template <int LT, int TPT, int MODE, int TR, int NT>
+template <int LT, int TPT, int MODE, int TR, int NT, int ST = LT>
 __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, float *sT,
                                                 const float *__restrict__ T2,
                                                 const float *__restrict__ T1,
@@ -236,8 +274,7 @@ __device__ __forceinline__ float lane_sum_exact(const uint8_t *ip, bool active, 
   // ip lies inside the inverse-row region for inactive lanes too: every lane
   // loads (no per-element branch, all loads in flight at once), then masks
   uint32_t A[LT];
-#pragma unroll
-  for (int j = 0; j < LT; ++j) A[j] = ip[j];
+  read_inv_row<LT, ST>(ip, A);
 #pragma unroll
   for (int j = 0; j < LT; ++j) {
     const uint32_t v = active ? A[j] : 0u;
@@ -331,7 +368,7 @@ __device__ __forceinline__ void load_quad(const float *__restrict__ T2, int L, i
 // BS rows, one 16-byte gather per cell feeds the four rows' interference
 // sums, each over j != l in increasing j; the SE terms are added in
 // increasing l.  Same arithmetic, same order, same bits as lane_sum_exact.
-template <int LT, int TPT>
+template <int LT, int TPT, int ST = LT>
 __device__ __forceinline__ float lane_sum_quad(const uint8_t *ip, bool active, const float *sQ,
                                                int mn = 0) {
   constexpr int LP = quad_rows<LT>();
@@ -339,8 +376,7 @@ __device__ __forceinline__ float lane_sum_quad(const uint8_t *ip, bool active, c
   typedef float f4 __attribute__((ext_vector_type(4)));
   const char *lds = reinterpret_cast<const char *>(sQ);
   uint32_t A[LT];
-#pragma unroll
-  for (int j = 0; j < LT; ++j) A[j] = ip[j];  // in bounds for inactive lanes too
+  read_inv_row<LT, ST>(ip, A);  // in bounds for inactive lanes too
 #pragma unroll
   for (int j = 0; j < LT; ++j) {
     const uint32_t v = active ? A[j] : 0u;
@@ -489,13 +525,12 @@ __device__ __forceinline__ float lane_sum_split_quad(const uint8_t *sInv, int ql
 // at j == l gives the same bits as skipping it.
 
 // A lane's base offsets into a tile of TR BS rows (cell-major).
-template <int LT, int TPT, int MODE, int TR>
+template <int LT, int TPT, int MODE, int TR, int ST = LT>
 __device__ __forceinline__ void tiled_offsets(const uint8_t *ip, bool active, uint32_t (&A)[LT]) {
   constexpr int ROWB = TPT * 4 * (MODE == 1 ? 2 : 1);
   constexpr int CELLB = TR * ROWB;
   // ip lies inside the inverse-row region for inactive lanes too
-#pragma unroll
-  for (int j = 0; j < LT; ++j) A[j] = ip[j];
+  read_inv_row<LT, ST>(ip, A);
 #pragma unroll
   for (int j = 0; j < LT; ++j) {
     const uint32_t v = active ? A[j] : 0u;

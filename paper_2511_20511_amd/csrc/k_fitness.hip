@@ -41,7 +41,8 @@ struct FitArgs {
 // staged that way (kQuad).
 template <int LT, int TPT, int MODE, int BLOCK>
 struct ExactPlan {
-  static constexpr int kInvBytes = ((BLOCK * LT) + 15) / 16 * 16;
+  // inverse rows at a stride of whole words (inv_stride)
+  static constexpr int kInvBytes = ((BLOCK * inv_stride<LT>()) + 15) / 16 * 16;
   static constexpr int kEBytes = BLOCK * 4;
   static constexpr int kOwnBytes = LT * TPT * 4;  // own-cell squares (tiled tables)
   // the round's chromosome bytes, stored as whole words from 4 bytes past
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   const int LK = LT * K;
   const int CPR = BLOCK / K;
   const int q = threadIdx.x;
+  constexpr int ST = inv_stride<LT>();  // inverse row stride (whole words)
   const int rounds = (a.n + CPR - 1) / CPR;
   const int mn = a.objective;
   // a chromosome's lanes in one wave: inverse rows by lane permutes; with a
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
             if (g + 1 < ng) prefetch_issue(wave_range(range(g + 1)), pf, lane, kWave);
             wave_sync();
             // (chromosome c of the round at base + c * LK)
-            inverse_rows_permute<LT>(sStage + 4 * (wave + 1) + wr.lead(), K, sInv);
+            inverse_rows_permute<LT, ST>(sStage + 4 * (wave + 1) + wr.lead(), K, sInv);
           } else {
             // (with the permute form, a round of a tile before the last ends
             // without a barrier: every lane's reads of sStage come before
@@ -164,16 +166,16 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
             if (g + 1 < ng) prefetch_issue(range(g + 1), pf);
             __syncthreads();
             if (perm) {
-              inverse_rows_permute<LT>(sStage + 4 + rr.lead(), K, sInv);
+              inverse_rows_permute<LT, ST>(sStage + 4 + rr.lead(), K, sInv);
             } else {
-              build_inverse(sStage + 4 + rr.lead(), nc * LT, LT, K, sInv);
+              build_inverse(sStage + 4 + rr.lead(), nc * LT, LT, K, sInv, ST);
               __syncthreads();
             }
           }
           const bool active = q / K < nc;
-          const uint8_t *ip = sInv + q * LT;
+          const uint8_t *ip = sInv + q * ST;
           uint32_t A[LT];
-          tiled_offsets<LT, TPT, MODE, TR>(ip, active, A);
+          tiled_offsets<LT, TPT, MODE, TR, ST>(ip, active, A);
           float acc = t == 0 ? obj_init(mn) : sAcc[g * BLOCK + q];
           acc = tiled_rows<LT, TPT, MODE, TR>(A, ip, active, sT, sOwn, a.lconst, t, acc, mn);
           if (t + 1 < NT) {
@@ -212,18 +214,18 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
     // (reduce_round's closing barrier keeps the next round's staging after
     // every lane's reads of sStage)
     if (perm) {
-      inverse_rows_permute<LT>(sStage + 4 + rr.lead(), K, sInv);
+      inverse_rows_permute<LT, ST>(sStage + 4 + rr.lead(), K, sInv);
     } else {
-      build_inverse(sStage + 4 + rr.lead(), nc * LT, LT, K, sInv);
+      build_inverse(sStage + 4 + rr.lead(), nc * LT, LT, K, sInv, ST);
       __syncthreads();
     }
     const bool active = q / K < nc;
     float acc;
     if constexpr (P::kQuad)
-      acc = lane_sum_quad<LT, TPT>(sInv + q * LT, active, sT, mn);
+      acc = lane_sum_quad<LT, TPT, ST>(sInv + q * ST, active, sT, mn);
     else
-      acc = lane_sum_exact<LT, TPT, MODE, TR, 1>(sInv + q * LT, active, sT, a.T2, a.T1, a.lconst,
-                                                 mn);
+      acc = lane_sum_exact<LT, TPT, MODE, TR, 1, ST>(sInv + q * ST, active, sT, a.T2, a.T1,
+                                                     a.lconst, mn);
     reduce_round(sE, acc, active, nc, K, a.prelog, a.fit + c0, mn);
   }
 }
