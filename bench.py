@@ -642,7 +642,7 @@ def main():
         oracle_sample(*v)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(each instance runs on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

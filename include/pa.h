@@ -58,7 +58,7 @@ enum {
   PA_EAGAIN = -4,      /* not finished yet (server poll) or queue full */
   PA_ECANCELED = -5,   /* request cancelled */
   PA_EINTERNAL = -6,   /* library bug: please report */
-  PA_EUNSUPPORTED = -7 /* valid request this build cannot serve */
+  PA_EUNSUPPORTED = -7 /* valid request the library cannot serve (e.g. not a gfx950 device) */
 };
 
 /* Fitness modes.
