@@ -17,22 +17,29 @@ namespace pa {
 struct GenArgs {
   const GenInst *insts;
   const GenTask *tasks;
+  const int32_t *bounds;  // null: runs of equal task counts (see task_range)
   int ntasks;
   int gen;             // -1: fitness of the initial populations
   const int32_t *gens; // non-null: a task's generation is gens[task.inst] (gen ignored)
 };
 
 // The range of tasks of this workgroup in a launch of `ntasks` tasks: the
-// tasks are cut into gridDim.x contiguous runs whose lengths differ by at most
-// one, and the runs are dealt so that the workgroups of one XCD take
-// neighbouring runs.  Workgroup b is dispatched to XCD b % 8, so the
-// workgroups of an XCD share the instances (tables, populations) of a
-// contiguous 1/8 of the task list, and its L2 serves them.
+// tasks are cut into gridDim.x contiguous runs, [bounds[r], bounds[r + 1])
+// when bounds is given (cut by the host by task cost), else runs whose
+// lengths differ by at most one, and the runs are dealt so that the
+// workgroups of one XCD take neighbouring runs.  Workgroup b is dispatched to
+// XCD b % 8, so the workgroups of an XCD share the instances (tables,
+// populations) of a contiguous 1/8 of the task list, and its L2 serves them.
 constexpr int kXcds = 8;
-__device__ __forceinline__ void task_range(int ntasks, int &t0, int &t1) {
+__device__ __forceinline__ void task_range(int ntasks, const int32_t *bounds, int &t0, int &t1) {
   const int b = blockIdx.x, G = gridDim.x;
   const int x = b % kXcds, r = b / kXcds, per = G / kXcds, rem = G % kXcds;
   const int run = x * per + min(x, rem) + r;  // a bijection of [0, G)
+  if (bounds) {
+    t0 = __builtin_amdgcn_readfirstlane(gp(bounds)[run]);
+    t1 = __builtin_amdgcn_readfirstlane(gp(bounds)[run + 1]);
+    return;
+  }
   t0 = (int)(((int64_t)run * ntasks) / G);
   t1 = (int)(((int64_t)(run + 1) * ntasks) / G);
 }
@@ -741,7 +748,7 @@ template <int LT, int TPT, int MODE, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_gen_exact(GenArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   int t0, t1;
-  task_range(a.ntasks, t0, t1);
+  task_range(a.ntasks, a.bounds, t0, t1);
   if constexpr (GenPlan<LT, TPT, MODE, BLOCK>::kTiles > 1) {
     if (a.gen >= 0 || a.gens) {
       gen_tasks_tiled<LT, TPT, MODE, BLOCK>(a.insts, a.tasks, t0, t1, a.gen, smem, a.gens);
@@ -907,7 +914,7 @@ __global__ __launch_bounds__(1024) void k_gen_generic(GenArgs a, GenGenericPlan 
   int32_t *sIdx = reinterpret_cast<int32_t *>(smem + pl.idx_off);
   int32_t *sSel = reinterpret_cast<int32_t *>(smem + pl.sel_off);
   int t0, t1;
-  task_range(a.ntasks, t0, t1);
+  task_range(a.ntasks, a.bounds, t0, t1);
   int loaded = -1;
   for (int t = t0; t < t1; ++t) {
     const GenTask task = load_task(a.tasks, t);
@@ -945,6 +952,7 @@ inline GenArgs gen_args(const GenInst *insts, const GenClass &c, int gen) {
   a.gens = c.gens;
   a.tasks = (gen < 0 && !c.gens) ? c.eval_tasks : c.tasks;
   a.ntasks = (gen < 0 && !c.gens) ? c.neval : c.ntasks;
+  a.bounds = (gen < 0 && !c.gens) ? nullptr : c.bounds;
   return a;
 }
 

@@ -150,6 +150,10 @@ struct GenClass {
   // non-null: the launch runs `tasks` with each instance at its own
   // generation gens[inst] (device; -1 = the initial fitness, eval tasks)
   const int32_t *gens = nullptr;
+  // non-null (device, grid + 1 entries): the generation launches' runs of
+  // `tasks` are [bounds[r], bounds[r + 1]) (cut by task cost) instead of
+  // runs of equal task counts; the initial-fitness launch ignores it
+  const int32_t *bounds = nullptr;
   // non-null: launch nothing, store how many workgroups of the class's
   // kernel (at `block`) one CU holds at once
   int *query_per_cu = nullptr;

@@ -32,6 +32,7 @@ struct PlanClass {
   GenClass c;
   int cpt_div = 1;  // children per task = ceil(block / K / cpt_div)
   GenTask *d_tasks = nullptr, *d_evals = nullptr;
+  int32_t *d_bounds = nullptr;  // runs of the generation launches (grid + 1)
   double work = 0.0;     // table gathers of one generation (for the class order)
   bool tuned = false;    // the shape came from timing candidates (not the cache)
 };
@@ -128,6 +129,56 @@ struct Shape {
   int block, cpt_div;
 };
 
+// Runs of a generation launch's task list for `grid` workgroups, cut by task
+// cost: a child task costs about the same whatever its number of children
+// (every lane of the workgroup runs the gathers), an elite task about a
+// quarter of one.  The runs are contiguous (a workgroup keeps an instance's
+// table across its tasks) and their largest cost is the smallest any cut
+// into `grid` contiguous runs achieves (binary search on the cap, greedy
+// filling); bounds[r] .. bounds[r + 1] is run r, unused runs are empty.
+std::vector<int32_t> cost_runs(const std::vector<GenTask> &tasks, int grid) {
+  const int n = (int)tasks.size();
+  std::vector<int64_t> w(n);
+  int64_t total = 0, wmax = 0;
+  for (int i = 0; i < n; ++i) {
+    w[i] = tasks[i].kind == kTaskElite ? 1 : 4;
+    total += w[i];
+    wmax = std::max(wmax, w[i]);
+  }
+  auto runs_for = [&](int64_t cap) {
+    int runs = 1;
+    int64_t cur = 0;
+    for (int i = 0; i < n; ++i) {
+      if (cur + w[i] > cap) {
+        ++runs;
+        cur = 0;
+      }
+      cur += w[i];
+    }
+    return runs;
+  };
+  int64_t lo = std::max(wmax, (total + grid - 1) / std::max(grid, 1)), hi = std::max(total, lo);
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) / 2;
+    if (runs_for(mid) <= grid)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  std::vector<int32_t> bounds(grid + 1, n);
+  bounds[0] = 0;
+  int r = 0;
+  int64_t cur = 0;
+  for (int i = 0; i < n; ++i) {
+    if (cur + w[i] > lo) {
+      bounds[++r] = i;
+      cur = 0;
+    }
+    cur += w[i];
+  }
+  return bounds;
+}
+
 // Task lists (device) of a class of instances for a launch shape.
 pa_status make_class(SolvePlan *pl, const ClassKey &key, const std::vector<int> &members,
                      const std::vector<GenInst> &hi, const Shape &sh, int cus, PlanClass *out) {
@@ -152,6 +203,7 @@ pa_status make_class(SolvePlan *pl, const ClassKey &key, const std::vector<int> 
                      key.L, key.TP, pc.c.block);
   pc.c.grid = std::min((int)tasks.size(), cus * per_cu);
   pc.c.ntasks = (int)tasks.size();
+  const std::vector<int32_t> bounds = cost_runs(tasks, pc.c.grid);
   pc.c.neval = (int)evals.size();
   PTRY(alloc(pl, &pc.d_tasks, tasks.size()), "hipMalloc(tasks)");
   PTRY(alloc(pl, &pc.d_evals, evals.size()), "hipMalloc(tasks)");
@@ -159,8 +211,13 @@ pa_status make_class(SolvePlan *pl, const ClassKey &key, const std::vector<int> 
        "upload");
   PTRY(hipMemcpy(pc.d_evals, evals.data(), sizeof(GenTask) * evals.size(), hipMemcpyHostToDevice),
        "upload");
+  PTRY(alloc(pl, &pc.d_bounds, bounds.size()), "hipMalloc(tasks)");
+  PTRY(hipMemcpy(pc.d_bounds, bounds.data(), sizeof(int32_t) * bounds.size(),
+                 hipMemcpyHostToDevice),
+       "upload");
   pc.c.tasks = pc.d_tasks;
   pc.c.eval_tasks = pc.d_evals;
+  pc.c.bounds = pc.d_bounds;
   *out = pc;
   return PA_OK;
 }
