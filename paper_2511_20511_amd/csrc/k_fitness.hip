@@ -146,6 +146,13 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
           const int c0 = r * CPR;
           const int nc = min(CPR, a.n - c0);
           if (wave_private) {
+            // the two waves of a SIMD (w, w + 4) take turns at the higher
+            // issue priority, round by round, so that neither falls behind
+            // before the next tile's barrier
+            if (((g + (wave >> 2)) & 1) != 0)
+              __builtin_amdgcn_s_setprio(1);
+            else
+              __builtin_amdgcn_s_setprio(0);
             // each wave stages and inverts its own chromosomes: no barrier
             // until the next tile (wave_sync keeps the previous round's
             // permute reads of the wave's stage before these writes)
@@ -189,6 +196,7 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     return;
   } else if constexpr (P::kQuad) {
     load_quad(a.T2, LT, TPT, 0, LT, quad_rows<LT>(), sT);
