@@ -92,13 +92,13 @@ __global__ __launch_bounds__(BLOCK) void k_fitness_exact(FitArgs a) {
   const int rounds = (a.n + CPR - 1) / CPR;
   const int mn = a.objective;
   // a chromosome's lanes in one wave: inverse rows by lane permutes; with a
-  // tiled asymptotic-SE table (K a power of two up to 32, so a pilot
-  // reduction in registers) every round is also staged, inverted, summed and
-  // reduced by each wave on its own chromosomes, with no barrier between
-  // rounds (finite-M tiles keep the workgroup staging: their registers would
-  // spill)
+  // tiled table (K a power of two up to 32, so a pilot reduction in
+  // registers) every round is also staged, inverted, summed and reduced by
+  // each wave on its own chromosomes, with no barrier between rounds (not for
+  // finite-M tables of at most 16 pilots: that kernel's registers would spill
+  // more and it runs slower)
   const bool perm = (64 % K) == 0 && K <= 32;
-  const bool wave_private = perm && NT > 1 && MODE == 0;
+  const bool wave_private = perm && NT > 1 && (MODE == 0 || TPT >= 32);
   const int lane = q & (kWave - 1);
   // the wave's chromosomes of a round: 64 / K of them, from the wave's
   // first; their bytes are contiguous in the round's and staged at the same
